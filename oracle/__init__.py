@@ -1,0 +1,39 @@
+"""Plain FP64 CPU oracle of randomized Tucker-sketched GMRES.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import, call or
+execute this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+library (``paper_2608_11091_amd``); the two meet only through the seeded
+inputs of ``workloads``.
+
+Every routine is written for a reader checking it against the paper by eye:
+NumPy/SciPy library primitives (tensordot, Householder QR, SVD, symmetric
+eigenvalues) serve as steps, with no blocking, fusion or reordering beyond
+what the paper's definitions state.
+
+Parity status (see the pins in ``tests/test_oracle_*.py``):
+  * apply / sketch / inner / exact norm: pinned (dense brute force, closed
+    forms, the superdiagonal identity of Sec. 3.3).
+  * RoundSum: pinned (exactness at eps=0, energy identity, error bound,
+    truncated HOSVD of the dense sum).
+  * sGMRES cycle / restarted solve: pinned (textbook GMRES reduction,
+    residual identity, exact solutions).
+  * adjoint gradients: pinned (dense gradient, finite differences).
+  * effective-rank heuristic's choice of sketch size beyond the exactness
+    test: parity unpinned (a heuristic; only its invariance and monotone
+    behaviour are tested).
+"""
+from .tucker import (Tucker, to_dense, ttm, multi_ttm, unfold, apply_op, transpose_terms,
+                     dense_operator, sketch_krp, sketch_kron, inner, exact_norm,
+                     block_dense, scale)
+from .roundsum import RoundParams, roundsum, effective_sketch_size, st_hosvd
+from .sgmres import SGMRESParams, sgmres_cycle, solve, sketched_lstsq
+from .adjoint import adjoint_gradients, loss_and_cotangent
+
+__all__ = [
+    "Tucker", "to_dense", "ttm", "multi_ttm", "unfold", "apply_op", "transpose_terms",
+    "dense_operator", "sketch_krp", "sketch_kron", "inner", "exact_norm", "block_dense",
+    "scale", "RoundParams", "roundsum", "effective_sketch_size", "st_hosvd",
+    "SGMRESParams", "sgmres_cycle", "solve", "sketched_lstsq", "adjoint_gradients",
+    "loss_and_cotangent",
+]

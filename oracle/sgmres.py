@@ -1,0 +1,180 @@
+"""RHOSVD-Tucker sGMRES (Alg. 2) with restarts and FP64 iterative
+refinement -- oracle, test infrastructure only.
+
+Alg. 2 step by step (one cycle, ``sgmres_cycle``):
+  beta = ||B||, V_1 = B / beta, b_s = S^T vec(B), beta_s = ||b_s||;
+  for k = 1..N_max:
+      W = RoundSum(L(V_k))                     (operator apply + recompression)
+      M = [M, S^T vec(W)]                      (sketch of the rounded W)
+      W = RoundSum(W - sum_{window} <V_j, W> V_j)   (truncated Arnoldi, window k_trunc)
+      y_k = argmin ||M y - b_s||, res_k = ||M y_k - b_s|| / beta_s
+      if ||W|| ~ 0: stop (breakdown);  V_{k+1} = W / ||W||
+      if res_k < eta * tol: stop
+  X = RoundSum(sum_i y_i V_i)
+
+Readings (listed in the design doc): classical one-pass orthogonalisation (all
+coefficients from the same W, one RoundSum of 1 + window blocks); y_k is
+computed before the breakdown test; breakdown when ||W|| <= 1e-14 ||RoundSum(L V_k)||
+or the new diagonal of the least-squares R factor is <= 1e-14 ||M||_F; the
+least squares use a Householder QR without pivoting.
+
+Restarts (``solve``): the paper discourages restarting for memory reasons but
+does not define it; the solver here wraps cycles in FP64 iterative refinement:
+x_0 = 0, r_0 = B; per cycle solve L d = r_c to relative tolerance
+``tol ||B|| / ||r_c||`` (floored), ``x <- RoundSum(x + d)``, then the exact FP64
+residual ``||B - L(x)|| / ||B||`` (QR of concatenated factors) decides;
+``r_{c+1} = RoundSum(B - L(x))``.  Two cycles in a row that reduce the true
+residual by less than 10% stop the solve with a rank-floor status.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import List, Optional
+
+import numpy as np
+from scipy.linalg import solve_triangular
+
+from .roundsum import RoundParams, roundsum
+from .tucker import Tucker, apply_op, exact_norm, inner, scale, sketch_krp
+
+OK, NOT_CONVERGED, BREAKDOWN, RANK_FLOOR = 0, 1, 2, 3
+
+
+@dataclasses.dataclass
+class SGMRESParams:
+    tol: float = 1e-8
+    eta: float = 0.4
+    maxiter: int = 60
+    k_trunc: int = 2
+    max_restarts: int = 50
+    cap: int = 48
+    p: int = 5
+    eps_trunc: Optional[float] = None      # inner RoundSums (default 1e-2 * inner tol)
+    eps_min: float = 1e-13                 # floor of the inner truncation tolerance
+    tol_inner_floor: float = 1e-13         # floor of the per-cycle relative tolerance
+    eps_outer: Optional[float] = None      # x-update / residual RoundSums (default 1e-2 * tol)
+    breakdown_tol: float = 1e-14
+    replay: Optional[dict] = None          # rank replay: {"s": [...], "ranks": [...]} consumed in order
+
+
+def sketched_lstsq(M: np.ndarray, b: np.ndarray):
+    """Sketched least squares (Eq. for y_k of sGMRES): Householder QR of M,
+    triangular solve, residual ``||M y - b||``.  Returns (y, res, |R_kk|)."""
+    Q, R = np.linalg.qr(M, mode="reduced")
+    y = solve_triangular(R, Q.T @ b)
+    res = float(np.linalg.norm(M @ y - b))
+    return y, res, float(abs(R[-1, -1]))
+
+
+class _Replay:
+    def __init__(self, rep):
+        self.rep = rep
+        self.i = 0
+
+    def next(self, prm: RoundParams) -> RoundParams:
+        if self.rep is None:
+            return prm
+        s = self.rep["s"][self.i]
+        r = self.rep["ranks"][self.i]
+        self.i += 1
+        return dataclasses.replace(prm, force_s=s, force_ranks=r)
+
+
+def sgmres_cycle(terms, B: Tucker, S, Omega, prm: SGMRESParams, tol: Optional[float] = None,
+                 transpose: bool = False, log: Optional[list] = None, replay=None):
+    """One cycle of Alg. 2 on ``L(X) = B``; returns (X, info)."""
+    tol = prm.tol if tol is None else tol
+    eps = prm.eps_trunc if prm.eps_trunc is not None else max(1e-2 * tol, prm.eps_min)
+    rp = RoundParams(eps=eps, cap=prm.cap, p=prm.p)
+    rep = replay if replay is not None else _Replay(prm.replay)
+    beta = exact_norm([(1.0, B)])
+    V = [scale(B, 1.0 / beta)]
+    b_s = sketch_krp([(1.0, B)], S)
+    beta_s = float(np.linalg.norm(b_s))
+    cols: List[np.ndarray] = []
+    hist = []
+    status = NOT_CONVERGED
+    y = np.zeros(0)
+    k = 0
+    for k in range(1, prm.maxiter + 1):
+        LV = apply_op(terms, V[-1], transpose=transpose)
+        W, i1 = roundsum(LV, Omega, rep.next(rp))
+        cols.append(sketch_krp([(1.0, W)], S))
+        window = V[max(0, k - prm.k_trunc):k]
+        h = [inner(Vj, W) for Vj in window]
+        W2, i2 = roundsum([(1.0, W)] + [(-hj, Vj) for hj, Vj in zip(h, window)], Omega, rep.next(rp))
+        omega = float(np.linalg.norm(W2.core.ravel()))
+        wnorm = float(np.linalg.norm(W.core.ravel()))
+        M = np.stack(cols, axis=1)
+        y, res, rkk = sketched_lstsq(M, b_s)
+        rel = res / beta_s
+        hist.append(rel)
+        if log is not None:
+            log.append(dict(k=k, s1=i1["s"], r1=i1["ranks"], s2=i2["s"], r2=i2["ranks"], h=h,
+                            omega=omega, res=rel))
+        if omega <= prm.breakdown_tol * wnorm or rkk <= prm.breakdown_tol * np.linalg.norm(M):
+            status = BREAKDOWN
+            break
+        V.append(scale(W2, 1.0 / omega))
+        if rel < prm.eta * tol:
+            status = OK
+            break
+    X, i3 = roundsum([(float(y[i]), V[i]) for i in range(len(y))], Omega, rep.next(rp))
+    if log is not None:
+        log.append(dict(final=True, s=i3["s"], r=i3["ranks"]))
+    return X, dict(status=status, iters=k, hist=hist, beta=beta, beta_s=beta_s)
+
+
+def _residual_blocks(terms, B: Tucker, X: Tucker, transpose=False):
+    """Block sum of ``B - L(X)``."""
+    return [(1.0, B)] + [(-c, T) for c, T in apply_op(terms, X, transpose=transpose)]
+
+
+def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False,
+          x0: Optional[Tucker] = None, log: Optional[list] = None):
+    """Restarted Tucker sGMRES with FP64 iterative refinement."""
+    t0 = time.perf_counter()
+    eps_out = prm.eps_outer if prm.eps_outer is not None else 1e-2 * prm.tol
+    rpo = RoundParams(eps=eps_out, cap=prm.cap, p=prm.p)
+    rep = _Replay(prm.replay)
+    bnorm = exact_norm([(1.0, B)])
+    if x0 is None:
+        x = None
+        r = B
+        rnorm = bnorm
+    else:
+        x = x0
+        Rb = _residual_blocks(terms, B, x, transpose)
+        rnorm = exact_norm(Rb)
+        r, _ = roundsum(Rb, Omega, rep.next(rpo))
+    true_hist, iters, status = [], 0, NOT_CONVERGED
+    cycles = 0
+    for c in range(prm.max_restarts):
+        if rnorm <= prm.tol * bnorm:
+            status = OK
+            break
+        cycles += 1
+        tol_in = min(0.5, max(prm.tol * bnorm / rnorm, prm.tol_inner_floor))
+        d, info = sgmres_cycle(terms, r, S, Omega, prm, tol=tol_in, transpose=transpose,
+                               log=log, replay=rep)
+        iters += info["iters"]
+        if x is None:
+            x = d
+        else:
+            x, _ = roundsum([(1.0, x), (1.0, d)], Omega, rep.next(rpo))
+        Rb = _residual_blocks(terms, B, x, transpose)
+        rnorm = exact_norm(Rb)
+        true_hist.append(rnorm / bnorm)
+        if rnorm <= prm.tol * bnorm:
+            status = OK
+            break
+        if len(true_hist) >= 3 and true_hist[-1] > 0.9 * true_hist[-2] and true_hist[-2] > 0.9 * true_hist[-3]:
+            status = RANK_FLOOR
+            break
+        r, _ = roundsum(Rb, Omega, rep.next(rpo))
+    if x is None:
+        x = Tucker(np.zeros((1,) * B.d), [np.eye(nk, 1) for nk in B.n])
+    return x, dict(status=status, iters=iters, cycles=cycles, true_hist=true_hist,
+                   true_relres=true_hist[-1] if true_hist else rnorm / bnorm,
+                   seconds=time.perf_counter() - t0)

@@ -1,0 +1,158 @@
+"""Pins of the oracle's sGMRES cycle (Alg. 2) and restarted solve: the
+textbook-GMRES special case, the residual identity of the sketched least
+squares, the truncated-Arnoldi relation, and exact solutions (CPU only)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.sgmres import BREAKDOWN, OK, RANK_FLOOR
+from workloads import laplacian_1d, make_config
+
+
+def _coordinate_sketch(n):
+    """S_k such that the Khatri-Rao product S_1 (.) ... (.) S_d is the N x N
+    identity: column l selects the multi-index of l in row-major order."""
+    d = len(n)
+    N = int(np.prod(n))
+    idx = np.unravel_index(np.arange(N), n)
+    return [np.eye(n[k])[:, idx[k]] for k in range(d)]
+
+
+def _textbook_gmres_history(A, b, kmax):
+    """Dense GMRES relative residuals: min over the Krylov space K_k(A, b),
+    with an orthonormal Krylov basis from twice-repeated Gram-Schmidt."""
+    N = len(b)
+    Q = np.zeros((N, kmax + 1))
+    Q[:, 0] = b / np.linalg.norm(b)
+    hist = []
+    for k in range(1, kmax + 1):
+        w = A @ Q[:, k - 1]
+        for _ in range(2):
+            w -= Q[:, :k] @ (Q[:, :k].T @ w)
+        Q[:, k] = w / np.linalg.norm(w)
+        AQ = A @ Q[:, :k]
+        y = np.linalg.lstsq(AQ, b, rcond=None)[0]
+        hist.append(np.linalg.norm(b - AQ @ y) / np.linalg.norm(b))
+    return np.array(hist)
+
+
+def _random_problem(rng, n):
+    terms = [(1.0, [np.diag(np.linspace(1, 3, n[0])) + 0.3 * rng.standard_normal((n[0], n[0])), None, None]),
+             (1.0, [None, np.diag(np.linspace(1, 2, n[1])) + 0.3 * rng.standard_normal((n[1], n[1])), None]),
+             (0.7, [None, None, np.eye(n[2]) + 0.2 * rng.standard_normal((n[2], n[2]))])]
+    B = O.Tucker(rng.standard_normal((2, 1, 2)), [rng.standard_normal((nk, r)) for nk, r in zip(n, (2, 1, 2))])
+    return terms, B
+
+
+def test_textbook_gmres_reduction():
+    # Coordinate-selector sketch with s = N, no truncation, window >= iterations:
+    # the sketched residual history equals dense GMRES.
+    rng = np.random.default_rng(0)
+    n = (4, 3, 4)
+    terms, B = _random_problem(rng, n)
+    S = _coordinate_sketch(n)
+    Om = [rng.standard_normal((nk, max(n) + 5)) for nk in n]
+    kmax = 12
+    prm = O.SGMRESParams(tol=1e-30, maxiter=kmax, k_trunc=kmax, cap=max(n), p=5, eps_trunc=1e-15)
+    X, info = O.sgmres_cycle(terms, B, S, Om, prm)
+    ref = _textbook_gmres_history(O.dense_operator(terms, n), O.to_dense(B).ravel(), kmax)
+    got = np.array(info["hist"])
+    assert len(got) == kmax
+    assert np.allclose(got, ref, rtol=1e-8, atol=1e-13)
+
+
+def test_residual_identity_and_arnoldi_relation():
+    # With exact RoundSums: b_s - M y_k = S^T vec(B - L(sum y_i V_i)), and
+    # L(V_k) = sum_window h_j V_j + omega V_{k+1}.
+    rng = np.random.default_rng(1)
+    n = (5, 4, 5)
+    terms, B = _random_problem(rng, n)
+    S = [rng.standard_normal((nk, 40)) for nk in n]
+    Om = [rng.standard_normal((nk, 10)) for nk in n]
+    prm = O.SGMRESParams(tol=1e-30, maxiter=5, k_trunc=2, cap=5, p=5, eps_trunc=1e-15)
+    log = []
+    X, info = O.sgmres_cycle(terms, B, S, Om, prm, log=log)
+    Ld = O.dense_operator(terms, n)
+    b = O.to_dense(B).ravel()
+    r = b - Ld @ O.to_dense(X).ravel()
+    krp = np.stack([np.kron(np.kron(S[0][:, l], S[1][:, l]), S[2][:, l]) for l in range(40)], axis=1)
+    bs = krp.T @ b
+    res_sk = np.linalg.norm(krp.T @ r) / np.linalg.norm(bs)
+    assert np.isclose(res_sk, info["hist"][-1], rtol=1e-8)
+    # Arnoldi relation, rebuilt densely from the logged coefficients
+    beta = np.linalg.norm(b)
+    V = [b / beta]
+    for entry in log[:-1]:
+        k = entry["k"]
+        w = Ld @ V[-1]
+        window = V[max(0, k - prm.k_trunc):k]
+        w2 = w - sum(h * v for h, v in zip(entry["h"], window))
+        assert np.isclose(np.linalg.norm(w2), entry["omega"], rtol=1e-9)
+        for v in window:
+            assert abs(np.dot(v, w2)) <= 1e-10 * np.linalg.norm(w)   # local orthogonality
+        V.append(w2 / entry["omega"])
+
+
+def _poisson_exact(n, B: O.Tucker):
+    """Exact 3D Poisson solution by DST-I diagonalisation of each mode."""
+    idx = np.arange(1, n + 1)
+    Vm = np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(idx, idx) * np.pi / (n + 1))
+    lam = 4 * (n + 1) ** 2 * np.sin(idx * np.pi / (2 * (n + 1))) ** 2
+    Bh = O.multi_ttm(O.to_dense(B), [Vm.T] * 3)
+    Xh = Bh / (lam[:, None, None] + lam[None, :, None] + lam[None, None, :])
+    return O.multi_ttm(Xh, [Vm] * 3)
+
+
+def test_solve_config1_against_dst_exact_solution():
+    # Poisson n=32, tol 1e-8.  At the configured cap 10 the rank-capped Krylov
+    # basis stalls near 0.2 (see test_rank_floor_is_reported); cap 16 converges.
+    w = make_config(1, cap=16)
+    B = O.Tucker(w.b_core, w.b_factors)
+    prm = O.SGMRESParams(tol=1e-8, maxiter=60, k_trunc=2, cap=w.cap, p=w.p, eta=w.eta)
+    X, info = O.solve(w.terms, B, w.S, w.Omega, prm)
+    assert info["status"] == OK, info
+    assert info["true_relres"] <= 1e-8
+    Xe = _poisson_exact(32, B)
+    Ld_res = np.linalg.norm(O.block_dense([(1.0, B)] + [(-c, T) for c, T in O.apply_op(w.terms, X)]))
+    assert Ld_res / np.linalg.norm(O.to_dense(B)) <= 1e-8
+    # kappa(L) ~ 441 bounds the forward error
+    assert np.linalg.norm(O.to_dense(X) - Xe) <= 441 * 2e-8 * np.linalg.norm(Xe)
+
+
+def test_solve_small_nonsymmetric_against_dense_lu():
+    rng = np.random.default_rng(3)
+    n = (6, 5, 6)
+    terms, B = _random_problem(rng, n)
+    S = [rng.standard_normal((nk, 60)) for nk in n]
+    Om = [rng.standard_normal((nk, 11)) for nk in n]
+    prm = O.SGMRESParams(tol=1e-10, maxiter=30, k_trunc=2, cap=6, p=5)
+    X, info = O.solve(terms, B, S, Om, prm)
+    assert info["status"] == OK and info["true_relres"] <= 1e-10
+    xe = np.linalg.solve(O.dense_operator(terms, n), O.to_dense(B).ravel())
+    assert np.linalg.norm(O.to_dense(X).ravel() - xe) <= 1e-7 * np.linalg.norm(xe)
+
+
+def test_lucky_breakdown_on_eigentensor():
+    n = 12
+    L = laplacian_1d(n)
+    idx = np.arange(1, n + 1)
+    v = [np.sin(idx * j * np.pi / (n + 1))[:, None] for j in (1, 2, 3)]
+    B = O.Tucker(np.ones((1, 1, 1)), v)
+    terms = [(1.0, [L if a == k else None for a in range(3)]) for k in range(3)]
+    rng = np.random.default_rng(4)
+    S = [rng.standard_normal((n, 20)) for _ in range(3)]
+    Om = [rng.standard_normal((n, 9)) for _ in range(3)]
+    prm = O.SGMRESParams(tol=1e-12, maxiter=10, k_trunc=2, cap=4, p=5)
+    X, info = O.sgmres_cycle(terms, B, S, Om, prm)
+    assert info["status"] == BREAKDOWN and info["iters"] == 1
+    lam = sum(4 * (n + 1) ** 2 * np.sin(j * np.pi / (2 * (n + 1))) ** 2 for j in (1, 2, 3))
+    assert np.allclose(O.to_dense(X), O.to_dense(B) / lam, rtol=1e-10, atol=1e-14)
+
+
+def test_rank_floor_is_reported():
+    w = make_config(1)      # configured cap 10
+    B = O.Tucker(w.b_core, w.b_factors)
+    prm = O.SGMRESParams(tol=1e-8, maxiter=60, k_trunc=2, cap=10, p=5, max_restarts=12)
+    X, info = O.solve(w.terms, B, w.S, w.Omega, prm)
+    assert info["status"] == RANK_FLOOR
+    assert 1e-8 < info["true_relres"] < 1.0
