@@ -1,0 +1,186 @@
+/*
+ * tsgmres.h -- C ABI of the MI355X (gfx950) Tucker-sketched GMRES library.
+ *
+ * The library implements the per-iteration Tucker arithmetic of RHOSVD-Tucker
+ * sGMRES (Bucci, Iannacito, Pasha, Smith, "Randomized Tucker-Sketched GMRES",
+ * Alg. 2) for Kronecker-sum tensor equations
+ *     L(X) = sum_j alpha_j  X x_1 A_j^(1) x_2 ... x_d A_j^(d) = B      (Eq. (2))
+ * with B and X in Tucker format (Sec. 2.3), plus restarts with FP64 iterative
+ * refinement, an FP32 form, and the adjoint solve for gradients.
+ *
+ * Conventions shared by every entry point
+ *   - Tensors are DEVICE memory owned by the caller.  A Tucker tensor
+ *     X = G x_1 U_1 ... x_d U_d stores its core row-major over (i_1..i_d)
+ *     (mode d fastest) with capacity strides: entry (i_1..i_d) sits at
+ *     sum_k i_k * prod_{j>k} rcap_j.  Factor U_k is n_k x rcap_k column-major
+ *     (leading dimension n_k).  Only the leading r_k columns / indices are
+ *     read on input; on output everything beyond the ranks is zero.
+ *   - Operator factors A_j^(k) are dense n_k x n_k ROW-major device matrices;
+ *     a NULL pointer stands for the identity.
+ *   - Random sketch matrices are always inputs (the library draws no random
+ *     numbers): S_k is n_k x s and Omega_k is n_k x (rank_cap + oversample),
+ *     both column-major device matrices.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Calls are ordered on
+ *     it; entry points that return host results (ranks, norms, statuses)
+ *     synchronise the stream before returning.
+ *   - The library allocates no device memory of its own: every call takes a
+ *     caller-provided device workspace `ws` of `ws_bytes` bytes.  The matching
+ *     *_workspace function reports the size needed (same arguments, no data).
+ *   - Return value: 0 = success; > 0 = informational solver status;
+ *     < 0 = error (outputs unspecified, message via tk_last_error()).
+ *     Nothing throws across the ABI.  The error message is thread-local.
+ *   - Limits of this build: 2 <= d <= 4, n_k <= 512, rank_cap + oversample
+ *     <= 64, sketch size s <= 256, maxiter <= 64.
+ */
+#ifndef TSGMRES_H_
+#define TSGMRES_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TK_MAX_D 4
+
+/* status codes */
+#define TK_OK 0
+#define TK_NOT_CONVERGED 1   /* x is the last iterate */
+#define TK_BREAKDOWN 2       /* exact solution in the Krylov space (lucky breakdown) */
+#define TK_RANK_FLOOR 3      /* two cycles in a row reduced the true residual by < 10% */
+#define TK_ERR_INVALID_ARG -1
+#define TK_ERR_SHAPE -2
+#define TK_ERR_CAPACITY -3    /* an output rank exceeds the caller's capacity */
+#define TK_ERR_WORKSPACE -4   /* ws_bytes smaller than the *_workspace size */
+#define TK_ERR_HIP -5
+#define TK_ERR_NONFINITE -6
+#define TK_ERR_UNSUPPORTED -7 /* outside the limits listed above */
+
+typedef enum { TK_FORM_FP64 = 0, TK_FORM_FP32 = 1 } tk_form;
+
+/* Tucker tensor (Sec. 2.3, Tucker format equation). */
+typedef struct {
+  int32_t d;
+  int64_t n[TK_MAX_D];
+  int64_t r[TK_MAX_D];    /* ranks: read on inputs, written on outputs */
+  int64_t rcap[TK_MAX_D]; /* capacities (core strides and factor widths) */
+  double* core;           /* device */
+  double* U[TK_MAX_D];    /* device, n_k x rcap_k column-major */
+} tk_tucker;
+
+/* Linear combination sum_b coef[b] * blocks[b] of Tucker tensors. */
+typedef struct {
+  int32_t nblocks;
+  const double* coef;       /* host [nblocks] */
+  const tk_tucker* blocks;  /* host [nblocks] */
+} tk_block_sum;
+
+/* Kronecker-sum operator of Eq. (2): sum_j alpha_j A_j^(1) kron ... kron A_j^(d). */
+typedef struct {
+  int32_t d;
+  int64_t n[TK_MAX_D];
+  int32_t nterms;
+  const double* alpha;          /* host [nterms] */
+  const double* const* A;       /* host [nterms * d] of device row-major n_k x n_k, NULL = identity */
+} tk_kron_op;
+
+/* RoundSum parameters (Sec. 3.1): effective-rank sketch width, range
+ * sketch, QR, core projection, ST-HOSVD truncation to tolerance eps. */
+typedef struct {
+  double eps;               /* relative ST-HOSVD tolerance */
+  double tau;               /* effective-rank energy threshold; <= 0 uses eps */
+  int32_t rank_cap;         /* output rank cap per mode */
+  int32_t oversample;       /* p: sketch width = min(max_k r~_k + p, rank_cap + p) */
+  int32_t force_s;          /* >= 0: use this sketch width (rank replay) */
+  int32_t force_ranks[TK_MAX_D]; /* >= 0: use these output ranks (rank replay) */
+} tk_round_params;
+
+/* Restarted Tucker sGMRES parameters (Alg. 2 inputs plus restarts). */
+typedef struct {
+  int32_t form;             /* tk_form */
+  double tol;               /* target relative residual ||B - L(X)|| / ||B|| */
+  double eta;               /* sketched-residual correction factor (Alg. 2) */
+  int32_t maxiter;          /* iterations per cycle (<= 64) */
+  int32_t max_restarts;     /* cycles */
+  int32_t k_trunc;          /* truncated-Arnoldi window */
+  int32_t rank_cap;
+  int32_t oversample;
+  int64_t s;                /* columns of the sketch factors S_k */
+  double eps_trunc;         /* inner RoundSum tolerance; <= 0: max(1e-2 * inner tol, eps_min) */
+  double eps_min;           /* <= 0: 1e-13 (FP64) / 1e-6 (FP32) */
+  double tol_inner_floor;   /* <= 0: 1e-13 (FP64) / 1e-5 (FP32) */
+  const tk_tucker* x0;      /* optional initial guess (NULL = zero) */
+} tk_sgmres_params;
+
+/* Solver report (host memory owned by the caller). */
+typedef struct {
+  int32_t status, iters_total, cycles;
+  double true_relres, seconds;
+  int32_t hist_cap, hist_len;  /* hist_cap: capacity of the arrays below */
+  double* hist_sketched;       /* [hist_cap] sketched relative residual per iteration, or NULL */
+  double* hist_true;           /* [hist_cap] true relative residual per cycle, or NULL */
+  int32_t* hist_ranks;         /* [hist_cap * TK_MAX_D] ranks of each new basis tensor, or NULL */
+} tk_sgmres_info;
+
+/* Operator factors applied to a Tucker tensor (Eq. (2)): for every term j and
+ * mode k with A_j^(k) != NULL writes AU[j*d+k] = A_j^(k) U_k (transpose = 0)
+ * or A_j^(k)^T U_k (transpose = 1) into caller buffers of n_k x x->rcap[k];
+ * L(x) is then the block sum of terms alpha_j * (core; AU or U).  AU entries
+ * of identity factors are ignored (may be NULL). */
+int tucker_apply_op(const tk_kron_op* op, const tk_tucker* x, int32_t transpose, double* const* AU, void* ws,
+                    size_t ws_bytes, void* stream);
+int tucker_apply_op_workspace(const tk_kron_op* op, const tk_tucker* x, size_t* bytes);
+
+/* Khatri-Rao sketch (Alg. 2, sketch of B and of each W): out[l] =
+ * (S_1[:,l] kron ... kron S_d[:,l])^T vec(sum_b coef_b X_b), l < s; out is a
+ * device vector of length s. */
+int tucker_sketch(const tk_block_sum* x, const double* const* S, int64_t s, double* out, void* ws, size_t ws_bytes,
+                  void* stream);
+int tucker_sketch_workspace(const tk_block_sum* x, int64_t s, size_t* bytes);
+
+/* RoundSum (Sec. 3.1): randomized RHOSVD recompression of a block sum into
+ * `out` (ranks written to out->r; out->rcap must hold them).  *s_out (host,
+ * optional) receives the sketch width used. */
+int tucker_rhosvd(const tk_block_sum* in, const tk_round_params* prm, const double* const* omega, tk_tucker* out,
+                  int32_t* s_out, void* ws, size_t ws_bytes, void* stream);
+int tucker_rhosvd_workspace(const tk_block_sum* in, const tk_round_params* prm, size_t* bytes);
+
+/* Restarted RHOSVD-Tucker sGMRES (Alg. 2 cycles wrapped in FP64 iterative
+ * refinement): solves L(X) = B to relative residual tol.  Returns the status
+ * (TK_OK / TK_NOT_CONVERGED / TK_BREAKDOWN / TK_RANK_FLOOR) or an error. */
+int tsgmres_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* prm, const double* const* S,
+                  const double* const* omega, tk_tucker* x, tk_sgmres_info* info, void* ws, size_t ws_bytes,
+                  void* stream);
+int tsgmres_solve_workspace(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* prm, size_t* bytes);
+
+/* Adjoint of the solve, for a loss l(x) with cotangent x_bar = dl/dx (a block
+ * sum): solves L^T lambda = RoundSum(x_bar) with the same sGMRES on transposed
+ * factors; lambda = dl/dB.  dalpha (host [nterms], optional) receives
+ * dl/dalpha_j = -<lambda, x x_1 A_j^(1) ... x_d A_j^(d)>; dA[j*d+k] (device
+ * row-major n_k x n_k, optional, NULL entries skipped) receives
+ * dl/dA_j^(k) = -alpha_j lambda_(k) (kron_{l!=k} A_j^(l)) x_(k)^T. */
+int tsgmres_backward(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xbar,
+                     const tk_sgmres_params* prm, const double* const* S, const double* const* omega,
+                     tk_tucker* lambda, double* dalpha, double* const* dA, tk_sgmres_info* info, void* ws,
+                     size_t ws_bytes, void* stream);
+int tsgmres_backward_workspace(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xbar,
+                               const tk_sgmres_params* prm, size_t* bytes);
+
+/* Exact Frobenius norm of a block sum without cancellation: per mode a
+ * Householder QR of the concatenated distinct factors, then the norm of the
+ * small coefficient core (the norm used for Alg. 2's beta and the restart
+ * residual).  *out (host) receives ||sum_b coef_b X_b||_F.  Ranks <= 64. */
+int tucker_norm(const tk_block_sum* x, double* out, void* ws, size_t ws_bytes, void* stream);
+int tucker_norm_workspace(const tk_block_sum* x, size_t* bytes);
+
+/* Message of the last error on this thread ("" if none). */
+const char* tk_last_error(void);
+/* ABI version (major * 100 + minor). */
+int tk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSGMRES_H_ */

@@ -25,7 +25,9 @@ Readings where the paper leaves a choice (each listed in the design doc):
   * ST-HOSVD visits modes 1..d, uses a true SVD of each unfolding, keeps
     ``r_k = min{r >= 1 : sum_{i>r} sigma_i^2 <= eps^2 ||C^||^2 / d}``
     capped at ``cap`` (or the forced rank, for rank replay);
-  * a zero sum returns a rank-(1,..,1) zero tensor.
+  * a sum whose projected core has ||C^||_F <= 16 u sum_b |c_b| ||G^(b)||_F
+    (u = 2^-53) is numerically zero -- below that level every digit of the
+    result is rounding noise -- and returns a rank-(1,..,1) zero tensor.
 """
 from __future__ import annotations
 
@@ -38,6 +40,7 @@ from .tucker import Tucker, multi_ttm, ttm, unfold
 
 DELTA_CLAMP = 1e-12
 EIG_MAX = 160
+ZERO_TOL = 16.0 * 2.0 ** -53
 
 
 @dataclasses.dataclass
@@ -87,12 +90,12 @@ def effective_sketch_size(blocks, prm: RoundParams):
     return int(s), rt
 
 
-def st_hosvd(C: np.ndarray, eps: float, cap: int, force_ranks=None):
+def st_hosvd(C: np.ndarray, eps: float, cap: int, force_ranks=None, zero: bool = False):
     """Sequentially truncated HOSVD of a small dense core (step 5): modes in
     order 1..d, thin SVD of the current unfolding, per-mode budget
     eps^2 ||C||^2 / d.  Returns (core, [V_k], ranks)."""
     d = C.ndim
-    total = float(np.sum(C * C))
+    total = 0.0 if zero else float(np.sum(C * C))
     Vs, ranks = [], []
     for k in range(d):
         Ck = unfold(C, k)
@@ -151,9 +154,11 @@ def roundsum(blocks, Omega: Sequence[np.ndarray], prm: RoundParams):
         T = c * multi_ttm(X.core, [Uh[k].T @ X.U[k] for k in range(d)])
         C = T if C is None else C + T
     # 5. ST-HOSVD of the projected core
-    core, Vs, ranks = st_hosvd(C, prm.eps, prm.cap, prm.force_ranks)
+    wsum = sum(abs(c) * np.linalg.norm(X.core.ravel()) for c, X in blocks)
+    zero = float(np.linalg.norm(C.ravel())) <= ZERO_TOL * wsum
+    core, Vs, ranks = st_hosvd(C, prm.eps, prm.cap, prm.force_ranks, zero=zero)
     U = [Uh[k] @ Vs[k] for k in range(d)]
-    if float(np.sum(C * C)) == 0.0 and prm.force_ranks is None:
+    if zero and prm.force_ranks is None:
         core = np.zeros((1,) * d)
         U = [np.eye(u.shape[0], 1) for u in U]
         ranks = [1] * d

@@ -1,0 +1,12 @@
+"""MI355X-native randomized Tucker-sketched GMRES (HIP, gfx950).
+
+The numerical work lives in ``libtsgmres.so`` (C ABI in ``include/tsgmres.h``);
+this package is the thin Python binding.  Importing it does not load the
+library; the first call does, and fails loudly if the library is not built.
+"""
+from ._abi import EXPORTS, LIB_PATH, TkError, load
+from .api import (KronOp, SolveParams, Tucker, TuckerSGMRESLoss, apply_op, backward, norm, rhosvd, sketch, solve,
+                  storage_floats)
+
+__all__ = ["EXPORTS", "LIB_PATH", "TkError", "load", "KronOp", "SolveParams", "Tucker", "TuckerSGMRESLoss",
+           "apply_op", "backward", "norm", "rhosvd", "sketch", "solve", "storage_floats"]

@@ -1,0 +1,365 @@
+"""Torch-facing wrappers of the C ABI (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module only lays out
+device buffers with PyTorch, fills the ABI structs and reads results back.
+
+Layouts (see ``include/tsgmres.h``):
+  * ``Tucker.core``: float64 CUDA tensor of shape ``rcap`` (C order);
+  * ``Tucker.U[k]``: float64 CUDA tensor of shape ``(rcap_k, n_k)`` -- the
+    row-major view of a column-major ``n_k x rcap_k`` factor;
+  * operator factors: ``(n_k, n_k)`` row-major tensors or ``None``;
+  * sketch factors ``S_k``: ``(s, n_k)`` (column-major ``n_k x s``) and
+    ``Omega_k``: ``(cap + p, n_k)``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import TK_MAX_D, TkBlockSum, TkKronOp, TkRoundParams, TkSgmresInfo, TkSgmresParams, TkTucker, check
+
+__all__ = ["Tucker", "KronOp", "SolveParams", "apply_op", "sketch", "rhosvd", "norm", "solve", "backward",
+           "TuckerSGMRESLoss", "storage_floats"]
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+@dataclasses.dataclass
+class Tucker:
+    """Tucker tensor on the GPU with capacity-padded core and factors."""
+    core: torch.Tensor
+    U: List[torch.Tensor]
+    ranks: Tuple[int, ...]
+
+    @property
+    def d(self) -> int:
+        return self.core.dim()
+
+    @property
+    def n(self) -> Tuple[int, ...]:
+        return tuple(int(u.shape[1]) for u in self.U)
+
+    @property
+    def rcap(self) -> Tuple[int, ...]:
+        return tuple(int(s) for s in self.core.shape)
+
+    @staticmethod
+    def empty(n: Sequence[int], rcap: Sequence[int], device="cuda") -> "Tucker":
+        core = torch.zeros(tuple(rcap), dtype=torch.float64, device=device)
+        U = [torch.zeros((r, nk), dtype=torch.float64, device=device) for nk, r in zip(n, rcap)]
+        return Tucker(core, U, tuple(1 for _ in n))
+
+    @staticmethod
+    def from_numpy(core: np.ndarray, factors: Sequence[np.ndarray], device="cuda",
+                   rcap: Optional[Sequence[int]] = None) -> "Tucker":
+        ranks = tuple(core.shape)
+        rcap = tuple(rcap) if rcap is not None else ranks
+        c = np.zeros(rcap)
+        c[tuple(slice(0, r) for r in ranks)] = core
+        Us = []
+        for k, u in enumerate(factors):
+            ut = np.zeros((rcap[k], u.shape[0]))
+            ut[: u.shape[1]] = u.T
+            Us.append(torch.from_numpy(ut).to(device))
+        return Tucker(torch.from_numpy(c).to(device), Us, ranks)
+
+    def to_numpy(self):
+        r = self.ranks
+        core = self.core[tuple(slice(0, x) for x in r)].cpu().numpy().copy()
+        U = [self.U[k][: r[k]].cpu().numpy().T.copy() for k in range(self.d)]
+        return core, U
+
+    def struct(self) -> TkTucker:
+        t = TkTucker()
+        t.d = self.d
+        for k in range(self.d):
+            t.n[k] = self.n[k]
+            t.r[k] = self.ranks[k]
+            t.rcap[k] = self.rcap[k]
+            t.U[k] = _ptr(self.U[k])
+        t.core = _ptr(self.core)
+        return t
+
+
+def _blocks_struct(blocks: Sequence[Tuple[float, Tucker]]):
+    arr = (TkTucker * len(blocks))(*[b.struct() for _, b in blocks])
+    coef = (C.c_double * len(blocks))(*[float(c) for c, _ in blocks])
+    bs = TkBlockSum()
+    bs.nblocks = len(blocks)
+    bs.coef = coef
+    bs.blocks = arr
+    return bs, (arr, coef)
+
+
+@dataclasses.dataclass
+class KronOp:
+    """``L(X) = sum_j alpha_j X x_1 A_j^(1) ... x_d A_j^(d)`` (row-major factors)."""
+    alpha: List[float]
+    A: List[List[Optional[torch.Tensor]]]
+
+    @property
+    def d(self) -> int:
+        return len(self.A[0])
+
+    @property
+    def nterms(self) -> int:
+        return len(self.alpha)
+
+    @staticmethod
+    def from_terms(terms, device="cuda") -> "KronOp":
+        cache = {}
+
+        def dev(A):
+            if A is None:
+                return None
+            key = id(A)
+            if key not in cache:
+                cache[key] = torch.from_numpy(np.ascontiguousarray(A, dtype=np.float64)).to(device)
+            return cache[key]
+        return KronOp([float(a) for a, _ in terms], [[dev(A) for A in As] for _, As in terms])
+
+    def struct(self, n: Sequence[int]):
+        op = TkKronOp()
+        op.d = self.d
+        for k in range(self.d):
+            op.n[k] = n[k]
+        op.nterms = self.nterms
+        alpha = (C.c_double * self.nterms)(*self.alpha)
+        ptrs = (C.c_void_p * (self.nterms * self.d))(*[_ptr(A) for As in self.A for A in As])
+        op.alpha = alpha
+        op.A = ptrs
+        return op, (alpha, ptrs)
+
+
+def _ptr_array(ts: Sequence[Optional[torch.Tensor]]):
+    return (C.c_void_p * len(ts))(*[_ptr(t) for t in ts])
+
+
+def apply_op(op: KronOp, x: Tucker, transpose: bool = False):
+    """Factor products of ``L(x)``; returns the block list ``[(alpha_j, Tucker)]``."""
+    lib = _abi.load()
+    d = x.d
+    AU = []
+    for As in op.A:
+        AU.append([None if A is None else torch.zeros_like(x.U[k]) for k, A in enumerate(As)])
+    ops, keep = op.struct(x.n)
+    xs = x.struct()
+    out = _ptr_array([t for row in AU for t in row])
+    nb = C.c_size_t()
+    check(lib.tucker_apply_op_workspace(C.byref(ops), C.byref(xs), C.byref(nb)))
+    ws = _workspace(nb.value, x.core.device)
+    check(lib.tucker_apply_op(C.byref(ops), C.byref(xs), int(transpose), out, C.c_void_p(ws.data_ptr()),
+                              nb.value, _stream()))
+    blocks = []
+    for j, As in enumerate(op.A):
+        U = [x.U[k] if A is None else AU[j][k] for k, A in enumerate(As)]
+        blocks.append((op.alpha[j], Tucker(x.core, U, x.ranks)))
+    return blocks
+
+
+def sketch(blocks, S: Sequence[torch.Tensor]) -> torch.Tensor:
+    """Khatri-Rao sketch ``S^T vec(sum_b c_b X_b)`` (length s)."""
+    lib = _abi.load()
+    bs, keep = _blocks_struct(blocks)
+    s = int(S[0].shape[0])
+    dev = blocks[0][1].core.device
+    out = torch.zeros(s, dtype=torch.float64, device=dev)
+    nb = C.c_size_t()
+    check(lib.tucker_sketch_workspace(C.byref(bs), s, C.byref(nb)))
+    ws = _workspace(nb.value, dev)
+    check(lib.tucker_sketch(C.byref(bs), _ptr_array(S), s, C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()),
+                            nb.value, _stream()))
+    return out
+
+
+def rhosvd(blocks, omega: Sequence[torch.Tensor], eps: float, cap: int, p: int = 5, tau: float = -1.0,
+           force_s: int = -1, force_ranks: Optional[Sequence[int]] = None, out_rcap: Optional[Sequence[int]] = None):
+    """RoundSum of a block sum; returns ``(Tucker, s)``."""
+    lib = _abi.load()
+    bs, keep = _blocks_struct(blocks)
+    x0 = blocks[0][1]
+    prm = TkRoundParams()
+    prm.eps, prm.tau, prm.rank_cap, prm.oversample, prm.force_s = eps, tau, cap, p, force_s
+    for k in range(TK_MAX_D):
+        prm.force_ranks[k] = -1 if force_ranks is None or k >= len(force_ranks) else int(force_ranks[k])
+    rc = tuple(out_rcap) if out_rcap is not None else (cap,) * x0.d
+    out = Tucker.empty(x0.n, rc, x0.core.device)
+    os_ = out.struct()
+    nb = C.c_size_t()
+    check(lib.tucker_rhosvd_workspace(C.byref(bs), C.byref(prm), C.byref(nb)))
+    ws = _workspace(nb.value, x0.core.device)
+    s_out = C.c_int32(0)
+    check(lib.tucker_rhosvd(C.byref(bs), C.byref(prm), _ptr_array(omega), C.byref(os_), C.byref(s_out),
+                            C.c_void_p(ws.data_ptr()), nb.value, _stream()))
+    out.ranks = tuple(int(os_.r[k]) for k in range(x0.d))
+    return out, int(s_out.value)
+
+
+def norm(blocks) -> float:
+    """Exact Frobenius norm of a block sum (QR of concatenated factors)."""
+    lib = _abi.load()
+    bs, keep = _blocks_struct(blocks)
+    dev = blocks[0][1].core.device
+    nb = C.c_size_t()
+    check(lib.tucker_norm_workspace(C.byref(bs), C.byref(nb)))
+    ws = _workspace(nb.value, dev)
+    out = C.c_double(0.0)
+    check(lib.tucker_norm(C.byref(bs), C.byref(out), C.c_void_p(ws.data_ptr()), nb.value, _stream()))
+    return float(out.value)
+
+
+@dataclasses.dataclass
+class SolveParams:
+    form: int = 0            # 0 FP64, 1 FP32 cycles
+    tol: float = 1e-8
+    eta: float = 0.4
+    maxiter: int = 60
+    max_restarts: int = 50
+    k_trunc: int = 2
+    rank_cap: int = 48
+    oversample: int = 5
+    eps_trunc: float = -1.0
+    eps_min: float = -1.0
+    tol_inner_floor: float = -1.0
+
+    def struct(self, s: int, x0: Optional[Tucker] = None):
+        p = TkSgmresParams()
+        p.form, p.tol, p.eta, p.maxiter, p.max_restarts = self.form, self.tol, self.eta, self.maxiter, self.max_restarts
+        p.k_trunc, p.rank_cap, p.oversample, p.s = self.k_trunc, self.rank_cap, self.oversample, s
+        p.eps_trunc, p.eps_min, p.tol_inner_floor = self.eps_trunc, self.eps_min, self.tol_inner_floor
+        keep = None
+        if x0 is not None:
+            keep = x0.struct()
+            p.x0 = C.pointer(keep)
+        return p, keep
+
+
+def _info(hist_cap: int):
+    info = TkSgmresInfo()
+    hs = (C.c_double * hist_cap)()
+    ht = (C.c_double * hist_cap)()
+    hr = (C.c_int32 * (hist_cap * TK_MAX_D))()
+    info.hist_cap = hist_cap
+    info.hist_sketched = hs
+    info.hist_true = ht
+    info.hist_ranks = hr
+    return info, (hs, ht, hr)
+
+
+def _info_dict(info, keep, d):
+    hs, ht, hr = keep
+    n = info.hist_len
+    return dict(status=int(info.status), status_name=_abi.STATUS.get(int(info.status), "?"),
+                iters=int(info.iters_total), cycles=int(info.cycles), true_relres=float(info.true_relres),
+                seconds=float(info.seconds), hist=[hs[i] for i in range(n)],
+                true_hist=[ht[i] for i in range(int(info.cycles))],
+                ranks=[tuple(hr[i * TK_MAX_D + k] for k in range(d)) for i in range(n)])
+
+
+def _hist_cap(prm: SolveParams) -> int:
+    return prm.maxiter * max(prm.max_restarts, 1) + 8
+
+
+def solve(op: KronOp, b: Tucker, S, omega, prm: SolveParams, x0: Optional[Tucker] = None, workspace=None):
+    """Restarted Tucker sGMRES; returns ``(x, info)``."""
+    lib = _abi.load()
+    ops, k1 = op.struct(b.n)
+    bst = b.struct()
+    s = int(S[0].shape[0])
+    ps, k2 = prm.struct(s, x0)
+    nb = C.c_size_t()
+    check(lib.tsgmres_solve_workspace(C.byref(ops), C.byref(bst), C.byref(ps), C.byref(nb)))
+    ws = workspace if workspace is not None and workspace.numel() >= nb.value else _workspace(nb.value, b.core.device)
+    x = Tucker.empty(b.n, (prm.rank_cap,) * b.d, b.core.device)
+    xs = x.struct()
+    info, keep = _info(_hist_cap(prm))
+    check(lib.tsgmres_solve(C.byref(ops), C.byref(bst), C.byref(ps), _ptr_array(S), _ptr_array(omega), C.byref(xs),
+                            C.byref(info), C.c_void_p(ws.data_ptr()), nb.value, _stream()))
+    x.ranks = tuple(int(xs.r[k]) for k in range(b.d))
+    return x, _info_dict(info, keep, b.d)
+
+
+def solve_workspace_bytes(op: KronOp, b: Tucker, s: int, prm: SolveParams) -> int:
+    lib = _abi.load()
+    ops, k1 = op.struct(b.n)
+    bst = b.struct()
+    ps, k2 = prm.struct(s)
+    nb = C.c_size_t()
+    check(lib.tsgmres_solve_workspace(C.byref(ops), C.byref(bst), C.byref(ps), C.byref(nb)))
+    return int(nb.value)
+
+
+def backward(op: KronOp, x: Tucker, xbar_blocks, S, omega, prm: SolveParams, want_dA: bool = True):
+    """Adjoint solve and gradients; returns ``(lambda, dalpha, dA, info)`` with
+    ``dA[j][k]`` row-major ``(n_k, n_k)`` tensors (None for identity factors)."""
+    lib = _abi.load()
+    ops, k1 = op.struct(x.n)
+    xst = x.struct()
+    bs, k3 = _blocks_struct(xbar_blocks)
+    s = int(S[0].shape[0])
+    ps, k2 = prm.struct(s)
+    nb = C.c_size_t()
+    check(lib.tsgmres_backward_workspace(C.byref(ops), C.byref(xst), C.byref(bs), C.byref(ps), C.byref(nb)))
+    ws = _workspace(nb.value, x.core.device)
+    lam = Tucker.empty(x.n, (prm.rank_cap,) * x.d, x.core.device)
+    ls_ = lam.struct()
+    dal = (C.c_double * op.nterms)()
+    dA = [[None if A is None else torch.zeros_like(A) for A in As] for As in op.A] if want_dA else None
+    dAp = _ptr_array([t for row in dA for t in row]) if want_dA else None
+    info, keep = _info(_hist_cap(prm))
+    check(lib.tsgmres_backward(C.byref(ops), C.byref(xst), C.byref(bs), C.byref(ps), _ptr_array(S),
+                               _ptr_array(omega), C.byref(ls_), dal, dAp, C.byref(info), C.c_void_p(ws.data_ptr()),
+                               nb.value, _stream()))
+    lam.ranks = tuple(int(ls_.r[k]) for k in range(x.d))
+    return lam, np.array([dal[j] for j in range(op.nterms)]), dA, _info_dict(info, keep, x.d)
+
+
+class TuckerSGMRESLoss(torch.autograd.Function):
+    """loss(alpha) = ||x(alpha) - x_target||^2 / 2 with L(alpha) x = b solved by
+    Tucker sGMRES; the backward pass is the hand-written adjoint solve.
+
+    ``problem`` is a dict with keys op (KronOp, its alphas are overridden),
+    b, x_target (Tucker), S, omega, prm (SolveParams).  After ``backward`` the
+    adjoint solution (= dl/db) is left in ``problem['lambda']``."""
+
+    @staticmethod
+    def forward(ctx, alpha: torch.Tensor, problem: dict):
+        op = KronOp([float(a) for a in alpha.detach().cpu().tolist()], problem["op"].A)
+        x, info = solve(op, problem["b"], problem["S"], problem["omega"], problem["prm"])
+        xt = problem["x_target"]
+        loss = 0.5 * norm([(1.0, x), (-1.0, xt)]) ** 2
+        ctx.problem = problem
+        ctx.op = op
+        ctx.x = x
+        problem["x"] = x
+        problem["forward_info"] = info
+        return torch.tensor(loss, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, g):
+        p = ctx.problem
+        lam, dalpha, _, info = backward(ctx.op, ctx.x, [(1.0, ctx.x), (-1.0, p["x_target"])], p["S"], p["omega"],
+                                        p["prm"], want_dA=False)
+        p["lambda"] = lam
+        p["backward_info"] = info
+        return g * torch.from_numpy(dalpha), None
+
+
+def storage_floats(n: Sequence[int], ranks: Sequence[int]) -> int:
+    """Floats stored by a Tucker tensor: sum_k n_k r_k + prod_k r_k."""
+    return int(sum(a * b for a, b in zip(n, ranks)) + np.prod(ranks))

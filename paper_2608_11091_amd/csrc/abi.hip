@@ -1,0 +1,584 @@
+// C ABI of the library (declared in include/tsgmres.h): argument checks,
+// import of caller tensors into capacity-padded internal layouts, planning
+// (measure-only for the *_workspace queries), execution and export.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+
+#include "../../include/tsgmres.h"
+#include "engine.hpp"
+
+namespace tk {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* last_error() { return g_err.c_str(); }
+
+template <typename F>
+static int guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const Error& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return kErrInvalidArg;
+  } catch (...) {
+    g_err = "unknown error";
+    return kErrInvalidArg;
+  }
+}
+
+namespace {
+
+void check_tucker(const tk_tucker* t, const char* name, int d, const int64_t* n) {
+  TK_CHECK(t != nullptr, kErrInvalidArg, std::string(name) + " is NULL");
+  TK_CHECK(t->d == d, kErrShape, std::string(name) + ": order mismatch");
+  TK_CHECK(t->core != nullptr, kErrInvalidArg, std::string(name) + ": core is NULL");
+  for (int k = 0; k < d; ++k) {
+    TK_CHECK(t->n[k] == n[k], kErrShape, std::string(name) + ": mode size mismatch");
+    TK_CHECK(t->r[k] >= 1 && t->r[k] <= t->rcap[k], kErrShape, std::string(name) + ": rank outside [1, rcap]");
+    TK_CHECK(t->r[k] <= t->n[k], kErrShape, std::string(name) + ": rank above mode size");
+    TK_CHECK(t->U[k] != nullptr, kErrInvalidArg, std::string(name) + ": factor is NULL");
+  }
+}
+
+void check_dims(int d, const int64_t* n) {
+  TK_CHECK(d >= 2 && d <= kMaxD, kErrUnsupported, "order d must be in [2, 4]");
+  for (int k = 0; k < d; ++k) {
+    TK_CHECK(n[k] >= 1, kErrShape, "mode sizes must be positive");
+    TK_CHECK(n[k] <= 512, kErrUnsupported, "mode sizes above 512 are not supported");
+  }
+}
+
+void check_op(const tk_kron_op* op, int d, const int64_t* n) {
+  TK_CHECK(op != nullptr, kErrInvalidArg, "operator is NULL");
+  TK_CHECK(op->d == d, kErrShape, "operator order mismatch");
+  for (int k = 0; k < d; ++k) TK_CHECK(op->n[k] == n[k], kErrShape, "operator mode size mismatch");
+  TK_CHECK(op->nterms >= 1 && op->alpha != nullptr && op->A != nullptr, kErrInvalidArg, "operator has no terms");
+}
+
+// Host-side rank staging kept alive by the plan.
+struct HostInts {
+  int v[kMaxD] = {1, 1, 1, 1};
+};
+
+template <typename T>
+void emit_import(Seq& q, const Shape& sh, const tk_tucker& u, const TT<T>& t) {
+  auto hr = std::make_shared<HostInts>();
+  int sd[kMaxD] = {1, 1, 1, 1}, sv[kMaxD] = {1, 1, 1, 1}, dd[kMaxD] = {1, 1, 1, 1};
+  std::array<int, kMaxD> rk{}, ncol{};
+  const int d = sh.d;
+  for (int k = 0; k < d; ++k) {
+    hr->v[k] = int(u.r[k]);
+    sd[k] = int(u.rcap[k]);
+    sv[k] = int(u.r[k]);
+    dd[k] = sh.rc;
+    rk[k] = int(u.r[k]);
+    ncol[k] = sh.n[k];
+  }
+  const double* core = u.core;
+  std::array<const double*, kMaxD> U = {u.U[0], u.U[1], u.U[2], u.U[3]};
+  const int rc = sh.rc;
+  q.steps.push_back([=](hipStream_t st) {
+    core_recap<double>(core, sd, sv, t.core, dd, d, st);
+    for (int k = 0; k < d; ++k) mat_recap<double>(U[k], ncol[k], ncol[k], rk[k], t.U[k], ncol[k], ncol[k], rc, st);
+    TK_HIP(hipMemcpyAsync(t.rank, hr->v, sizeof(int) * kMaxD, hipMemcpyHostToDevice, st));
+  });
+}
+
+// Copies an internal tensor out; ranks are read back first.
+void export_tt(const Shape& sh, const TT<double>& t, tk_tucker* u, hipStream_t st) {
+  int r[kMaxD] = {0, 0, 0, 0};
+  TK_HIP(hipMemcpyAsync(r, t.rank, sizeof(int) * kMaxD, hipMemcpyDeviceToHost, st));
+  TK_HIP(hipStreamSynchronize(st));
+  const int d = sh.d;
+  for (int k = 0; k < d; ++k)
+    TK_CHECK(r[k] >= 1 && r[k] <= u->rcap[k], kErrCapacity,
+             "output rank " + std::to_string(r[k]) + " exceeds the capacity of the output tensor");
+  int sd[kMaxD] = {1, 1, 1, 1}, sv[kMaxD] = {1, 1, 1, 1}, dd[kMaxD] = {1, 1, 1, 1};
+  for (int k = 0; k < d; ++k) {
+    sd[k] = sh.rc;
+    sv[k] = r[k];
+    dd[k] = int(u->rcap[k]);
+  }
+  core_recap<double>(t.core, sd, sv, u->core, dd, d, st);
+  for (int k = 0; k < d; ++k)
+    mat_recap<double>(t.U[k], sh.n[k], sh.n[k], r[k], u->U[k], sh.n[k], sh.n[k], int(u->rcap[k]), st);
+  for (int k = 0; k < d; ++k) u->r[k] = r[k];
+  TK_HIP(hipStreamSynchronize(st));
+}
+
+void finish_blob(Arena& ar, Blob& blob, hipStream_t st) {
+  blob.dev = ar.alloc<unsigned char>(std::max<size_t>(blob.host.size(), 16));
+  if (!ar.measuring())
+    TK_HIP(hipMemcpyAsync(blob.dev, blob.host.data(), blob.host.size(), hipMemcpyHostToDevice, st));
+}
+
+Shape shape_of(int d, const int64_t* n, int rc, int cap, int p) {
+  Shape sh;
+  sh.d = d;
+  for (int k = 0; k < d; ++k) sh.n[k] = int(n[k]);
+  sh.rc = rc;
+  sh.cap = cap;
+  sh.p = p;
+  return sh;
+}
+
+// ---------------------------------------------------------------- apply
+int do_apply(const tk_kron_op* op, const tk_tucker* x, int transpose, double* const* AU, Arena& ar, hipStream_t st) {
+  TK_CHECK(x != nullptr, kErrInvalidArg, "x is NULL");
+  check_dims(x->d, x->n);
+  check_op(op, x->d, x->n);
+  check_tucker(x, "x", x->d, x->n);
+  const int d = x->d;
+  Blob blob;
+  Planner pl(ar, blob);
+  Seq q;
+  for (int j = 0; j < op->nterms; ++j)
+    for (int k = 0; k < d; ++k) {
+      const double* A = op->A[j * d + k];
+      if (!A) continue;
+      TK_CHECK(AU != nullptr && AU[j * d + k] != nullptr, kErrInvalidArg, "missing output buffer for a factor product");
+      const int n = int(x->n[k]), rcap = int(x->rcap[k]);
+      plan_gemm<double>(q, pl, !transpose, false, n, rcap, n, A, n, x->U[k], n, AU[j * d + k], n, 1.0, 0.0);
+    }
+  finish_blob(ar, blob, st);
+  if (ar.measuring()) return 0;
+  q.run(st);
+  TK_HIP(hipStreamSynchronize(st));
+  return 0;
+}
+
+// ---------------------------------------------------------------- block sums
+struct Imported {
+  Shape sh;
+  std::vector<TT<double>> t;
+  Blocks<double> blocks;
+  std::shared_ptr<std::vector<double>> coef;
+};
+
+Imported import_blocks(Seq& q, Arena& ar, const tk_block_sum* in, int cap, int p) {
+  TK_CHECK(in != nullptr && in->nblocks >= 1 && in->blocks != nullptr && in->coef != nullptr, kErrInvalidArg,
+           "empty block sum");
+  const tk_tucker& b0 = in->blocks[0];
+  check_dims(b0.d, b0.n);
+  int rc = std::max(cap, 1);
+  for (int b = 0; b < in->nblocks; ++b) {
+    check_tucker(&in->blocks[b], "block", b0.d, b0.n);
+    for (int k = 0; k < b0.d; ++k) rc = std::max<int>(rc, int(in->blocks[b].r[k]));
+  }
+  TK_CHECK(rc <= 128, kErrUnsupported, "ranks above 128 are not supported");
+  Imported im;
+  im.sh = shape_of(b0.d, b0.n, rc, cap, p);
+  im.coef = std::make_shared<std::vector<double>>(in->coef, in->coef + in->nblocks);
+  for (int b = 0; b < in->nblocks; ++b) {
+    TT<double> t = alloc_tt<double>(ar, im.sh);
+    emit_import<double>(q, im.sh, in->blocks[b], t);
+    im.t.push_back(t);
+    im.blocks.add(t, nullptr, in->coef[b]);
+  }
+  return im;
+}
+
+int do_sketch(const tk_block_sum* x, const double* const* S, int64_t s, double* out, Arena& ar, hipStream_t st) {
+  TK_CHECK(S != nullptr && out != nullptr, kErrInvalidArg, "sketch factors or output missing");
+  TK_CHECK(s >= 1 && s <= 65535, kErrInvalidArg, "sketch size out of range");
+  Blob blob;
+  Planner pl(ar, blob);
+  Seq q;
+  Imported im = import_blocks(q, ar, x, 1, 0);
+  std::array<const double*, kMaxD> Sk{};
+  for (int k = 0; k < im.sh.d; ++k) {
+    TK_CHECK(S[k] != nullptr, kErrInvalidArg, "sketch factor is NULL");
+    Sk[k] = S[k];
+  }
+  plan_sketch<double>(q, pl, im.sh, im.blocks, Sk, int(s), out);
+  finish_blob(ar, blob, st);
+  if (ar.measuring()) return 0;
+  q.run(st);
+  TK_HIP(hipStreamSynchronize(st));
+  return 0;
+}
+
+int do_rhosvd(const tk_block_sum* in, const tk_round_params* prm, const double* const* omega, tk_tucker* out,
+              int32_t* s_out, Arena& ar, hipStream_t st) {
+  TK_CHECK(prm != nullptr, kErrInvalidArg, "parameters are NULL");
+  TK_CHECK(prm->rank_cap >= 1 && prm->oversample >= 0, kErrInvalidArg, "invalid rank cap / oversampling");
+  TK_CHECK(prm->rank_cap + prm->oversample <= 64, kErrUnsupported, "rank_cap + oversample above 64");
+  TK_CHECK(prm->eps >= 0.0, kErrInvalidArg, "eps must be >= 0");
+  Blob blob;
+  Planner pl(ar, blob);
+  Seq q;
+  Imported im = import_blocks(q, ar, in, prm->rank_cap, prm->oversample);
+  const Shape& sh = im.sh;
+  TK_CHECK(prm->force_s < 0 || (prm->force_s >= 1 && prm->force_s <= sh.sc()), kErrInvalidArg,
+           "force_s outside [1, rank_cap + oversample]");
+  RoundCfg cfg;
+  cfg.eps = prm->eps;
+  cfg.tau = prm->tau;
+  cfg.force_s = prm->force_s;
+  for (int k = 0; k < sh.d; ++k) {
+    cfg.force_r[k] = prm->force_ranks[k];
+    TK_CHECK(cfg.force_r[k] <= prm->rank_cap, kErrInvalidArg, "forced rank above rank_cap");
+  }
+  std::array<const double*, kMaxD> om{};
+  TK_CHECK(omega != nullptr, kErrInvalidArg, "omega is NULL");
+  for (int k = 0; k < sh.d; ++k) om[k] = omega[k];
+  if (out) check_dims(out->d, out->n);
+  TT<double> o = alloc_tt<double>(ar, sh);
+  RoundSumOut<double> ro = plan_roundsum<double>(q, pl, sh, im.blocks, cfg, om, o, nullptr);
+  finish_blob(ar, blob, st);
+  if (ar.measuring()) return 0;
+  TK_CHECK(out != nullptr && out->d == sh.d, kErrInvalidArg, "output tensor missing or of wrong order");
+  for (int k = 0; k < sh.d; ++k) TK_CHECK(out->n[k] == sh.n[k], kErrShape, "output mode size mismatch");
+  q.run(st);
+  if (s_out) {
+    TK_HIP(hipMemcpyAsync(s_out, ro.s_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  export_tt(sh, o, out, st);
+  return 0;
+}
+
+int do_norm(const tk_block_sum* x, double* out, Arena& ar, hipStream_t st) {
+  Blob blob;
+  Planner pl(ar, blob);
+  Seq q;
+  Imported im = import_blocks(q, ar, x, 1, 0);
+  TK_CHECK(im.sh.rc <= 64, kErrUnsupported, "exact norm: ranks above 64");
+  double* n2 = ar.alloc<double>(1);
+  plan_exact_norm2(q, pl, im.sh, im.blocks, n2);
+  finish_blob(ar, blob, st);
+  if (ar.measuring()) return 0;
+  TK_CHECK(out != nullptr, kErrInvalidArg, "output pointer is NULL");
+  q.run(st);
+  double h = 0.0;
+  TK_HIP(hipMemcpyAsync(&h, n2, sizeof(double), hipMemcpyDeviceToHost, st));
+  TK_HIP(hipStreamSynchronize(st));
+  *out = std::sqrt(std::max(h, 0.0));
+  return 0;
+}
+
+// ---------------------------------------------------------------- solve
+SolveCfg solve_cfg(const tk_sgmres_params* prm) {
+  SolveCfg c;
+  c.form = prm->form;
+  c.tol = prm->tol;
+  c.eta = prm->eta;
+  c.maxiter = prm->maxiter;
+  c.max_restarts = prm->max_restarts;
+  c.k_trunc = prm->k_trunc;
+  c.s = int(prm->s);
+  c.eps_trunc = prm->eps_trunc;
+  c.eps_min = prm->eps_min;
+  c.tol_inner_floor = prm->tol_inner_floor;
+  return c;
+}
+
+void check_params(const tk_sgmres_params* prm) {
+  TK_CHECK(prm != nullptr, kErrInvalidArg, "parameters are NULL");
+  TK_CHECK(prm->form == TK_FORM_FP64 || prm->form == TK_FORM_FP32, kErrUnsupported, "unknown precision form");
+  TK_CHECK(prm->tol > 0 && prm->eta > 0 && prm->eta <= 1, kErrInvalidArg, "tol > 0 and 0 < eta <= 1 required");
+  TK_CHECK(prm->maxiter >= 1 && prm->maxiter <= 64, kErrUnsupported, "maxiter must be in [1, 64]");
+  TK_CHECK(prm->max_restarts >= 0, kErrInvalidArg, "max_restarts must be >= 0");
+  TK_CHECK(prm->k_trunc >= 1, kErrInvalidArg, "k_trunc must be >= 1");
+  TK_CHECK(prm->rank_cap >= 1 && prm->oversample >= 0 && prm->rank_cap + prm->oversample <= 64, kErrUnsupported,
+           "rank_cap + oversample must be in [1, 64]");
+  TK_CHECK(prm->s >= prm->maxiter && prm->s <= 256, kErrUnsupported, "sketch size must be in [maxiter, 256]");
+}
+
+OpDev<double> op_dev(const tk_kron_op* op) {
+  OpDev<double> o;
+  o.nterms = op->nterms;
+  o.alpha.assign(op->alpha, op->alpha + op->nterms);
+  for (int i = 0; i < op->nterms * op->d; ++i) o.A.push_back(op->A[i]);
+  return o;
+}
+
+void fill_info(const SolveInfo& si, tk_sgmres_info* info, int d) {
+  if (!info) return;
+  info->status = si.status;
+  info->iters_total = si.iters;
+  info->cycles = si.cycles;
+  info->true_relres = si.true_relres;
+  info->seconds = si.seconds;
+  const int nh = int(si.hist_sketched.size());
+  info->hist_len = std::min(nh, std::max(0, info->hist_cap));
+  for (int i = 0; i < info->hist_len; ++i) {
+    if (info->hist_sketched) info->hist_sketched[i] = si.hist_sketched[i];
+    if (info->hist_ranks)
+      for (int k = 0; k < TK_MAX_D; ++k) info->hist_ranks[i * TK_MAX_D + k] = k < d ? si.hist_ranks[i * d + k] : 0;
+  }
+  if (info->hist_true)
+    for (int i = 0; i < std::min<int>(int(si.hist_true.size()), info->hist_cap); ++i) info->hist_true[i] = si.hist_true[i];
+}
+
+int do_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* prm, const double* const* S,
+             const double* const* omega, tk_tucker* x, tk_sgmres_info* info, Arena& ar, hipStream_t st) {
+  TK_CHECK(b != nullptr, kErrInvalidArg, "b is NULL");
+  check_dims(b->d, b->n);
+  check_op(op, b->d, b->n);
+  check_tucker(b, "b", b->d, b->n);
+  check_params(prm);
+  TK_CHECK(S != nullptr && omega != nullptr, kErrInvalidArg, "sketch matrices missing");
+  const int d = b->d;
+  int rc = prm->rank_cap;
+  for (int k = 0; k < d; ++k) rc = std::max<int>(rc, int(b->r[k]));
+  if (prm->x0) {
+    check_tucker(prm->x0, "x0", d, b->n);
+    for (int k = 0; k < d; ++k) rc = std::max<int>(rc, int(prm->x0->r[k]));
+  }
+  TK_CHECK(rc <= 64, kErrUnsupported, "ranks above 64 are not supported by the solver");
+  Shape sh = shape_of(d, b->n, rc, prm->rank_cap, prm->oversample);
+  Seq imp;
+  TT<double> bi = alloc_tt<double>(ar, sh);
+  emit_import<double>(imp, sh, *b, bi);
+  TT<double> x0i;
+  if (prm->x0) {
+    x0i = alloc_tt<double>(ar, sh);
+    emit_import<double>(imp, sh, *prm->x0, x0i);
+  }
+  std::array<const double*, kMaxD> Sk{}, Ok{};
+  for (int k = 0; k < d; ++k) {
+    Sk[k] = S[k];
+    Ok[k] = omega[k];
+  }
+  auto solver = make_solver(ar, sh, op_dev(op), bi, solve_cfg(prm), Sk, Ok, prm->x0 ? &x0i : nullptr, st);
+  if (ar.measuring()) return 0;
+  TK_CHECK(x != nullptr, kErrInvalidArg, "x is NULL");
+  imp.run(st);
+  TT<double> xo;
+  SolveInfo si;
+  solver_run(*solver, xo, si, st);
+  export_tt(sh, xo, x, st);
+  fill_info(si, info, d);
+  return si.status;
+}
+
+// ---------------------------------------------------------------- backward
+int do_backward(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xbar, const tk_sgmres_params* prm,
+                const double* const* S, const double* const* omega, tk_tucker* lambda, double* dalpha,
+                double* const* dA, tk_sgmres_info* info, Arena& ar, hipStream_t st) {
+  TK_CHECK(x != nullptr, kErrInvalidArg, "x is NULL");
+  check_dims(x->d, x->n);
+  check_op(op, x->d, x->n);
+  check_tucker(x, "x", x->d, x->n);
+  check_params(prm);
+  TK_CHECK(S != nullptr && omega != nullptr, kErrInvalidArg, "sketch matrices missing");
+  const int d = x->d;
+  int rc = prm->rank_cap;
+  for (int k = 0; k < d; ++k) rc = std::max<int>(rc, int(x->r[k]));
+  TK_CHECK(xbar != nullptr && xbar->nblocks >= 1, kErrInvalidArg, "cotangent is empty");
+  for (int b = 0; b < xbar->nblocks; ++b) {
+    check_tucker(&xbar->blocks[b], "xbar block", d, x->n);
+    for (int k = 0; k < d; ++k) rc = std::max<int>(rc, int(xbar->blocks[b].r[k]));
+  }
+  TK_CHECK(rc <= 64, kErrUnsupported, "ranks above 64 are not supported by the solver");
+  Shape sh = shape_of(d, x->n, rc, prm->rank_cap, prm->oversample);
+  Blob blob;
+  Planner pl(ar, blob);
+  Seq pre, post;
+  // import x and the cotangent blocks, round the cotangent (FP64)
+  TT<double> xi = alloc_tt<double>(ar, sh);
+  emit_import<double>(pre, sh, *x, xi);
+  Blocks<double> xb;
+  for (int b = 0; b < xbar->nblocks; ++b) {
+    TT<double> t = alloc_tt<double>(ar, sh);
+    emit_import<double>(pre, sh, xbar->blocks[b], t);
+    xb.add(t, nullptr, xbar->coef[b]);
+  }
+  std::array<const double*, kMaxD> Sk{}, Ok{};
+  for (int k = 0; k < d; ++k) {
+    Sk[k] = S[k];
+    Ok[k] = omega[k];
+  }
+  RoundCfg rc_cfg;
+  rc_cfg.eps = 1e-2 * prm->tol;
+  TT<double> xbr = alloc_tt<double>(ar, sh);
+  plan_roundsum<double>(pre, pl, sh, xb, rc_cfg, Ok, xbr, nullptr);
+  // adjoint solve L^T lambda = xbar
+  SolveCfg scfg = solve_cfg(prm);
+  scfg.transpose = true;
+  OpDev<double> od = op_dev(op);
+  auto solver = make_solver(ar, sh, od, xbr, scfg, Sk, Ok, nullptr, st);
+  // gradient contractions, planned for both solution slots of the solver
+  double* dal = ar.alloc<double>(op->nterms);
+  Seq grad[2];
+  for (int slot = 0; slot < 2; ++slot) {
+    const TT<double> lam = solver_slot(*solver, slot);
+    Seq& q = grad[slot];
+    Blocks<double> lx = plan_apply<double>(q, pl, sh, od, xi, false);
+    std::vector<double*> P;  // P[j*d+l] = U_lam,l^T A_j^(l) U_x,l
+    plan_inner<double>(q, pl, sh, {lam}, lx, dal, -1.0, &P);
+    if (dA == nullptr) continue;
+    for (int j = 0; j < op->nterms; ++j)
+      for (int k = 0; k < d; ++k) {
+        if (op->A[j * d + k] == nullptr || dA[j * d + k] == nullptr) continue;
+        int dims[kMaxD];
+        for (int l = 0; l < d; ++l) dims[l] = sh.rc;
+        const double* cur = xi.core;
+        double* tA = ar.alloc<double>(sh.core_len());
+        double* tB = ar.alloc<double>(sh.core_len());
+        double* tgt = tA;
+        for (int l = d - 1; l >= 0; --l) {
+          if (l == k) continue;
+          plan_ttm<double>(q, pl, d, dims, l, sh.rc, cur, P[j * d + l], sh.rc, false, tgt);
+          cur = tgt;
+          tgt = (tgt == tA) ? tB : tA;
+        }
+        double* Mid = ar.alloc<double>(size_t(sh.rc) * sh.rc);
+        plan_unfold_gram<double>(q, pl, d, dims, k, lam.core, cur, Mid, sh.rc, 1.0);
+        const int n = sh.n[k];
+        double* tmp = ar.alloc<double>(size_t(n) * sh.rc);
+        plan_gemm<double>(q, pl, false, true, n, sh.rc, sh.rc, xi.U[k], n, Mid, sh.rc, tmp, n, 1.0, 0.0);
+        plan_gemm<double>(q, pl, false, true, n, n, sh.rc, tmp, n, lam.U[k], n, dA[j * d + k], n,
+                          -op->alpha[j], 0.0);
+      }
+  }
+  finish_blob(ar, blob, st);
+  if (ar.measuring()) return 0;
+  pre.run(st);
+  TT<double> lam;
+  SolveInfo si;
+  solver_run(*solver, lam, si, st);
+  grad[solver_slot_index(*solver)].run(st);
+  if (dalpha) {
+    TK_HIP(hipMemcpyAsync(dalpha, dal, sizeof(double) * op->nterms, hipMemcpyDeviceToHost, st));
+  }
+  TK_HIP(hipStreamSynchronize(st));
+  if (lambda) export_tt(sh, lam, lambda, st);
+  fill_info(si, info, d);
+  return si.status;
+}
+
+}  // namespace
+}  // namespace tk
+
+// ====================================================================== extern "C"
+using namespace tk;
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" {
+
+int tucker_apply_op(const tk_kron_op* op, const tk_tucker* x, int32_t transpose, double* const* AU, void* ws,
+                    size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TK_CHECK(ws != nullptr || ws_bytes == 0, kErrInvalidArg, "workspace pointer is NULL");
+    Arena ar(ws ? ws : reinterpret_cast<void*>(uintptr_t(1)), ws_bytes);
+    return do_apply(op, x, transpose, AU, ar, as_stream(stream));
+  });
+}
+int tucker_apply_op_workspace(const tk_kron_op* op, const tk_tucker* x, size_t* bytes) {
+  return guarded([&] {
+    Arena ar(nullptr, 0);
+    double* dummy[TK_MAX_D * 64] = {};
+    for (auto& p : dummy) p = reinterpret_cast<double*>(uintptr_t(0x1000));
+    const int r = do_apply(op, x, 0, dummy, ar, nullptr);
+    if (bytes) *bytes = ar.used();
+    return r;
+  });
+}
+
+int tucker_sketch(const tk_block_sum* x, const double* const* S, int64_t s, double* out, void* ws, size_t ws_bytes,
+                  void* stream) {
+  return guarded([&] {
+    TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
+    Arena ar(ws, ws_bytes);
+    return do_sketch(x, S, s, out, ar, as_stream(stream));
+  });
+}
+int tucker_sketch_workspace(const tk_block_sum* x, int64_t s, size_t* bytes) {
+  return guarded([&] {
+    Arena ar(nullptr, 0);
+    const double* S[TK_MAX_D] = {reinterpret_cast<const double*>(uintptr_t(0x1000)),
+                                 reinterpret_cast<const double*>(uintptr_t(0x1000)),
+                                 reinterpret_cast<const double*>(uintptr_t(0x1000)),
+                                 reinterpret_cast<const double*>(uintptr_t(0x1000))};
+    const int r = do_sketch(x, S, s, reinterpret_cast<double*>(uintptr_t(0x1000)), ar, nullptr);
+    if (bytes) *bytes = ar.used();
+    return r;
+  });
+}
+
+int tucker_rhosvd(const tk_block_sum* in, const tk_round_params* prm, const double* const* omega, tk_tucker* out,
+                  int32_t* s_out, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
+    Arena ar(ws, ws_bytes);
+    return do_rhosvd(in, prm, omega, out, s_out, ar, as_stream(stream));
+  });
+}
+int tucker_rhosvd_workspace(const tk_block_sum* in, const tk_round_params* prm, size_t* bytes) {
+  return guarded([&] {
+    Arena ar(nullptr, 0);
+    const double* om[TK_MAX_D] = {nullptr, nullptr, nullptr, nullptr};
+    const int r = do_rhosvd(in, prm, om, nullptr, nullptr, ar, nullptr);
+    if (bytes) *bytes = ar.used();
+    return r;
+  });
+}
+
+int tsgmres_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* prm, const double* const* S,
+                  const double* const* omega, tk_tucker* x, tk_sgmres_info* info, void* ws, size_t ws_bytes,
+                  void* stream) {
+  return guarded([&] {
+    TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
+    Arena ar(ws, ws_bytes);
+    return do_solve(op, b, prm, S, omega, x, info, ar, as_stream(stream));
+  });
+}
+int tsgmres_solve_workspace(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* prm, size_t* bytes) {
+  return guarded([&] {
+    Arena ar(nullptr, 0);
+    const double* dummy[TK_MAX_D] = {nullptr, nullptr, nullptr, nullptr};
+    const int r = do_solve(op, b, prm, dummy, dummy, nullptr, nullptr, ar, nullptr);
+    if (bytes) *bytes = ar.used();
+    return r;
+  });
+}
+
+int tsgmres_backward(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xbar,
+                     const tk_sgmres_params* prm, const double* const* S, const double* const* omega,
+                     tk_tucker* lambda, double* dalpha, double* const* dA, tk_sgmres_info* info, void* ws,
+                     size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
+    Arena ar(ws, ws_bytes);
+    return do_backward(op, x, xbar, prm, S, omega, lambda, dalpha, dA, info, ar, as_stream(stream));
+  });
+}
+int tsgmres_backward_workspace(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xbar,
+                               const tk_sgmres_params* prm, size_t* bytes) {
+  return guarded([&] {
+    Arena ar(nullptr, 0);
+    const double* dummy[TK_MAX_D] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<double*> dA(size_t(op ? op->nterms * op->d : 0), reinterpret_cast<double*>(uintptr_t(0x1000)));
+    const int r = do_backward(op, x, xbar, prm, dummy, dummy, nullptr, nullptr, dA.data(), nullptr, ar, nullptr);
+    if (bytes) *bytes = ar.used();
+    return r;
+  });
+}
+
+int tucker_norm(const tk_block_sum* x, double* out, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
+    Arena ar(ws, ws_bytes);
+    return do_norm(x, out, ar, as_stream(stream));
+  });
+}
+int tucker_norm_workspace(const tk_block_sum* x, size_t* bytes) {
+  return guarded([&] {
+    Arena ar(nullptr, 0);
+    const int r = do_norm(x, nullptr, ar, nullptr);
+    if (bytes) *bytes = ar.used();
+    return r;
+  });
+}
+
+const char* tk_last_error(void) { return tk::last_error(); }
+int tk_version(void) { return 100; }
+
+}  // extern "C"

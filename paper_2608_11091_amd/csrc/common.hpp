@@ -1,0 +1,133 @@
+// Shared definitions of the Tucker sGMRES HIP library (gfx950 / CDNA4).
+//
+// Data layout on the device (all buffers capacity-padded, zero beyond rank):
+//   * a core of capacity rc per mode is row-major over (i_1..i_d), mode d
+//     fastest, with strides rc^(d-1-k); entries with i_k >= r_k are zero;
+//   * a factor U_k is n_k x rc column-major (ld = n_k); columns >= r_k are zero;
+//   * ranks, sketch widths, coefficients and status flags live in device
+//     memory, so an iteration never needs the host to know a rank.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+namespace tk {
+
+constexpr int kMaxD = 4;
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- errors
+enum Status : int {
+  kOk = 0,
+  kNotConverged = 1,
+  kBreakdown = 2,
+  kRankFloor = 3,
+  kErrInvalidArg = -1,
+  kErrShape = -2,
+  kErrCapacity = -3,
+  kErrWorkspace = -4,
+  kErrHip = -5,
+  kErrNonFinite = -6,
+  kErrUnsupported = -7,
+};
+
+void set_error(const std::string& msg);
+const char* last_error();
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define TK_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw ::tk::Error{::tk::kErrHip, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define TK_CHECK(cond, code, msg)                                                 \
+  do {                                                                            \
+    if (!(cond)) throw ::tk::Error{(code), (msg)};                                \
+  } while (0)
+
+#define TK_LAUNCH_CHECK() TK_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- workspace
+// Bump allocator over the caller's workspace.  With a null base it only
+// measures, so every entry point can report its exact workspace need by
+// running its planning phase without data.
+class Arena {
+ public:
+  Arena(void* base, size_t bytes) : base_(static_cast<char*>(base)), cap_(bytes) {}
+  template <typename T>
+  T* alloc(size_t count) {
+    size_t off = (used_ + 255) & ~size_t(255);
+    used_ = off + count * sizeof(T);
+    if (base_ == nullptr) return reinterpret_cast<T*>(uintptr_t(0x1000) + off);  // measuring only
+    if (used_ > cap_) throw Error{kErrWorkspace, "workspace too small: need at least " + std::to_string(used_) + " bytes"};
+    return reinterpret_cast<T*>(base_ + off);
+  }
+  size_t used() const { return used_; }
+  bool measuring() const { return base_ == nullptr; }
+
+ private:
+  char* base_;
+  size_t cap_;
+  size_t used_ = 0;
+};
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ double shfl_xor_d(double v, int mask) {
+  return __shfl_xor(v, mask, kWave);
+}
+__device__ __forceinline__ float shfl_xor_d(float v, int mask) {
+  return __shfl_xor(v, mask, kWave);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    T o = shfl_xor_d(v, m);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Block-wide sum for blockDim.x a multiple of 64; `red` holds >= nwaves values.
+// Every thread gets the same result (fixed reduction order: deterministic).
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  T s = 0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+inline int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+}  // namespace tk

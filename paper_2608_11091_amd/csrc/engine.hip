@@ -1,0 +1,1065 @@
+// Plans of the Tucker sGMRES hot path: RoundSum (Sec. 3.1), operator apply
+// (Eq. (2)), Khatri-Rao sketch (Alg. 2), inner products and the exact norm
+// of a block sum.  See engine.hpp for the planning model.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <map>
+
+namespace tk {
+
+namespace {
+
+// ---------------------------------------------------------------- helpers
+template <typename T>
+struct GemmDesc {
+  bool ta = false, tb = false;
+  int M = 0, N = 0, K = 0, lda = 0, ldb = 0, ldc = 0;
+  double beta = 0.0;
+  std::vector<GemmTerm<T>> terms;
+  std::vector<GemmGroup<T>> groups;
+  // runtime limits (optional): number of active blocks -> groups / terms
+  const int* nb = nullptr;
+  std::function<int(int)> ngroups_of;  // active groups as a function of *nb
+  bool terms_are_blocks = false;       // clamp each group's terms to *nb
+
+  void group(T* C, const std::vector<GemmTerm<T>>& ts) {
+    GemmGroup<T> g;
+    g.C = C;
+    g.t0 = int(terms.size());
+    for (auto& t : ts) terms.push_back(t);
+    g.t1 = int(terms.size());
+    groups.push_back(g);
+  }
+  void group1(T* C, const T* A, const T* B, const double* c1 = nullptr, const double* c2 = nullptr,
+              const double* c3 = nullptr, double scale = 1.0) {
+    group(C, {GemmTerm<T>{A, B, c1, c2, c3, scale}});
+  }
+};
+
+template <typename T>
+GemmTerm<T> term(const T* A, const T* B, const double* c1 = nullptr, const double* c2 = nullptr,
+                 const double* c3 = nullptr, double scale = 1.0) {
+  return GemmTerm<T>{A, B, c1, c2, c3, scale};
+}
+
+template <typename T>
+void emit_gemm(Seq& q, Planner& pl, GemmDesc<T>&& g) {
+  if (g.groups.empty()) return;
+  const int ng = int(g.groups.size());
+  int maxt = 1;
+  for (auto& gr : g.groups) maxt = std::max(maxt, gr.t1 - gr.t0);
+  const long tiles = long(ceil_div(g.M, 64)) * ceil_div(g.N, 64) * ng;
+  const long slabs = long(maxt) * ceil_div(g.K, 16);
+  int splits = 1;
+  if (tiles < 256 && slabs >= 16) {
+    splits = int(std::min<long>(slabs / 8, std::max<long>(1, 512 / tiles)));
+    splits = std::max(1, std::min(splits, 64));
+  }
+  T* partial = splits > 1 ? pl.ar.alloc<T>(size_t(ng) * splits * g.M * g.N) : nullptr;
+  const size_t toff = pl.blob.add(g.terms), goff = pl.blob.add(g.groups);
+  Blob* bl = &pl.blob;
+  GemmLaunch<T> L;
+  L.ta = g.ta;
+  L.tb = g.tb;
+  L.M = g.M;
+  L.N = g.N;
+  L.K = g.K;
+  L.lda = g.lda;
+  L.ldb = g.ldb;
+  L.ldc = g.ldc;
+  L.beta = g.beta;
+  L.splits = splits;
+  L.partial = partial;
+  L.ngroups = ng;
+  const int* nb = g.nb;
+  auto ngf = g.ngroups_of;
+  const bool tb = g.terms_are_blocks;
+  q.steps.push_back([=](hipStream_t st) {
+    GemmLaunch<T> l = L;
+    l.terms = bl->at<GemmTerm<T>>(toff);
+    l.groups = bl->at<GemmGroup<T>>(goff);
+    if (nb) {
+      if (ngf) l.ngroups = std::min(ng, ngf(*nb));
+      if (tb) l.max_terms = *nb;
+    }
+    gemm_run(l, st);
+  });
+}
+
+template <typename X>
+size_t blob_ptrs(Blob& b, const std::vector<X>& v) {
+  return b.add(v);
+}
+
+// Y_b = X_b x_k W_b (mode-k TTM) for a batch.  X dims `dims` (row-major);
+// W_b is (newdim x dims[k]) col-major with leading dimension ldw, or, when
+// w_transposed, W_b^T is given as (dims[k] x newdim) with leading dim ldw.
+// When `sum_into` is set (k == 0 or k == d-1 only) every batch entry is
+// accumulated into sum_into with coefficient c1[b] (scaled by cscale).
+template <typename T>
+void emit_ttm(Seq& q, Planner& pl, int d, const int* dims, int k, int newdim, const std::vector<const T*>& X,
+              const std::vector<const T*>& W, int ldw, bool w_transposed, const std::vector<T*>& Y,
+              T* sum_into = nullptr, const std::vector<const double*>* c1 = nullptr, double cscale = 1.0,
+              const int* nb = nullptr) {
+  long pre = 1, post = 1;
+  for (int j = 0; j < k; ++j) pre *= dims[j];
+  for (int j = k + 1; j < d; ++j) post *= dims[j];
+  const int mid = dims[k];
+  const int nbat = int(X.size());
+  GemmDesc<T> g;
+  g.nb = nb;
+  if (post == 1) {
+    // X is (mid x pre) col-major; Y = W X  (newdim x pre)
+    g.ta = w_transposed;
+    g.tb = false;
+    g.M = newdim;
+    g.N = int(pre);
+    g.K = mid;
+    g.lda = ldw;
+    g.ldb = mid;
+    g.ldc = newdim;
+    if (sum_into) {
+      std::vector<GemmTerm<T>> ts;
+      for (int b = 0; b < nbat; ++b) ts.push_back(term<T>(W[b], X[b], c1 ? (*c1)[b] : nullptr, nullptr, nullptr, cscale));
+      g.group(sum_into, ts);
+      g.terms_are_blocks = nb != nullptr;
+    } else {
+      for (int b = 0; b < nbat; ++b) g.group1(Y[b], W[b], X[b]);
+      if (nb) g.ngroups_of = [](int n) { return n; };
+    }
+  } else {
+    // per pre-slice: X_p is (post x mid) col-major; Y_p = X_p W^T  (post x newdim)
+    g.ta = false;
+    g.tb = !w_transposed;
+    g.M = int(post);
+    g.N = newdim;
+    g.K = mid;
+    g.lda = int(post);
+    g.ldb = ldw;
+    g.ldc = int(post);
+    if (sum_into) {
+      TK_CHECK(pre == 1, kErrInvalidArg, "internal: summed TTM needs a leading mode");
+      std::vector<GemmTerm<T>> ts;
+      for (int b = 0; b < nbat; ++b) ts.push_back(term<T>(X[b], W[b], c1 ? (*c1)[b] : nullptr, nullptr, nullptr, cscale));
+      g.group(sum_into, ts);
+      g.terms_are_blocks = nb != nullptr;
+    } else {
+      for (int b = 0; b < nbat; ++b)
+        for (long p = 0; p < pre; ++p)
+          g.group1(Y[b] + size_t(p) * post * newdim, X[b] + size_t(p) * post * mid, W[b]);
+      if (nb) {
+        const long pr = pre;
+        g.ngroups_of = [pr](int n) { return int(n * pr); };
+      }
+    }
+  }
+  emit_gemm(q, pl, std::move(g));
+}
+
+// G = X_(k) Y_(k)^T (mid x mid, ld ldg) for two tensors of dims `dims`.
+template <typename T>
+void emit_unfold_gram(Seq& q, Planner& pl, int d, const int* dims, int k, const T* X, const T* Y, T* G, int ldg,
+                      double scale = 1.0) {
+  long pre = 1, post = 1;
+  for (int j = 0; j < k; ++j) pre *= dims[j];
+  for (int j = k + 1; j < d; ++j) post *= dims[j];
+  const int mid = dims[k];
+  GemmDesc<T> g;
+  g.M = mid;
+  g.N = mid;
+  g.ldc = ldg;
+  if (post == 1) {
+    g.ta = false;
+    g.tb = true;
+    g.K = int(pre);
+    g.lda = mid;
+    g.ldb = mid;
+    g.group1(G, X, Y, nullptr, nullptr, nullptr, scale);
+  } else {
+    g.ta = true;
+    g.tb = false;
+    g.K = int(post);
+    g.lda = int(post);
+    g.ldb = int(post);
+    std::vector<GemmTerm<T>> ts;
+    for (long p = 0; p < pre; ++p)
+      ts.push_back(term<T>(X + size_t(p) * post * mid, Y + size_t(p) * post * mid, nullptr, nullptr, nullptr, scale));
+    g.group(G, ts);
+  }
+  emit_gemm(q, pl, std::move(g));
+}
+
+template <typename T>
+std::vector<std::vector<int>> modes_by_n(const Shape& sh) {
+  std::map<int, std::vector<int>> m;
+  for (int k = 0; k < sh.d; ++k) m[sh.n[k]].push_back(k);
+  std::vector<std::vector<int>> out;
+  for (auto& kv : m) out.push_back(kv.second);
+  return out;
+}
+
+template <typename T>
+void emit_cast(Seq& q, const T* src, double* dst, size_t len);
+template <>
+void emit_cast<double>(Seq& q, const double* src, double* dst, size_t len) {
+  (void)q; (void)src; (void)dst; (void)len;
+}
+template <>
+void emit_cast<float>(Seq& q, const float* src, double* dst, size_t len) {
+  q.steps.push_back([=](hipStream_t st) { cast_copy<float, double>(src, dst, len, st); });
+}
+
+}  // namespace
+
+// ====================================================================== RoundSum
+template <typename T>
+RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>& in, const RoundCfg& cfg,
+                             const std::array<const T*, kMaxD>& omega, const TT<T>& out, const int* nb_active) {
+  const int d = sh.d, rc = sh.rc, sc = sh.sc(), nb = in.size();
+  TK_CHECK(nb >= 1, kErrInvalidArg, "RoundSum of an empty sum");
+  TK_CHECK(sc <= 64, kErrUnsupported, "RoundSum: rank cap + oversampling above 64");
+  Arena& ar = pl.ar;
+  Blob& blob = pl.blob;
+  Blob* bl = &blob;
+  const size_t P = size_t(ipow(rc, d - 1));       // rc^(d-1)
+  const size_t corelen = size_t(ipow(rc, d));
+  const size_t sclen = size_t(ipow(sc, d));
+
+  // --- device scalars and tables
+  double* coef = ar.alloc<double>(nb);
+  double* sumsq = ar.alloc<double>(nb);
+  double* w = ar.alloc<double>(nb);
+  int* rt = ar.alloc<int>(kMaxD);
+  int* s_dev = ar.alloc<int>(1);
+  double* total = ar.alloc<double>(1);
+  double* zthr = ar.alloc<double>(1);
+  const double zero_tol = 16.0 * (std::is_same<T, double>::value ? 1.1102230246251565e-16 : 5.9604644775390625e-08);
+  const bool own_eps = cfg.eps_dev == nullptr;
+  const double* epsd = own_eps ? ar.alloc<double>(2) : cfg.eps_dev;  // [0] eps, [1] tau
+  int* force_dev = ar.alloc<int>(kMaxD);
+  const size_t off_cptr = blob.add(in.cptr);
+  const size_t off_cscale = blob.add(in.cscale);
+  const size_t off_cores = blob.add(in.core);
+  const size_t off_ranks = blob.add(in.rank);
+  const double eps_v = cfg.eps, tau_v = cfg.tau > 0 ? cfg.tau : cfg.eps;
+  auto nbA = [nb, nb_active]() { return nb_active ? std::min(nb, *nb_active) : nb; };
+  // Host values copied to device scalars by the first step (pageable source:
+  // the copy completes before the call returns).
+  struct Params {
+    double ev[2];
+    int force[kMaxD];
+  };
+  auto hp = std::make_shared<Params>();
+  hp->ev[0] = eps_v;
+  hp->ev[1] = tau_v;
+  for (int k = 0; k < kMaxD; ++k) hp->force[k] = cfg.force_r[k];
+  bool any_force = false;
+  for (int k = 0; k < d; ++k) any_force |= cfg.force_r[k] >= 0;
+
+  q.steps.push_back([=](hipStream_t st) {
+    if (own_eps) TK_HIP(hipMemcpyAsync(const_cast<double*>(epsd), hp->ev, sizeof(hp->ev), hipMemcpyHostToDevice, st));
+    if (any_force) TK_HIP(hipMemcpyAsync(force_dev, hp->force, sizeof(hp->force), hipMemcpyHostToDevice, st));
+    gather_coef(bl->at<const double*>(off_cptr), bl->at<double>(off_cscale), nbA(), coef, st);
+    dot_batched<T>(bl->at<const T*>(off_cores), bl->at<const T*>(off_cores), corelen, nbA(), 1.0, sumsq, st);
+    block_weights(coef, sumsq, nbA(), w, st);
+    zero_threshold(w, nbA(), zero_tol, zthr, st);
+  });
+
+  // --- 1. effective-rank heuristic (Gram eigenvalues) -> sketch width
+  if (cfg.force_s < 0) {
+    for (auto& modes : modes_by_n<T>(sh)) {
+      const int n = sh.n[modes[0]];
+      if (n <= cfg.eig_max) {
+        // n-side Gram: sum_b w_b^2 U_b U_b^T
+        T* Gn = ar.alloc<T>(size_t(n) * n * modes.size());
+        T* lam = ar.alloc<T>(size_t(n) * modes.size());
+        GemmDesc<T> g;
+        g.ta = false;
+        g.tb = true;
+        g.M = n;
+        g.N = n;
+        g.K = rc;
+        g.lda = n;
+        g.ldb = n;
+        g.ldc = n;
+        g.nb = nb_active;
+        g.terms_are_blocks = nb_active != nullptr;
+        std::vector<EigTask<T>> et;
+        for (size_t i = 0; i < modes.size(); ++i) {
+          const int k = modes[i];
+          std::vector<GemmTerm<T>> ts;
+          for (int b = 0; b < nb; ++b) ts.push_back(term<T>(in.U[b][k], in.U[b][k], w + b, w + b));
+          g.group(Gn + i * size_t(n) * n, ts);
+          EigTask<T> e{};
+          e.A = Gn + i * size_t(n) * n;
+          e.lda = n;
+          e.lam = lam + i * n;
+          e.rule.kind = 1;
+          e.rule.tau = epsd + 1;
+          e.rule.delta = cfg.delta;
+          e.rule.rank_out = rt + k;
+          et.push_back(e);
+        }
+        emit_gemm(q, pl, std::move(g));
+        const size_t off_et = blob.add(et);
+        const int ne = int(et.size());
+        q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off_et), ne, n, false, st); });
+      } else {
+        // R-side Gram of the padded concatenation, compacted to the active ranks
+        const int Rp = nb * rc;
+        const int NM = cfg.eig_max;
+        double* enable = ar.alloc<double>(kMaxD);
+        int* nact = ar.alloc<int>(kMaxD);
+        T* Gp = ar.alloc<T>(size_t(Rp) * Rp * d);
+        T* Gc = ar.alloc<T>(size_t(NM) * NM * d);
+        T* lam = ar.alloc<T>(size_t(NM) * d);
+        q.steps.push_back([=](hipStream_t st) {
+          gram_prep(bl->at<const int*>(off_ranks), nbA(), d, NM, enable, nact, st);
+        });
+        GemmDesc<T> g;
+        g.ta = true;
+        g.tb = false;
+        g.M = rc;
+        g.N = rc;
+        g.K = n;
+        g.lda = n;
+        g.ldb = n;
+        g.ldc = Rp;
+        g.nb = nb_active;
+        const int nmod = int(modes.size());
+        g.ngroups_of = [nmod](int a) { return a * (a + 1) / 2 * nmod; };
+        for (int b = 0; b < nb; ++b)
+          for (int b2 = 0; b2 <= b; ++b2)
+            for (int k : modes)
+              g.group1(Gp + size_t(k) * Rp * Rp + size_t(b) * rc + size_t(b2) * rc * Rp, in.U[b][k], in.U[b2][k], w + b,
+                       w + b2, enable + k);
+        emit_gemm(q, pl, std::move(g));
+        q.steps.push_back([=](hipStream_t st) {
+          gram_compact<T>(Gp, Rp, bl->at<const int*>(off_ranks), nbA(), d, rc, nact, Gc, NM, size_t(Rp) * Rp,
+                          size_t(NM) * NM, st);
+        });
+        std::vector<EigTask<T>> et;
+        for (int k : modes) {
+          EigTask<T> e{};
+          e.A = Gc + size_t(k) * NM * NM;
+          e.lda = NM;
+          e.lam = lam + size_t(k) * NM;
+          e.ndyn = nact + k;
+          e.rule.kind = 1;
+          e.rule.tau = epsd + 1;
+          e.rule.delta = cfg.delta;
+          e.rule.rank_out = rt + k;
+          et.push_back(e);
+        }
+        const size_t off_et = blob.add(et);
+        const int ne = int(et.size());
+        q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off_et), ne, NM, false, st); });
+      }
+    }
+  }
+  {
+    const int p = sh.p, cap = sh.cap, fs = cfg.force_s;
+    q.steps.push_back([=](hipStream_t st) { sketch_width(rt, d, p, cap, fs, s_dev, st); });
+  }
+
+  // --- 2. Khatri-Rao range sketch Y_k = sum_b c_b U_bk MTTKRP(G_b; M_b, k)
+  T* Mb = ar.alloc<T>(size_t(nb) * d * rc * sc);
+  auto Mp = [&](int b, int j) { return Mb + (size_t(b) * d + j) * rc * sc; };
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    GemmDesc<T> g;
+    g.ta = true;
+    g.tb = false;
+    g.M = rc;
+    g.N = sc;
+    g.K = n;
+    g.lda = n;
+    g.ldb = n;
+    g.ldc = rc;
+    g.nb = nb_active;
+    const int nm = int(modes.size());
+    g.ngroups_of = [nm](int a) { return a * nm; };
+    for (int b = 0; b < nb; ++b)
+      for (int j : modes) g.group1(Mp(b, j), in.U[b][j], omega[j]);
+    emit_gemm(q, pl, std::move(g));
+  }
+  T* Zl = ar.alloc<T>(size_t(nb) * P * sc);
+  T* Zf = ar.alloc<T>(size_t(nb) * P * sc);
+  {
+    GemmDesc<T> g;  // Zlast_b = G_b x_d M_bd^T : (P x sc)
+    g.ta = true;
+    g.tb = false;
+    g.M = int(P);
+    g.N = sc;
+    g.K = rc;
+    g.lda = rc;
+    g.ldb = rc;
+    g.ldc = int(P);
+    g.nb = nb_active;
+    g.ngroups_of = [](int a) { return a; };
+    for (int b = 0; b < nb; ++b) g.group1(Zl + size_t(b) * P * sc, in.core[b], Mp(b, d - 1));
+    emit_gemm(q, pl, std::move(g));
+    GemmDesc<T> h;  // Zfirst_b = G_b x_1 M_b1^T : (P x sc)
+    h.ta = false;
+    h.tb = false;
+    h.M = int(P);
+    h.N = sc;
+    h.K = rc;
+    h.lda = int(P);
+    h.ldb = rc;
+    h.ldc = int(P);
+    h.nb = nb_active;
+    h.ngroups_of = [](int a) { return a; };
+    for (int b = 0; b < nb; ++b) h.group1(Zf + size_t(b) * P * sc, in.core[b], Mp(b, 0));
+    emit_gemm(q, pl, std::move(h));
+  }
+  T* Tb = ar.alloc<T>(size_t(nb) * d * rc * sc);
+  auto Tp = [&](int b, int k) { return Tb + (size_t(b) * d + k) * rc * sc; };
+  {
+    std::vector<KrpTask<T>> tasks;
+    for (int b = 0; b < nb; ++b)
+      for (int k = 0; k < d; ++k) {
+        KrpTask<T> t{};
+        t.out = Tp(b, k);
+        t.scale = 1.0;
+        t.ldo = rc;
+        if (k < d - 1) {
+          t.Z = Zl + size_t(b) * P * sc;
+          t.f = k;
+          for (int j = 0; j < d - 1; ++j) {
+            t.Mj[j] = Mp(b, j);
+            t.ldm[j] = rc;
+          }
+        } else {
+          t.Z = Zf + size_t(b) * P * sc;
+          t.f = d - 2;
+          for (int j = 0; j < d - 1; ++j) {
+            t.Mj[j] = Mp(b, j + 1);
+            t.ldm[j] = rc;
+          }
+        }
+        tasks.push_back(t);
+      }
+    const size_t off = blob.add(tasks);
+    std::vector<int> z(d - 1, rc);
+    q.steps.push_back([=](hipStream_t st) {
+      krp_reduce<T>(bl->at<KrpTask<T>>(off), nbA() * d, d - 1, z.data(), int(P), sc, st);
+    });
+  }
+  std::array<T*, kMaxD> Y{}, Uh{};
+  std::array<double*, kMaxD> Y64{}, Q64{};
+  for (int k = 0; k < d; ++k) {
+    Y[k] = ar.alloc<T>(size_t(sh.n[k]) * sc);
+    Q64[k] = ar.alloc<double>(size_t(sh.n[k]) * sc);
+    if (std::is_same<T, double>::value) {
+      Y64[k] = reinterpret_cast<double*>(Y[k]);
+      Uh[k] = reinterpret_cast<T*>(Q64[k]);
+    } else {
+      Y64[k] = ar.alloc<double>(size_t(sh.n[k]) * sc);
+      Uh[k] = ar.alloc<T>(size_t(sh.n[k]) * sc);
+    }
+  }
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    GemmDesc<T> g;
+    g.ta = false;
+    g.tb = false;
+    g.M = n;
+    g.N = sc;
+    g.K = rc;
+    g.lda = n;
+    g.ldb = rc;
+    g.ldc = n;
+    g.nb = nb_active;
+    g.terms_are_blocks = nb_active != nullptr;
+    for (int k : modes) {
+      std::vector<GemmTerm<T>> ts;
+      for (int b = 0; b < nb; ++b) ts.push_back(term<T>(in.U[b][k], Tp(b, k), coef + b));
+      g.group(Y[k], ts);
+    }
+    emit_gemm(q, pl, std::move(g));
+  }
+  // --- 3. economy QR of every Y_k (FP64)
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    std::vector<QrTask> qt;
+    for (int k : modes) {
+      emit_cast<T>(q, Y[k], Y64[k], size_t(n) * sc);
+      qt.push_back(QrTask{Y64[k], Q64[k], nullptr, nullptr});
+    }
+    const size_t off = blob.add(qt);
+    const int nt = int(qt.size());
+    q.steps.push_back([=](hipStream_t st) { qr_batched(bl->at<QrTask>(off), nt, n, sc, s_dev, st); });
+    if (!std::is_same<T, double>::value)
+      for (int k : modes) {
+        double* src = Q64[k];
+        T* dst = Uh[k];
+        const size_t len = size_t(n) * sc;
+        q.steps.push_back([=](hipStream_t st) { cast_copy<double, T>(src, dst, len, st); });
+      }
+  }
+  // --- 4. core projection C^ = sum_b c_b G_b x_k (U^_k^T U_bk)
+  T* Wb = ar.alloc<T>(size_t(nb) * d * sc * rc);
+  auto Wp = [&](int b, int k) { return Wb + (size_t(b) * d + k) * sc * rc; };
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    GemmDesc<T> g;
+    g.ta = true;
+    g.tb = false;
+    g.M = sc;
+    g.N = rc;
+    g.K = n;
+    g.lda = n;
+    g.ldb = n;
+    g.ldc = sc;
+    g.nb = nb_active;
+    const int nm = int(modes.size());
+    g.ngroups_of = [nm](int a) { return a * nm; };
+    for (int b = 0; b < nb; ++b)
+      for (int k : modes) g.group1(Wp(b, k), Uh[k], in.U[b][k]);
+    emit_gemm(q, pl, std::move(g));
+  }
+  // after the TTM of mode k (k = d-1 .. 1) the block tensor has dims
+  // (rc^k, sc^(d-k)); size the two ping-pong buffers for the largest
+  size_t tmplen = 0;
+  for (int k = 1; k < d; ++k) tmplen = std::max(tmplen, size_t(ipow(rc, k)) * size_t(ipow(sc, d - k)));
+  T* X0 = ar.alloc<T>(size_t(nb) * tmplen);
+  T* X1 = ar.alloc<T>(size_t(nb) * tmplen);
+  T* Cb[2] = {ar.alloc<T>(sclen), ar.alloc<T>(sclen)};
+  T* Bt = ar.alloc<T>(sclen);
+  {
+    int dims[kMaxD];
+    for (int j = 0; j < d; ++j) dims[j] = rc;
+    std::vector<const T*> Xs, Ws;
+    std::vector<T*> Ys;
+    std::vector<const double*> cs;
+    T* cur = nullptr;
+    // mode d-1 from the block cores
+    for (int b = 0; b < nb; ++b) {
+      Xs.push_back(in.core[b]);
+      Ws.push_back(Wp(b, d - 1));
+      Ys.push_back(X0 + size_t(b) * tmplen);
+      cs.push_back(coef + b);
+    }
+    if (d == 1) TK_CHECK(false, kErrUnsupported, "d = 1");
+    emit_ttm<T>(q, pl, d, dims, d - 1, sc, Xs, Ws, sc, false, Ys, nullptr, nullptr, 1.0, nb_active);
+    dims[d - 1] = sc;
+    cur = X0;
+    T* nxt = X1;
+    for (int k = d - 2; k >= 1; --k) {
+      Xs.clear();
+      Ws.clear();
+      Ys.clear();
+      for (int b = 0; b < nb; ++b) {
+        Xs.push_back(cur + size_t(b) * tmplen);
+        Ws.push_back(Wp(b, k));
+        Ys.push_back(nxt + size_t(b) * tmplen);
+      }
+      emit_ttm<T>(q, pl, d, dims, k, sc, Xs, Ws, sc, false, Ys, nullptr, nullptr, 1.0, nb_active);
+      dims[k] = sc;
+      std::swap(cur, nxt);
+    }
+    Xs.clear();
+    Ws.clear();
+    for (int b = 0; b < nb; ++b) {
+      Xs.push_back(cur + size_t(b) * tmplen);
+      Ws.push_back(Wp(b, 0));
+    }
+    emit_ttm<T>(q, pl, d, dims, 0, sc, Xs, Ws, sc, false, {}, Cb[0], &cs, 1.0, nb_active);
+  }
+  // --- 5. ST-HOSVD of C^ (two-pass Gram-Jacobi per mode: the second Gram of the
+  //        rotated unfolding is graded, so small singular values keep their digits)
+  {
+    // total = ||C^||_F^2
+    std::vector<const T*> pc = {Cb[0]};
+    const size_t offc = blob.add(pc);
+    q.steps.push_back([=](hipStream_t st) {
+      dot_batched<T>(bl->at<const T*>(offc), bl->at<const T*>(offc), sclen, 1, 1.0, total, st);
+    });
+  }
+  T* G1 = ar.alloc<T>(size_t(sc) * sc);
+  T* G2 = ar.alloc<T>(size_t(sc) * sc);
+  T* lam1 = ar.alloc<T>(sc);
+  T* lam2 = ar.alloc<T>(sc);
+  std::array<T*, kMaxD> V1{}, V2{}, U12{};
+  int dims[kMaxD];
+  for (int j = 0; j < d; ++j) dims[j] = sc;
+  int cb = 0;
+  for (int k = 0; k < d; ++k) {
+    V1[k] = ar.alloc<T>(size_t(sc) * sc);
+    V2[k] = ar.alloc<T>(size_t(sc) * sc);
+    U12[k] = ar.alloc<T>(size_t(sc) * sc);
+    emit_unfold_gram<T>(q, pl, d, dims, k, Cb[cb], Cb[cb], G1, sc);
+    {
+      std::vector<EigTask<T>> et(1);
+      et[0] = EigTask<T>{};
+      et[0].A = G1;
+      et[0].lda = sc;
+      et[0].lam = lam1;
+      et[0].V = V1[k];
+      const size_t off = blob.add(et);
+      q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off), 1, sc, true, st); });
+    }
+    emit_ttm<T>(q, pl, d, dims, k, sc, {Cb[cb]}, {V1[k]}, sc, true, {Bt});
+    emit_unfold_gram<T>(q, pl, d, dims, k, Bt, Bt, G2, sc);
+    {
+      std::vector<EigTask<T>> et(1);
+      et[0] = EigTask<T>{};
+      et[0].A = G2;
+      et[0].lda = sc;
+      et[0].lam = lam2;
+      et[0].V = V2[k];
+      et[0].rule.kind = 2;
+      et[0].rule.eps = epsd;
+      et[0].rule.d = d;
+      et[0].rule.cap = sh.cap;
+      et[0].rule.total = total;
+      et[0].rule.zthr = zthr;
+      et[0].rule.force = (cfg.force_r[k] >= 0) ? force_dev + k : nullptr;
+      et[0].rule.rank_out = out.rank + k;
+      const size_t off = blob.add(et);
+      q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off), 1, sc, true, st); });
+    }
+    emit_ttm<T>(q, pl, d, dims, k, sc, {Bt}, {V2[k]}, sc, true, {Cb[1 - cb]});
+    {
+      GemmDesc<T> g;
+      g.M = sc;
+      g.N = sc;
+      g.K = sc;
+      g.lda = sc;
+      g.ldb = sc;
+      g.ldc = sc;
+      g.group1(U12[k], V1[k], V2[k]);
+      emit_gemm(q, pl, std::move(g));
+    }
+    cb = 1 - cb;
+  }
+  // factors U_k = U^_k U12_k[:, :min(rc, sc)]
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    if (rc > sc)
+      for (int k : modes) {
+        T* u = out.U[k];
+        const size_t len = size_t(n) * rc;
+        q.steps.push_back([=](hipStream_t st) { fill<T>(u, len, T(0), st); });
+      }
+    GemmDesc<T> g;
+    g.M = n;
+    g.N = std::min(rc, sc);
+    g.K = sc;
+    g.lda = n;
+    g.ldb = sc;
+    g.ldc = n;
+    for (int k : modes) g.group1(out.U[k], Uh[k], U12[k]);
+    emit_gemm(q, pl, std::move(g));
+  }
+  {
+    T* src = Cb[cb];
+    T* dst = out.core;
+    int sd[kMaxD], dd[kMaxD], nn[kMaxD];
+    for (int j = 0; j < kMaxD; ++j) {
+      sd[j] = sc;
+      dd[j] = rc;
+      nn[j] = sh.n[j];
+    }
+    std::array<T*, kMaxD> U = {out.U[0], out.U[1], out.U[2], out.U[3]};
+    int* rk = out.rank;
+    q.steps.push_back([=](hipStream_t st) {
+      core_recap<T>(src, sd, nullptr, dst, dd, d, st);
+      zero_sum_fixup<T>(total, zthr, d, nn, rc, U.data(), dst, corelen, rk, st);
+    });
+  }
+  RoundSumOut<T> o;
+  o.s_dev = s_dev;
+  o.total_dev = total;
+  return o;
+}
+
+// ====================================================================== apply
+template <typename T>
+Blocks<T> plan_apply(Seq& q, Planner& pl, const Shape& sh, const OpDev<T>& op, const TT<T>& x, bool transpose,
+                     std::vector<T*>* products) {
+  const int d = sh.d, rc = sh.rc;
+  std::map<std::pair<const T*, int>, T*> prod;
+  std::vector<std::pair<const T*, int>> order;
+  for (int j = 0; j < op.nterms; ++j)
+    for (int k = 0; k < d; ++k) {
+      const T* A = op.A[j * d + k];
+      if (!A) continue;
+      auto key = std::make_pair(A, k);
+      if (prod.count(key)) continue;
+      prod[key] = pl.ar.alloc<T>(size_t(sh.n[k]) * rc);
+      order.push_back(key);
+    }
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    GemmDesc<T> g;
+    g.ta = !transpose;  // row-major A seen column-major is A^T
+    g.tb = false;
+    g.M = n;
+    g.N = rc;
+    g.K = n;
+    g.lda = n;
+    g.ldb = n;
+    g.ldc = n;
+    for (auto& key : order)
+      if (std::find(modes.begin(), modes.end(), key.second) != modes.end())
+        g.group1(prod[key], key.first, x.U[key.second]);
+    emit_gemm(q, pl, std::move(g));
+  }
+  Blocks<T> out;
+  for (int j = 0; j < op.nterms; ++j) {
+    std::array<const T*, kMaxD> U{};
+    for (int k = 0; k < d; ++k) {
+      const T* A = op.A[j * d + k];
+      U[k] = A ? prod[std::make_pair(A, k)] : x.U[k];
+    }
+    out.add(x.core, U, x.rank, nullptr, op.alpha[j]);
+  }
+  if (products)
+    for (auto& key : order) products->push_back(prod[key]);
+  return out;
+}
+
+// ====================================================================== sketch
+template <typename T>
+void plan_sketch(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>& in, const std::array<const T*, kMaxD>& S,
+                 int s, double* out) {
+  const int d = sh.d, rc = sh.rc, nb = in.size();
+  Arena& ar = pl.ar;
+  Blob* bl = &pl.blob;
+  const size_t P = size_t(ipow(rc, d - 1));
+  T* Pk = ar.alloc<T>(size_t(nb) * d * rc * s);
+  auto Pp = [&](int b, int k) { return Pk + (size_t(b) * d + k) * rc * s; };
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    GemmDesc<T> g;
+    g.ta = true;
+    g.tb = false;
+    g.M = rc;
+    g.N = s;
+    g.K = n;
+    g.lda = n;
+    g.ldb = n;
+    g.ldc = rc;
+    for (int b = 0; b < nb; ++b)
+      for (int k : modes) g.group1(Pp(b, k), in.U[b][k], S[k]);
+    emit_gemm(q, pl, std::move(g));
+  }
+  T* Z = ar.alloc<T>(size_t(nb) * P * s);
+  {
+    GemmDesc<T> g;
+    g.ta = true;
+    g.tb = false;
+    g.M = int(P);
+    g.N = s;
+    g.K = rc;
+    g.lda = rc;
+    g.ldb = rc;
+    g.ldc = int(P);
+    for (int b = 0; b < nb; ++b) g.group1(Z + size_t(b) * P * s, in.core[b], Pp(b, d - 1));
+    emit_gemm(q, pl, std::move(g));
+  }
+  T* vb = ar.alloc<T>(size_t(nb) * s);
+  std::vector<KrpTask<T>> tasks;
+  for (int b = 0; b < nb; ++b) {
+    KrpTask<T> t{};
+    t.Z = Z + size_t(b) * P * s;
+    for (int j = 0; j < d - 1; ++j) {
+      t.Mj[j] = Pp(b, j);
+      t.ldm[j] = rc;
+    }
+    t.out = vb + size_t(b) * s;
+    t.coef = in.cptr[b];
+    t.scale = in.cscale[b];
+    t.f = -1;
+    t.ldo = 1;
+    tasks.push_back(t);
+  }
+  const size_t off = pl.blob.add(tasks);
+  std::vector<int> z(d - 1, rc);
+  q.steps.push_back([=](hipStream_t st) {
+    krp_reduce<T>(bl->at<KrpTask<T>>(off), nb, d - 1, z.data(), int(P), s, st);
+    sum_vectors<T>(vb, size_t(s), nb, s, out, st);
+  });
+}
+
+// ====================================================================== inner products
+template <typename T>
+void plan_inner(Seq& q, Planner& pl, const Shape& sh, const std::vector<TT<T>>& xs, const Blocks<T>& ys, double* out,
+                double scale, std::vector<T*>* grams_out) {
+  // pairs i: (xs[i] or xs[0]) with (ys block i or ys block 0)
+  const int d = sh.d, rc = sh.rc;
+  const int np = std::max<int>(int(xs.size()), ys.size());
+  Arena& ar = pl.ar;
+  Blob* bl = &pl.blob;
+  auto X = [&](int i) { return xs.size() == 1 ? xs[0] : xs[i]; };
+  auto Yi = [&](int i) { return ys.size() == 1 ? 0 : i; };
+  T* G = ar.alloc<T>(size_t(np) * d * rc * rc);
+  auto Gp = [&](int i, int k) { return G + (size_t(i) * d + k) * rc * rc; };
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    GemmDesc<T> g;
+    g.ta = true;
+    g.tb = false;
+    g.M = rc;
+    g.N = rc;
+    g.K = n;
+    g.lda = n;
+    g.ldb = n;
+    g.ldc = rc;
+    for (int i = 0; i < np; ++i)
+      for (int k : modes) g.group1(Gp(i, k), X(i).U[k], ys.U[Yi(i)][k]);
+    emit_gemm(q, pl, std::move(g));
+  }
+  const size_t corelen = size_t(ipow(rc, d));
+  T* H0 = ar.alloc<T>(size_t(np) * corelen);
+  T* H1 = ar.alloc<T>(size_t(np) * corelen);
+  int dims[kMaxD];
+  for (int j = 0; j < d; ++j) dims[j] = rc;
+  const T* const* src = nullptr;
+  (void)src;
+  std::vector<const T*> Xs, Ws;
+  std::vector<T*> Ys;
+  for (int i = 0; i < np; ++i) {
+    Xs.push_back(ys.core[Yi(i)]);
+    Ws.push_back(Gp(i, d - 1));
+    Ys.push_back(H0 + size_t(i) * corelen);
+  }
+  emit_ttm<T>(q, pl, d, dims, d - 1, rc, Xs, Ws, rc, false, Ys);
+  T* cur = H0;
+  T* nxt = H1;
+  for (int k = d - 2; k >= 0; --k) {
+    Xs.clear();
+    Ws.clear();
+    Ys.clear();
+    for (int i = 0; i < np; ++i) {
+      Xs.push_back(cur + size_t(i) * corelen);
+      Ws.push_back(Gp(i, k));
+      Ys.push_back(nxt + size_t(i) * corelen);
+    }
+    emit_ttm<T>(q, pl, d, dims, k, rc, Xs, Ws, rc, false, Ys);
+    std::swap(cur, nxt);
+  }
+  std::vector<const T*> a, b;
+  for (int i = 0; i < np; ++i) {
+    a.push_back(X(i).core);
+    b.push_back(cur + size_t(i) * corelen);
+  }
+  const size_t oa = pl.blob.add(a), ob = pl.blob.add(b);
+  q.steps.push_back([=](hipStream_t st) {
+    dot_batched<T>(bl->at<const T*>(oa), bl->at<const T*>(ob), corelen, np, scale, out, st);
+  });
+  if (grams_out)
+    for (int i = 0; i < np; ++i)
+      for (int k = 0; k < d; ++k) grams_out->push_back(Gp(i, k));
+}
+
+// ====================================================================== exact norm
+void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>& in, double* out_norm2) {
+  const int d = sh.d, rc = sh.rc, nb = in.size();
+  Arena& ar = pl.ar;
+  Blob* bl = &pl.blob;
+  // distinct factors per mode (first appearance order)
+  // The QR of each distinct factor uses its owner's rank as the active column
+  // count: padding columns must give zero basis vectors, not unit vectors that
+  // would break the orthonormality of the concatenated basis.
+  std::vector<std::vector<const double*>> fac(d);
+  std::vector<std::vector<const int*>> facr(d);
+  std::vector<std::vector<int>> idx(nb, std::vector<int>(d));
+  int m = 1;
+  for (int k = 0; k < d; ++k) {
+    for (int b = 0; b < nb; ++b) {
+      auto it = std::find(fac[k].begin(), fac[k].end(), in.U[b][k]);
+      if (it == fac[k].end()) {
+        fac[k].push_back(in.U[b][k]);
+        facr[k].push_back(in.rank[b] + k);
+        idx[b][k] = int(fac[k].size()) - 1;
+      } else {
+        idx[b][k] = int(it - fac[k].begin());
+      }
+    }
+    m = std::max(m, int(fac[k].size()));
+  }
+  TK_CHECK(rc <= 64, kErrUnsupported, "exact norm: rank capacity above 64");
+  const int Md = m * rc;
+  std::vector<double*> Qk(d), Rk(d);
+  double* Xt = ar.alloc<double>(size_t(*std::max_element(sh.n, sh.n + d)) * rc);
+  double* Ct = ar.alloc<double>(size_t(Md) * rc);
+  double* Rt = ar.alloc<double>(size_t(rc) * rc);
+  double* coef = ar.alloc<double>(nb);
+  const size_t off_cptr = pl.blob.add(in.cptr), off_cs = pl.blob.add(in.cscale);
+  q.steps.push_back([=](hipStream_t st) {
+    gather_coef(bl->at<const double*>(off_cptr), bl->at<double>(off_cs), nb, coef, st);
+  });
+  for (int k = 0; k < d; ++k) {
+    const int n = sh.n[k];
+    Qk[k] = ar.alloc<double>(size_t(n) * Md);
+    Rk[k] = ar.alloc<double>(size_t(Md) * Md);
+    double* R = Rk[k];
+    double* Q = Qk[k];
+    q.steps.push_back([=](hipStream_t st) { fill<double>(R, size_t(Md) * Md, 0.0, st); });
+    for (int i = 0; i < int(fac[k].size()); ++i) {
+      const double* F = fac[k][i];
+      double* Rblk = R + size_t(i) * rc * Md;  // column block i
+      if (i > 0) {
+        const int Kq = i * rc;
+        {  // C1 = Q^T F -> R[0:Kq, block i]
+          GemmDesc<double> g;
+          g.ta = true;
+          g.M = Kq;
+          g.N = rc;
+          g.K = n;
+          g.lda = n;
+          g.ldb = n;
+          g.ldc = Md;
+          g.group1(Rblk, Q, F);
+          emit_gemm(q, pl, std::move(g));
+        }
+        q.steps.push_back([=](hipStream_t st) { mat_recap<double>(F, n, n, rc, Xt, n, n, rc, st); });
+        {  // X -= Q C1
+          GemmDesc<double> g;
+          g.M = n;
+          g.N = rc;
+          g.K = Kq;
+          g.lda = n;
+          g.ldb = Md;
+          g.ldc = n;
+          g.beta = 1.0;
+          g.group1(Xt, Q, Rblk, nullptr, nullptr, nullptr, -1.0);
+          emit_gemm(q, pl, std::move(g));
+        }
+        {  // C2 = Q^T X
+          GemmDesc<double> g;
+          g.ta = true;
+          g.M = Kq;
+          g.N = rc;
+          g.K = n;
+          g.lda = n;
+          g.ldb = n;
+          g.ldc = Md;
+          g.group1(Ct, Q, Xt);
+          emit_gemm(q, pl, std::move(g));
+        }
+        {  // X -= Q C2
+          GemmDesc<double> g;
+          g.M = n;
+          g.N = rc;
+          g.K = Kq;
+          g.lda = n;
+          g.ldb = Md;
+          g.ldc = n;
+          g.beta = 1.0;
+          g.group1(Xt, Q, Ct, nullptr, nullptr, nullptr, -1.0);
+          emit_gemm(q, pl, std::move(g));
+        }
+        q.steps.push_back([=](hipStream_t st) { mat_axpy<double>(Ct, Md, Rblk, Md, Kq, rc, st); });
+      } else {
+        q.steps.push_back([=](hipStream_t st) { mat_recap<double>(F, n, n, rc, Xt, n, n, rc, st); });
+      }
+      std::vector<QrTask> qt = {QrTask{Xt, Q + size_t(i) * rc * n, Rt, facr[k][i]}};
+      const size_t off = pl.blob.add(qt);
+      double* Rdiag = Rblk + size_t(i) * rc;
+      q.steps.push_back([=](hipStream_t st) {
+        qr_batched(bl->at<QrTask>(off), 1, n, rc, nullptr, st);
+        mat_recap<double>(Rt, rc, rc, rc, Rdiag, Md, rc, rc, st);
+      });
+    }
+  }
+  // core = sum_b c_b G_b x_k R_k[:, block(b, k)]   (Md^d)
+  const size_t tl = size_t(rc) * size_t(ipow(Md, d - 1));
+  double* T0 = ar.alloc<double>(size_t(nb) * tl);
+  double* T1 = ar.alloc<double>(size_t(nb) * tl);
+  double* core = ar.alloc<double>(size_t(ipow(Md, d)));
+  int dims[kMaxD];
+  for (int j = 0; j < d; ++j) dims[j] = rc;
+  auto W = [&](int b, int k) { return (const double*)(Rk[k] + size_t(idx[b][k]) * rc * Md); };
+  std::vector<const double*> Xs, Ws;
+  std::vector<double*> Ys;
+  std::vector<const double*> cs;
+  for (int b = 0; b < nb; ++b) {
+    Xs.push_back(in.core[b]);
+    Ws.push_back(W(b, d - 1));
+    Ys.push_back(T0 + size_t(b) * tl);
+    cs.push_back(coef + b);
+  }
+  emit_ttm<double>(q, pl, d, dims, d - 1, Md, Xs, Ws, Md, false, Ys);
+  dims[d - 1] = Md;
+  double* cur = T0;
+  double* nxt = T1;
+  for (int k = d - 2; k >= 1; --k) {
+    Xs.clear();
+    Ws.clear();
+    Ys.clear();
+    for (int b = 0; b < nb; ++b) {
+      Xs.push_back(cur + size_t(b) * tl);
+      Ws.push_back(W(b, k));
+      Ys.push_back(nxt + size_t(b) * tl);
+    }
+    emit_ttm<double>(q, pl, d, dims, k, Md, Xs, Ws, Md, false, Ys);
+    dims[k] = Md;
+    std::swap(cur, nxt);
+  }
+  Xs.clear();
+  Ws.clear();
+  for (int b = 0; b < nb; ++b) {
+    Xs.push_back(cur + size_t(b) * tl);
+    Ws.push_back(W(b, 0));
+  }
+  emit_ttm<double>(q, pl, d, dims, 0, Md, Xs, Ws, Md, false, {}, core, &cs);
+  const size_t corelen = size_t(ipow(Md, d));
+  std::vector<const double*> pc = {core};
+  const size_t offc = pl.blob.add(pc);
+  q.steps.push_back([=](hipStream_t st) {
+    dot_batched<double>(bl->at<const double*>(offc), bl->at<const double*>(offc), corelen, 1, 1.0, out_norm2, st);
+  });
+}
+
+template <typename T>
+void plan_ttm(Seq& q, Planner& pl, int d, const int* dims, int k, int newdim, const T* X, const T* W, int ldw,
+              bool w_transposed, T* Y) {
+  emit_ttm<T>(q, pl, d, dims, k, newdim, {X}, {W}, ldw, w_transposed, {Y});
+}
+
+template <typename T>
+void plan_unfold_gram(Seq& q, Planner& pl, int d, const int* dims, int k, const T* X, const T* Y, T* G, int ldg,
+                      double scale) {
+  emit_unfold_gram<T>(q, pl, d, dims, k, X, Y, G, ldg, scale);
+}
+
+template <typename T>
+void plan_gemm(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int K, const T* A, int lda, const T* B, int ldb,
+               T* C, int ldc, double alpha, double beta) {
+  GemmDesc<T> g;
+  g.ta = ta;
+  g.tb = tb;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.beta = beta;
+  g.group1(C, A, B, nullptr, nullptr, nullptr, alpha);
+  emit_gemm(q, pl, std::move(g));
+}
+
+#define TK_INST(T)                                                                                             \
+  template void plan_ttm<T>(Seq&, Planner&, int, const int*, int, int, const T*, const T*, int, bool, T*);     \
+  template void plan_unfold_gram<T>(Seq&, Planner&, int, const int*, int, const T*, const T*, T*, int, double); \
+  template void plan_gemm<T>(Seq&, Planner&, bool, bool, int, int, int, const T*, int, const T*, int, T*, int,   \
+                             double, double);                                                                  \
+  template RoundSumOut<T> plan_roundsum<T>(Seq&, Planner&, const Shape&, const Blocks<T>&, const RoundCfg&,   \
+                                           const std::array<const T*, kMaxD>&, const TT<T>&, const int*);      \
+  template Blocks<T> plan_apply<T>(Seq&, Planner&, const Shape&, const OpDev<T>&, const TT<T>&, bool,         \
+                                   std::vector<T*>*);                                                          \
+  template void plan_sketch<T>(Seq&, Planner&, const Shape&, const Blocks<T>&, const std::array<const T*, kMaxD>&, \
+                               int, double*);                                                                  \
+  template void plan_inner<T>(Seq&, Planner&, const Shape&, const std::vector<TT<T>>&, const Blocks<T>&,      \
+                              double*, double, std::vector<T*>*);
+TK_INST(double)
+TK_INST(float)
+#undef TK_INST
+
+}  // namespace tk

@@ -1,0 +1,187 @@
+// Grouped GEMM kernel on MFMA (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).
+//
+// Tile: 64 x 64 outputs per workgroup of 256 threads (4 waves in a 2 x 2
+// arrangement), each wave owning a 32 x 32 sub-tile = 2 x 2 MFMA 16x16
+// accumulators so four independent MFMA chains hide the pipeline latency.
+// K is staged through LDS in slabs of 16 with global loads coalesced along
+// the contiguous dimension of each operand; the alpha of a term is folded
+// into the A slab while it is staged.
+#include "gemm.hpp"
+
+namespace tk {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef d4 type; static constexpr bool f64 = true; };
+template <> struct Acc<float> { typedef f4 type; static constexpr bool f64 = false; };
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+
+template <typename T, bool TA, bool TB>
+__global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, int ldb, int ldc,
+                                                  const GemmTerm<T>* __restrict__ terms,
+                                                  const GemmGroup<T>* __restrict__ groups, double beta,
+                                                  int splits, T* __restrict__ partial, int max_terms) {
+  __shared__ T As[BK][BM + 1];
+  __shared__ T Bs[BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int wm = wid & 1, wn = wid >> 1;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int g = blockIdx.z / splits;
+  const int sp = blockIdx.z % splits;
+  const GemmGroup<T> grp = groups[g];
+
+  typedef typename Acc<T>::type AT;
+  AT acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
+
+  // The (term, K-slab) iteration space of the group is split evenly over
+  // `splits` workgroups; each sums its slabs in order.
+  const int t1 = min(grp.t1, grp.t0 + max_terms);
+  const int nterm = max(0, t1 - grp.t0);
+  const int nks = (K + BK - 1) / BK;
+  const int total = nterm * nks;
+  const int per = (total + splits - 1) / splits;
+  const int sb = sp * per, se = min(total, sb + per);
+  int cur = -1;
+  T alpha = T(0);
+  const T* Ap = nullptr;
+  const T* Bp = nullptr;
+  for (int slab = sb; slab < se; ++slab) {
+    const int t = grp.t0 + slab / nks;
+    const int k0 = (slab % nks) * BK;
+    if (t != cur) {
+      const GemmTerm<T> tm = terms[t];
+      double al = tm.scale;
+      if (tm.c1) al *= *tm.c1;
+      if (tm.c2) al *= *tm.c2;
+      if (tm.c3) al *= *tm.c3;
+      alpha = T(al);
+      Ap = tm.A;
+      Bp = tm.B;
+      cur = t;
+    }
+    if (alpha == T(0)) continue;
+    // stage op(A)[m0:m0+BM, k0:k0+BK] -> As[k][m]
+#pragma unroll
+    for (int i = 0; i < (BM * BK) / NT; ++i) {
+      int m, k;
+      if (!TA) { m = tid & 63; k = (tid >> 6) + 4 * i; }
+      else { k = tid & 15; m = (tid >> 4) + 16 * i; }
+      const int gm = m0 + m, gk = k0 + k;
+      T v = T(0);
+      if (gm < M && gk < K) v = TA ? Ap[gk + (size_t)gm * lda] : Ap[gm + (size_t)gk * lda];
+      As[k][m] = v * alpha;
+    }
+    // stage op(B)[k0:k0+BK, n0:n0+BN] -> Bs[k][n]
+#pragma unroll
+    for (int i = 0; i < (BN * BK) / NT; ++i) {
+      int n, k;
+      if (!TB) { k = tid & 15; n = (tid >> 4) + 16 * i; }
+      else { n = tid & 63; k = (tid >> 6) + 4 * i; }
+      const int gn = n0 + n, gk = k0 + k;
+      T v = T(0);
+      if (gn < N && gk < K) v = TB ? Bp[gn + (size_t)gk * ldb] : Bp[gk + (size_t)gn * ldb];
+      Bs[k][n] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      T a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[kr][wm * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+
+  // Accumulator layout of a 16x16 tile (measured on gfx950): for FP32, D[r][c]
+  // sits in lane c + 16*(r/4), element r%4; for FP64 in lane c + 16*(r%4),
+  // element r/4.
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r16 = Acc<T>::f64 ? 4 * v + (lane >> 4) : 4 * (lane >> 4) + v;
+        const int row = m0 + wm * 32 + i * 16 + r16;
+        const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          if (splits == 1) {
+            T* c = grp.C + row + (size_t)col * ldc;
+            *c = (beta == 0.0) ? acc[i][j][v] : T(beta) * (*c) + acc[i][j][v];
+          } else {
+            partial[((size_t)blockIdx.z * N + col) * M + row] = acc[i][j][v];
+          }
+        }
+      }
+}
+
+template <typename T>
+__global__ void splitk_reduce(int M, int N, int ldc, const GemmGroup<T>* __restrict__ groups, double beta,
+                              int splits, const T* __restrict__ partial) {
+  const int g = blockIdx.y;
+  const size_t MN = (size_t)M * N;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < MN; e += (size_t)gridDim.x * blockDim.x) {
+    T s = T(0);
+    for (int sp = 0; sp < splits; ++sp) s += partial[((size_t)g * splits + sp) * MN + e];
+    const int row = int(e % M), col = int(e / M);
+    T* c = groups[g].C + row + (size_t)col * ldc;
+    *c = (beta == 0.0) ? s : T(beta) * (*c) + s;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void gemm_run(const GemmLaunch<T>& g, hipStream_t st) {
+  if (g.ngroups <= 0 || g.M <= 0 || g.N <= 0) return;
+  dim3 grid(ceil_div(g.M, BM), ceil_div(g.N, BN), g.ngroups * g.splits);
+  T* part = g.splits > 1 ? g.partial : nullptr;
+#define TK_GEMM_CASE(TA, TB)                                                                          \
+  if (g.ta == TA && g.tb == TB)                                                                       \
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB>), grid, dim3(NT), 0, st, g.M, g.N, g.K, g.lda, g.ldb, g.ldc, \
+                       g.terms, g.groups, g.beta, g.splits, part, g.max_terms);
+  TK_GEMM_CASE(false, false)
+  TK_GEMM_CASE(false, true)
+  TK_GEMM_CASE(true, false)
+  TK_GEMM_CASE(true, true)
+#undef TK_GEMM_CASE
+  TK_LAUNCH_CHECK();
+  if (g.splits > 1) {
+    const size_t MN = (size_t)g.M * g.N;
+    dim3 rg((unsigned)std::min<size_t>((MN + 255) / 256, 64), g.ngroups);
+    hipLaunchKernelGGL((splitk_reduce<T>), rg, dim3(256), 0, st, g.M, g.N, g.ldc, g.groups, g.beta, g.splits, part);
+    TK_LAUNCH_CHECK();
+  }
+}
+
+template void gemm_run<double>(const GemmLaunch<double>&, hipStream_t);
+template void gemm_run<float>(const GemmLaunch<float>&, hipStream_t);
+
+}  // namespace tk

@@ -1,0 +1,164 @@
+// Launchers of the non-GEMM kernels of the Tucker sGMRES hot path.
+#pragma once
+
+#include "common.hpp"
+
+namespace tk {
+
+// ---- Khatri-Rao reductions (MTTKRP tail and Khatri-Rao sketch) -------------
+// Z is a P x S column-major matrix whose rows are a row-major multi-index over
+// m modes of sizes z[0..m-1].  For free position f (0 <= f < m) it computes
+//   out[i_f + l * ldo] = sum_{i_j, j != f} Z[(i), l] * prod_{j != f} M_j[i_j, l]
+// and for f < 0 the full contraction
+//   out[l * ldo] = sum_{(i)} Z[(i), l] * prod_j M_j[i_j, l].
+// Result = scale * (*coef) * value, added to out when accumulate != 0.
+template <typename T>
+struct KrpTask {
+  const T* Z;
+  const T* Mj[kMaxD];
+  int ldm[kMaxD];
+  T* out;
+  const double* coef;
+  double scale;
+  int accumulate;
+  int f;    // free position (or -1 for the full contraction)
+  int ldo;  // leading dimension of out (stride between columns l)
+};
+// Mode sizes z[0..m-1] are uniform across the tasks of one launch.
+template <typename T>
+void krp_reduce(const KrpTask<T>* tasks_d, int ntasks, int m, const int* z, int P, int S, hipStream_t st);
+
+// ---- reductions over flat vectors --------------------------------------------
+// out[i] = sum_e x_i[e]^2 for i < n (x_i = base + i * stride), deterministic order.
+template <typename T>
+void sumsq_batched(const T* base, size_t stride, size_t len, int n, double* out, hipStream_t st);
+// out[i] = |coef[i]| * sqrt(sumsq[i]) (RoundSum energy weights).
+void block_weights(const double* coef, const double* sumsq, int n, double* w, hipStream_t st);
+// out[i] = scale_i * sum_e x_i[e] * y_i[e]; x_i = xs[i], y_i = ys[i] (device pointer tables).
+template <typename T>
+void dot_batched(const T* const* xs, const T* const* ys, size_t len, int n, double scale, double* out,
+                 hipStream_t st);
+
+// ---- elementwise --------------------------------------------------------------
+// y = alpha * x with alpha = scale * (*num) / (*den) (num/den optional device scalars).
+template <typename T>
+void scale_copy(const T* x, T* y, size_t len, double scale, const double* num, const double* den,
+                hipStream_t st);
+template <typename T>
+void fill(T* y, size_t len, T v, hipStream_t st);
+template <typename A, typename B>
+void cast_copy(const A* x, B* y, size_t len, hipStream_t st);
+// Copy a d-way core between capacity layouts: src has layout dims sd[] of
+// which the leading sv[] are valid, dst has layout dims dd[]; dst entries
+// outside the valid region are zero.
+template <typename T>
+void core_recap(const T* src, const int* sd, const int* sv, T* dst, const int* dd, int d, hipStream_t st);
+// Copy the leading rows x cols of a column-major matrix (zero-filling dst beyond src).
+template <typename T>
+void mat_recap(const T* src, int ld_src, int rows_src, int cols_src, T* dst, int ld_dst, int rows_dst,
+               int cols_dst, hipStream_t st);
+
+// ---- Householder QR (one workgroup per matrix, rows in registers) ----------
+// Y: n x cap col-major (ld n).  Active columns m = min(*m_dev (or cap), n).
+// Writes Q (n x cap, zero columns >= m) and optionally R (cap x cap, col-major,
+// upper triangle of the m x m factor, zero elsewhere).  n <= 512, cap <= 64.
+struct QrTask {
+  const double* Y;
+  double* Q;
+  double* R;
+  const int* m;  // optional per-task active column count (overrides m_dev)
+};
+void qr_batched(const QrTask* tasks_d, int ntasks, int n, int cap, const int* m_dev, hipStream_t st);
+
+// ---- symmetric Jacobi eigensolver (one workgroup per matrix) ---------------
+// A: N x N symmetric (lower triangle read, col-major, ld lda).  Eigenvalues
+// sorted descending -> lam (N); eigenvectors -> V (N x N col-major, ld N) when
+// V != nullptr (N <= 64).  Rank rule (optional, see EigRule).
+struct EigRule {
+  int kind;            // 0: none; 1: effective rank (RoundSum heuristic); 2: ST-HOSVD truncation
+  const double* tau;   // kind 1: device energy threshold tau (tail <= tau^2 * total)
+  double delta;        // kind 1: eigenvalues <= delta * lambda_max count as zero
+  const double* eps;   // kind 2: device tolerance; threshold eps^2 * (*total) / d
+  int d;               // kind 2
+  int cap;             // kind 2: rank cap
+  const double* total; // kind 2: ||C||_F^2 of the projected core
+  const double* zthr;  // kind 2: total <= *zthr means a numerically zero sum (rank 1)
+  const int* force;    // kind 2: forced rank (nullptr / negative = none)
+  int* rank_out;       // resulting rank
+};
+template <typename T>
+struct EigTask {
+  const T* A;
+  int lda;
+  T* lam;
+  T* V;          // eigenvectors (ld = launch N); for rule kind 2 columns >= rank are zeroed
+  const int* ndyn; // optional device size (< launch N); negative: skip, rank_out = -1
+  EigRule rule;
+};
+template <typename T>
+void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipStream_t st);
+
+// Per mode k: R_k = sum_b rank_b[k]; enable[k] = (R_k <= rmax); nact[k] = R_k or -1.
+// Then the padded Gram (blocks of rc rows/cols) is compacted to its R_k x R_k
+// active part (ld = ldc) for every mode with enable[k] = 1.
+void gram_prep(const int* const* ranks, int nb, int d, int rmax, double* enable, int* nact, hipStream_t st);
+template <typename T>
+void gram_compact(const T* padded, int ldp, const int* const* ranks, int nb, int d, int rc, const int* nact,
+                  T* compact, int ldc, size_t mode_stride_p, size_t mode_stride_c, hipStream_t st);
+
+// s_r = min(max_k (rt_k + p), cap + p), or *force when force >= 0; rt_k < 0 = skipped.
+void sketch_width(const int* rt, int d, int p, int cap, int force, int* s_out, hipStream_t st);
+
+// ---- small bookkeeping kernels ------------------------------------------------
+// coef[b] = cscale[b] * (cptr[b] ? *cptr[b] : 1) for b < *nb (or nb_static).
+void gather_coef(const double* const* cptr, const double* cscale, int nb, double* coef, hipStream_t st);
+// If *total <= *zthr: ranks = 1, factor columns = e_1, core zero (capacity rc layout).
+template <typename T>
+void zero_sum_fixup(const double* total, const double* zthr, int d, const int* n, int rc, T* const* U, T* core,
+                    size_t core_len, int* rank, hipStream_t st);
+// zthr = (tol * sum_{b < nb} w[b])^2.
+void zero_threshold(const double* w, int nb, double tol, double* zthr, hipStream_t st);
+// Y[:, :] += X[:, :] (rows x cols, col-major with their own leading dims).
+template <typename T>
+void mat_axpy(const T* X, int ldx, T* Y, int ldy, int rows, int cols, hipStream_t st);
+// out[l] = sum_b base[b * stride + l] (fixed order), as double.
+template <typename T>
+void sum_vectors(const T* base, size_t stride, int nb, int len, double* out, hipStream_t st);
+// Copy n ints.
+void copy_ints(const int* src, int* dst, int n, hipStream_t st);
+// dst[i] = sqrt(src[i]) for i < n.
+void vec_sqrt(const double* src, double* dst, int n, hipStream_t st);
+// Per-iteration status: omega = sqrt(sumsq[1]), ||W|| = sqrt(sumsq[0]); breakdown when
+// omega <= bd_tol * ||W||; packs LS flags, residual and the ranks of the new basis tensor.
+struct IterStatus {
+  int breakdown_ls;
+  int converged;
+  int breakdown_w;
+  int pad;
+  int rank[kMaxD];
+  double res;
+  double omega;
+};
+void iter_status(const double* sumsq2, const int* ls_flags, const double* res_k, const int* rank, int d,
+                 double bd_tol, double* omega, IterStatus* out, hipStream_t st);
+
+// ---- sketched least squares, one column at a time --------------------------
+struct LsState {
+  const double* Mcol;  // s x kmax sketched columns (col-major, ld s)
+  const double* bs;    // s
+  double* Hv;          // s x kmax Householder vectors
+  double* tau;         // kmax
+  double* R;           // kmax x kmax
+  double* qtb;         // s
+  double* y;           // kmax
+  double* res;         // relative sketched residual after each column (kmax)
+  double* nrmM2;       // running ||M||_F^2
+  int* flags;          // [0] breakdown, [1] converged
+  double beta_s_inv;   // not used when bs_norm is given
+  const double* bs_norm; // device ||b_s||
+};
+void ls_add_column(const LsState& st_, int s, int kmax, int k, double conv_tol, double breakdown_tol,
+                   hipStream_t st);
+void ls_init(const LsState& st_, int s, hipStream_t st);
+
+}  // namespace tk

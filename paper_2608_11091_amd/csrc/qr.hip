@@ -1,0 +1,164 @@
+// Householder QR of tall-skinny FP64 matrices, one workgroup per matrix.
+//
+// Thread t owns row t of the n x m matrix (n <= 512, m <= 64) in registers.
+// Step j forms the reflector of column j (a block reduction of the column
+// tail), then the row vector w = v^T A[:, j+1:] is reduced with a wave-level
+// reduce-scatter (each lane ends with one column's wave partial, 63
+// shuffles per wave) followed by an 8-way LDS sum in fixed order.  Q is then
+// formed in place by backward accumulation of the reflectors.  Everything
+// is deterministic: no atomics, fixed reduction trees.
+#include "kernels.hpp"
+
+namespace tk {
+
+namespace {
+
+constexpr int QR_NT = 512;
+constexpr int QR_MC = 64;
+constexpr int QR_NW = QR_NT / kWave;
+
+// Sums p[c] over the workgroup for every c < 64 (p computed by `term(c)`),
+// result in wv[c].  Uses red[QR_NW][64].
+template <typename F>
+__device__ __forceinline__ void column_sums(F term, double (*red)[QR_MC], double* wv) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  double p[32];
+  {
+    const bool up = lane & 32;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const double lo = term(i), hi = term(i + 32);
+      const double send = up ? lo : hi, keep = up ? hi : lo;
+      p[i] = keep + __shfl_xor(send, 32, 64);
+    }
+  }
+#pragma unroll
+  for (int h = 16; h >= 1; h >>= 1) {
+    const bool up = lane & h;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const double lo = p[i], hi = p[i + h];
+      const double send = up ? lo : hi, keep = up ? hi : lo;
+      p[i] = keep + __shfl_xor(send, h, 64);
+    }
+  }
+  red[w][lane] = p[0];  // wave partial of column `lane`
+  __syncthreads();
+  if (threadIdx.x < QR_MC) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < QR_NW; ++q) s += red[q][threadIdx.x];
+    wv[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(QR_NT) void qr_kernel(const QrTask* __restrict__ tasks, int n, int cap,
+                                                   const int* __restrict__ m_dev) {
+  __shared__ double red[QR_NW][QR_MC];
+  __shared__ double wv[QR_MC];
+  __shared__ double tau_s[QR_MC];
+  __shared__ double r2[2][QR_NW];
+  const QrTask tk_ = tasks[blockIdx.x];
+  const int row = threadIdx.x;
+  const int lane = row & 63, wid = row >> 6;
+  int m = tk_.m ? *tk_.m : (m_dev ? *m_dev : cap);
+  m = min(m, cap);
+  m = min(m, n);
+
+  double a[QR_MC];
+#pragma unroll
+  for (int c = 0; c < QR_MC; ++c) a[c] = (row < n && c < m) ? tk_.Y[row + (size_t)c * n] : 0.0;
+
+  // ---------------- factorisation
+  for (int j = 0; j < m; ++j) {
+    double xj = 0.0;
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c) xj = (c == j) ? a[c] : xj;
+    // alpha = A[j][j], xnorm^2 = sum_{i>j} A[i][j]^2, one two-value block reduction
+    double va = (row == j) ? xj : 0.0;
+    double vn = (row > j) ? xj * xj : 0.0;
+    va = wave_sum(va);
+    vn = wave_sum(vn);
+    if (lane == 0) {
+      r2[0][wid] = va;
+      r2[1][wid] = vn;
+    }
+    __syncthreads();
+    double alpha = 0.0, xnorm2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < QR_NW; ++q) {
+      alpha += r2[0][q];
+      xnorm2 += r2[1][q];
+    }
+    double beta, tau, scal;
+    if (xnorm2 == 0.0) {
+      beta = alpha;
+      tau = 0.0;
+      scal = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    const double vr = (row == j) ? 1.0 : (row > j ? xj * scal : 0.0);
+    if (tau != 0.0) {
+      column_sums([&](int c) { return c > j ? vr * a[c] : 0.0; }, red, wv);
+      const double tv = tau * vr;
+#pragma unroll
+      for (int c = 0; c < QR_MC; ++c)
+        if (c > j) a[c] -= tv * wv[c];
+    } else {
+      __syncthreads();  // keep r2 reads ahead of the next step's writes
+    }
+    const double nj = (row == j) ? beta : (row > j ? vr : xj);
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c) a[c] = (c == j) ? nj : a[c];
+    if (row == 0) tau_s[j] = tau;
+  }
+  __syncthreads();
+
+  // ---------------- R (upper triangle of the leading m x m block)
+  if (tk_.R != nullptr && row < cap) {
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c)
+      if (c < cap) tk_.R[row + (size_t)c * cap] = (row < m && c < m && c >= row) ? a[c] : 0.0;
+  }
+
+  // ---------------- Q, backward accumulation in place (LAPACK org2r order)
+  for (int j = m - 1; j >= 0; --j) {
+    const double tau = tau_s[j];
+    double xj = 0.0;
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c) xj = (c == j) ? a[c] : xj;
+    const double vr = (row == j) ? 1.0 : (row > j ? xj : 0.0);
+    if (j < m - 1 && tau != 0.0) {
+      column_sums([&](int c) { return (c > j && c < m) ? vr * a[c] : 0.0; }, red, wv);
+      const double tv = tau * vr;
+#pragma unroll
+      for (int c = 0; c < QR_MC; ++c)
+        if (c > j && c < m) a[c] -= tv * wv[c];
+    }
+    const double nj = (row == j) ? 1.0 - tau : (row > j ? -tau * xj : 0.0);
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c) a[c] = (c == j) ? nj : a[c];
+  }
+  if (row < n) {
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c)
+      if (c < cap) tk_.Q[row + (size_t)c * n] = (c < m) ? a[c] : 0.0;
+  }
+}
+
+}  // namespace
+
+void qr_batched(const QrTask* tasks_d, int ntasks, int n, int cap, const int* m_dev, hipStream_t st) {
+  if (ntasks <= 0) return;
+  TK_CHECK(n <= QR_NT, kErrUnsupported, "Householder QR: more than 512 rows");
+  TK_CHECK(cap <= QR_MC, kErrUnsupported, "Householder QR: more than 64 columns");
+  hipLaunchKernelGGL(qr_kernel, dim3(ntasks), dim3(QR_NT), 0, st, tasks_d, n, cap, m_dev);
+  TK_LAUNCH_CHECK();
+}
+
+}  // namespace tk

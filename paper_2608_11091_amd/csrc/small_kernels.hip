@@ -1,0 +1,152 @@
+// Small bookkeeping kernels: coefficient gathering, zero-sum fix-up,
+// accumulation, vector sums and the per-iteration status record.
+#include "kernels.hpp"
+
+namespace tk {
+
+namespace {
+
+__global__ void gather_coef_kernel(const double* const* cptr, const double* cscale, int nb, double* coef) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) coef[b] = cscale[b] * (cptr[b] ? *cptr[b] : 1.0);
+}
+
+__global__ void zero_threshold_kernel(const double* w, int nb, double tol, double* zthr) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += w[b];
+  s *= tol;
+  *zthr = s * s;
+}
+
+template <typename T>
+__global__ void zero_sum_fixup_kernel(const double* total, const double* zthr, int d, int n0, int n1, int n2, int n3, int rc, T* U0, T* U1,
+                                      T* U2, T* U3, T* core, size_t core_len, int* rank) {
+  if (*total > *zthr) return;
+  const int ns[4] = {n0, n1, n2, n3};
+  T* Us[4] = {U0, U1, U2, U3};
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t nth = (size_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < d; ++k) {
+    const size_t len = size_t(ns[k]) * rc;
+    for (size_t e = tid; e < len; e += nth) Us[k][e] = (e == 0) ? T(1) : T(0);
+  }
+  for (size_t e = tid; e < core_len; e += nth) core[e] = T(0);
+  if (tid < size_t(d)) rank[tid] = 1;
+}
+
+template <typename T>
+__global__ void mat_axpy_kernel(const T* X, int ldx, T* Y, int ldy, int rows, int cols) {
+  const size_t total = size_t(rows) * cols;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = int(e % rows), j = int(e / rows);
+    Y[i + size_t(j) * ldy] += X[i + size_t(j) * ldx];
+  }
+}
+
+template <typename T>
+__global__ void sum_vectors_kernel(const T* base, size_t stride, int nb, int len, double* out) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= len) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += double(base[b * stride + l]);
+  out[l] = s;
+}
+
+__global__ void copy_ints_kernel(const int* src, int* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void vec_sqrt_kernel(const double* src, double* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = sqrt(src[i]);
+}
+
+__global__ void iter_status_kernel(const double* sumsq2, const int* ls_flags, const double* res_k, const int* rank,
+                                   int d, double bd_tol, double* omega, IterStatus* out) {
+  if (threadIdx.x != 0) return;
+  const double wn = sqrt(sumsq2[0]);
+  const double om = sqrt(sumsq2[1]);
+  *omega = om;
+  IterStatus s;
+  s.breakdown_ls = ls_flags[0];
+  s.converged = ls_flags[1];
+  s.breakdown_w = (om <= bd_tol * wn) ? 1 : 0;
+  s.pad = 0;
+  for (int k = 0; k < kMaxD; ++k) s.rank[k] = k < d ? rank[k] : 0;
+  s.res = *res_k;
+  s.omega = om;
+  *out = s;
+}
+
+inline unsigned gsz(size_t n) {
+  size_t g = (n + 255) / 256;
+  return (unsigned)(g == 0 ? 1 : (g > 1024 ? 1024 : g));
+}
+
+}  // namespace
+
+void gather_coef(const double* const* cptr, const double* cscale, int nb, double* coef, hipStream_t st) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(gather_coef_kernel, dim3(ceil_div(nb, 64)), dim3(64), 0, st, cptr, cscale, nb, coef);
+  TK_LAUNCH_CHECK();
+}
+
+void zero_threshold(const double* w, int nb, double tol, double* zthr, hipStream_t st) {
+  hipLaunchKernelGGL(zero_threshold_kernel, dim3(1), dim3(64), 0, st, w, nb, tol, zthr);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void zero_sum_fixup(const double* total, const double* zthr, int d, const int* n, int rc, T* const* U, T* core,
+                    size_t core_len, int* rank, hipStream_t st) {
+  int nn[4] = {0, 0, 0, 0};
+  T* uu[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int k = 0; k < d; ++k) {
+    nn[k] = n[k];
+    uu[k] = U[k];
+  }
+  hipLaunchKernelGGL((zero_sum_fixup_kernel<T>), dim3(gsz(core_len)), dim3(256), 0, st, total, zthr, d, nn[0], nn[1], nn[2],
+                     nn[3], rc, uu[0], uu[1], uu[2], uu[3], core, core_len, rank);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void mat_axpy(const T* X, int ldx, T* Y, int ldy, int rows, int cols, hipStream_t st) {
+  hipLaunchKernelGGL((mat_axpy_kernel<T>), dim3(gsz(size_t(rows) * cols)), dim3(256), 0, st, X, ldx, Y, ldy, rows, cols);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void sum_vectors(const T* base, size_t stride, int nb, int len, double* out, hipStream_t st) {
+  hipLaunchKernelGGL((sum_vectors_kernel<T>), dim3(ceil_div(len, 256)), dim3(256), 0, st, base, stride, nb, len, out);
+  TK_LAUNCH_CHECK();
+}
+
+void copy_ints(const int* src, int* dst, int n, hipStream_t st) {
+  hipLaunchKernelGGL(copy_ints_kernel, dim3(1), dim3(64), 0, st, src, dst, n);
+  TK_LAUNCH_CHECK();
+}
+
+void vec_sqrt(const double* src, double* dst, int n, hipStream_t st) {
+  hipLaunchKernelGGL(vec_sqrt_kernel, dim3(1), dim3(64), 0, st, src, dst, n);
+  TK_LAUNCH_CHECK();
+}
+
+void iter_status(const double* sumsq2, const int* ls_flags, const double* res_k, const int* rank, int d, double bd_tol,
+                 double* omega, IterStatus* out, hipStream_t st) {
+  hipLaunchKernelGGL(iter_status_kernel, dim3(1), dim3(64), 0, st, sumsq2, ls_flags, res_k, rank, d, bd_tol, omega, out);
+  TK_LAUNCH_CHECK();
+}
+
+template void zero_sum_fixup<double>(const double*, const double*, int, const int*, int, double* const*, double*,
+                                     size_t, int*, hipStream_t);
+template void zero_sum_fixup<float>(const double*, const double*, int, const int*, int, float* const*, float*, size_t,
+                                    int*, hipStream_t);
+template void mat_axpy<double>(const double*, int, double*, int, int, int, hipStream_t);
+template void mat_axpy<float>(const float*, int, float*, int, int, int, hipStream_t);
+template void sum_vectors<double>(const double*, size_t, int, int, double*, hipStream_t);
+template void sum_vectors<float>(const float*, size_t, int, int, double*, hipStream_t);
+
+}  // namespace tk

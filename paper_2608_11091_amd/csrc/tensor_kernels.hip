@@ -1,0 +1,331 @@
+// Khatri-Rao reductions, flat reductions and layout kernels.
+#include "kernels.hpp"
+
+namespace tk {
+
+namespace {
+
+struct Dims4 {
+  int v[kMaxD];
+};
+
+constexpr int KRP_NT = 256;
+constexpr int KRP_ZMAX = 128;
+
+// One workgroup per (column l, task).  M_j[:, l] is staged in LDS; threads
+// split the contraction over the non-free multi-index and combine partial
+// sums in a fixed order (bitwise reproducible).
+template <typename T>
+__global__ __launch_bounds__(KRP_NT) void krp_kernel(const KrpTask<T>* __restrict__ tasks, int m, Dims4 z,
+                                                     int P, int S) {
+  __shared__ T mv[kMaxD][KRP_ZMAX];
+  __shared__ T part[KRP_NT];
+  const int l = blockIdx.x;
+  const KrpTask<T> tk_ = tasks[blockIdx.y];
+  const int f = tk_.f, ldo = tk_.ldo;
+  const int tid = threadIdx.x;
+  for (int j = 0; j < m; ++j) {
+    if (j == f) continue;
+    for (int i = tid; i < z.v[j]; i += KRP_NT) mv[j][i] = tk_.Mj[j][i + (size_t)l * tk_.ldm[j]];
+  }
+  __syncthreads();
+  const T* Zl = tk_.Z + (size_t)l * P;
+  double coef = tk_.scale * (tk_.coef ? *tk_.coef : 1.0);
+  if (f >= 0) {
+    const int zf = z.v[f];
+    const int nparts = KRP_NT / zf;
+    const int a = tid % zf, pp = tid / zf;
+    const int O = P / zf;
+    T acc = T(0);
+    if (pp < nparts) {
+      // strides of the row-major multi-index
+      int stride[kMaxD];
+      stride[m - 1] = 1;
+      for (int j = m - 2; j >= 0; --j) stride[j] = stride[j + 1] * z.v[j + 1];
+      for (int o = pp; o < O; o += nparts) {
+        int rem = o, row = a * stride[f];
+        T prod = T(1);
+        for (int j = m - 1; j >= 0; --j) {
+          if (j == f) continue;
+          const int ij = rem % z.v[j];
+          rem /= z.v[j];
+          row += ij * stride[j];
+          prod *= mv[j][ij];
+        }
+        acc += Zl[row] * prod;
+      }
+    }
+    part[tid] = acc;
+    __syncthreads();
+    if (tid < zf) {
+      T s = T(0);
+      for (int q = 0; q < nparts; ++q) s += part[q * zf + tid];
+      T* o = tk_.out + tid + (size_t)l * ldo;
+      const T v = T(coef) * s;
+      *o = tk_.accumulate ? *o + v : v;
+    }
+  } else {
+    T acc = T(0);
+    for (int e = tid; e < P; e += KRP_NT) {
+      int rem = e;
+      T prod = T(1);
+      for (int j = m - 1; j >= 0; --j) {
+        const int ij = rem % z.v[j];
+        rem /= z.v[j];
+        prod *= mv[j][ij];
+      }
+      acc += Zl[e] * prod;
+    }
+    __shared__ T red[KRP_NT / kWave];
+    const T s = block_sum(acc, red);
+    if (tid == 0) {
+      T* o = tk_.out + (size_t)l * ldo;
+      const T v = T(coef) * s;
+      *o = tk_.accumulate ? *o + v : v;
+    }
+  }
+}
+
+template <typename T>
+__global__ void sumsq_kernel(const T* __restrict__ base, size_t stride, size_t len, double* __restrict__ out) {
+  __shared__ double red[4];
+  const T* x = base + blockIdx.x * stride;
+  double acc = 0.0;
+  for (size_t e = threadIdx.x; e < len; e += blockDim.x) {
+    const double v = double(x[e]);
+    acc += v * v;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+__global__ void weights_kernel(const double* coef, const double* sumsq, int n, double* w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = fabs(coef ? coef[i] : 1.0) * sqrt(sumsq[i]);
+}
+
+template <typename T>
+__global__ void dot_kernel(const T* const* xs, const T* const* ys, size_t len, double scale, double* out) {
+  __shared__ double red[4];
+  const T* x = xs[blockIdx.x];
+  const T* y = ys[blockIdx.x];
+  double acc = 0.0;
+  for (size_t e = threadIdx.x; e < len; e += blockDim.x) acc += double(x[e]) * double(y[e]);
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = scale * s;
+}
+
+template <typename T>
+__global__ void scale_kernel(const T* __restrict__ x, T* __restrict__ y, size_t len, double scale, const double* num,
+                             const double* den) {
+  double a = scale;
+  if (num) a *= *num;
+  if (den) a /= *den;
+  const T at = T(a);
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
+    y[e] = at * x[e];
+}
+
+template <typename T>
+__global__ void fill_kernel(T* y, size_t len, T v) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
+    y[e] = v;
+}
+
+template <typename A, typename B>
+__global__ void cast_kernel(const A* __restrict__ x, B* __restrict__ y, size_t len) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
+    y[e] = B(x[e]);
+}
+
+template <typename T>
+__global__ void core_recap_kernel(const T* __restrict__ src, Dims4 sd, Dims4 sv, T* __restrict__ dst, Dims4 dd,
+                                  int d, size_t total) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    size_t rem = e, so = 0, sstr = 1;
+    bool inside = true;
+    for (int k = d - 1; k >= 0; --k) {
+      const int ik = int(rem % dd.v[k]);
+      rem /= dd.v[k];
+      if (ik >= sv.v[k] || ik >= sd.v[k]) inside = false;
+      so += size_t(ik) * sstr;
+      sstr *= sd.v[k];
+    }
+    dst[e] = inside ? src[so] : T(0);
+  }
+}
+
+template <typename T>
+__global__ void mat_recap_kernel(const T* __restrict__ src, int lds, int rs, int cs, T* __restrict__ dst, int ldd,
+                                 int rd, int cd) {
+  const size_t total = size_t(rd) * cd;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = int(e % rd), j = int(e / rd);
+    dst[i + size_t(j) * ldd] = (i < rs && j < cs) ? src[i + size_t(j) * lds] : T(0);
+  }
+}
+
+__global__ void sketch_width_kernel(const int* rt, int d, int p, int cap, int force, int* s_out) {
+  if (threadIdx.x != 0) return;
+  if (force >= 0) {
+    *s_out = force;
+    return;
+  }
+  int est = 0;
+  for (int k = 0; k < d; ++k) {
+    const int v = rt[k] < 0 ? cap + p : rt[k] + p;
+    est = v > est ? v : est;
+  }
+  *s_out = est < cap + p ? est : cap + p;
+}
+
+__global__ void gram_prep_kernel(const int* const* ranks, int nb, int d, int rmax, double* enable, int* nact) {
+  const int k = threadIdx.x;
+  if (k >= d) return;
+  int R = 0;
+  for (int b = 0; b < nb; ++b) R += ranks[b][k];
+  enable[k] = R <= rmax ? 1.0 : 0.0;
+  nact[k] = R <= rmax ? R : -1;
+}
+
+// Compacts the lower triangle of a padded block Gram: compact index i maps to
+// (block b, local a) through the prefix sums of the block ranks.
+template <typename T>
+__global__ void gram_compact_kernel(const T* __restrict__ padded, int ldp, const int* const* ranks, int nb, int rc,
+                                    const int* nact, T* __restrict__ compact, int ldc, size_t msp, size_t msc) {
+  const int k = blockIdx.y;
+  const int R = nact[k];
+  if (R <= 0) return;
+  const T* P = padded + k * msp;
+  T* C = compact + k * msc;
+  const size_t total = size_t(R) * R;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = int(e % R), j = int(e / R);
+    if (i < j) continue;
+    int bi = 0, oi = i;
+    while (oi >= ranks[bi][k]) { oi -= ranks[bi][k]; ++bi; }
+    int bj = 0, oj = j;
+    while (oj >= ranks[bj][k]) { oj -= ranks[bj][k]; ++bj; }
+    C[i + size_t(j) * ldc] = P[(bi * rc + oi) + size_t(bj * rc + oj) * ldp];
+  }
+}
+
+inline unsigned grid_for(size_t n, unsigned nt = 256) {
+  size_t g = (n + nt - 1) / nt;
+  return (unsigned)(g < 2048 ? (g == 0 ? 1 : g) : 2048);
+}
+
+}  // namespace
+
+template <typename T>
+void krp_reduce(const KrpTask<T>* tasks_d, int ntasks, int m, const int* z, int P, int S, hipStream_t st) {
+  if (ntasks <= 0 || S <= 0) return;
+  Dims4 zz{};
+  for (int j = 0; j < m; ++j) {
+    zz.v[j] = z[j];
+    TK_CHECK(z[j] <= KRP_ZMAX, kErrUnsupported, "Khatri-Rao reduction: mode size above 128");
+  }
+  hipLaunchKernelGGL((krp_kernel<T>), dim3(S, ntasks), dim3(KRP_NT), 0, st, tasks_d, m, zz, P, S);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void sumsq_batched(const T* base, size_t stride, size_t len, int n, double* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((sumsq_kernel<T>), dim3(n), dim3(256), 0, st, base, stride, len, out);
+  TK_LAUNCH_CHECK();
+}
+
+void block_weights(const double* coef, const double* sumsq, int n, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(weights_kernel, dim3(ceil_div(n, 64)), dim3(64), 0, st, coef, sumsq, n, w);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void dot_batched(const T* const* xs, const T* const* ys, size_t len, int n, double scale, double* out,
+                 hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((dot_kernel<T>), dim3(n), dim3(256), 0, st, xs, ys, len, scale, out);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void scale_copy(const T* x, T* y, size_t len, double scale, const double* num, const double* den, hipStream_t st) {
+  hipLaunchKernelGGL((scale_kernel<T>), dim3(grid_for(len)), dim3(256), 0, st, x, y, len, scale, num, den);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void fill(T* y, size_t len, T v, hipStream_t st) {
+  if (len == 0) return;
+  hipLaunchKernelGGL((fill_kernel<T>), dim3(grid_for(len)), dim3(256), 0, st, y, len, v);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename A, typename B>
+void cast_copy(const A* x, B* y, size_t len, hipStream_t st) {
+  if (len == 0) return;
+  hipLaunchKernelGGL((cast_kernel<A, B>), dim3(grid_for(len)), dim3(256), 0, st, x, y, len);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void core_recap(const T* src, const int* sd, const int* sv, T* dst, const int* dd, int d, hipStream_t st) {
+  Dims4 a{}, v{}, b{};
+  size_t total = 1;
+  for (int k = 0; k < d; ++k) {
+    a.v[k] = sd[k];
+    v.v[k] = sv ? sv[k] : sd[k];
+    b.v[k] = dd[k];
+    total *= size_t(dd[k]);
+  }
+  hipLaunchKernelGGL((core_recap_kernel<T>), dim3(grid_for(total)), dim3(256), 0, st, src, a, v, dst, b, d, total);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void mat_recap(const T* src, int ld_src, int rows_src, int cols_src, T* dst, int ld_dst, int rows_dst, int cols_dst,
+               hipStream_t st) {
+  const size_t total = size_t(rows_dst) * cols_dst;
+  if (total == 0) return;
+  hipLaunchKernelGGL((mat_recap_kernel<T>), dim3(grid_for(total)), dim3(256), 0, st, src, ld_src, rows_src, cols_src,
+                     dst, ld_dst, rows_dst, cols_dst);
+  TK_LAUNCH_CHECK();
+}
+
+void gram_prep(const int* const* ranks, int nb, int d, int rmax, double* enable, int* nact, hipStream_t st) {
+  hipLaunchKernelGGL(gram_prep_kernel, dim3(1), dim3(64), 0, st, ranks, nb, d, rmax, enable, nact);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void gram_compact(const T* padded, int ldp, const int* const* ranks, int nb, int d, int rc, const int* nact,
+                  T* compact, int ldc, size_t mode_stride_p, size_t mode_stride_c, hipStream_t st) {
+  hipLaunchKernelGGL((gram_compact_kernel<T>), dim3(64, d), dim3(256), 0, st, padded, ldp, ranks, nb, rc, nact,
+                     compact, ldc, mode_stride_p, mode_stride_c);
+  TK_LAUNCH_CHECK();
+}
+
+void sketch_width(const int* rt, int d, int p, int cap, int force, int* s_out, hipStream_t st) {
+  hipLaunchKernelGGL(sketch_width_kernel, dim3(1), dim3(64), 0, st, rt, d, p, cap, force, s_out);
+  TK_LAUNCH_CHECK();
+}
+
+#define TK_INST(T)                                                                                         \
+  template void krp_reduce<T>(const KrpTask<T>*, int, int, const int*, int, int, hipStream_t);             \
+  template void sumsq_batched<T>(const T*, size_t, size_t, int, double*, hipStream_t);                     \
+  template void dot_batched<T>(const T* const*, const T* const*, size_t, int, double, double*, hipStream_t); \
+  template void scale_copy<T>(const T*, T*, size_t, double, const double*, const double*, hipStream_t);    \
+  template void fill<T>(T*, size_t, T, hipStream_t);                                                       \
+  template void core_recap<T>(const T*, const int*, const int*, T*, const int*, int, hipStream_t);         \
+  template void mat_recap<T>(const T*, int, int, int, T*, int, int, int, hipStream_t);                     \
+  template void gram_compact<T>(const T*, int, const int* const*, int, int, int, const int*, T*, int, size_t, \
+                                size_t, hipStream_t);
+TK_INST(double)
+TK_INST(float)
+#undef TK_INST
+template void cast_copy<double, float>(const double*, float*, size_t, hipStream_t);
+template void cast_copy<float, double>(const float*, double*, size_t, hipStream_t);
+template void fill<int>(int*, size_t, int, hipStream_t);
+
+}  // namespace tk
