@@ -121,6 +121,7 @@ typedef struct {
   double* hist_sketched;       /* [hist_cap] sketched relative residual per iteration, or NULL */
   double* hist_true;           /* [hist_cap] true relative residual per cycle, or NULL */
   int32_t* hist_ranks;         /* [hist_cap * TK_MAX_D] ranks of each new basis tensor, or NULL */
+  double* hist_cycle_seconds;  /* [hist_cap] elapsed seconds at the end of each cycle, or NULL */
 } tk_sgmres_info;
 
 /* Operator factors applied to a Tucker tensor (Eq. (2)): for every term j and
@@ -173,6 +174,16 @@ int tsgmres_backward_workspace(const tk_kron_op* op, const tk_tucker* x, const t
  * residual).  *out (host) receives ||sum_b coef_b X_b||_F.  Ranks <= 64. */
 int tucker_norm(const tk_block_sum* x, double* out, void* ws, size_t ws_bytes, void* stream);
 int tucker_norm_workspace(const tk_block_sum* x, size_t* bytes);
+
+/* Kernel-class timers for performance reporting (not thread-safe; for
+ * benchmarks).  kind: 0 GEMM, 1 Jacobi eigensolver, 2 Householder QR,
+ * 3 Khatri-Rao reduction.  Enabling (or disabling) clears the record; while
+ * enabled, every launch of the class records a HIP event pair on its stream.
+ * tk_kernel_timer_read synchronises those events and returns the launch count,
+ * the summed kernel time in milliseconds and (GEMM class; optional, may be
+ * NULL) the summed algorithmic flops 2*M*N*K per product of those launches. */
+int tk_kernel_timer(int32_t kind, int32_t enable);
+int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, double* flops);
 
 /* Message of the last error on this thread ("" if none). */
 const char* tk_last_error(void);

@@ -21,7 +21,7 @@ EXPORTS = [
     "tucker_apply_op", "tucker_apply_op_workspace", "tucker_sketch", "tucker_sketch_workspace",
     "tucker_rhosvd", "tucker_rhosvd_workspace", "tsgmres_solve", "tsgmres_solve_workspace",
     "tsgmres_backward", "tsgmres_backward_workspace", "tucker_norm", "tucker_norm_workspace",
-    "tk_last_error", "tk_version",
+    "tk_kernel_timer", "tk_kernel_timer_read", "tk_last_error", "tk_version",
 ]
 
 
@@ -55,7 +55,8 @@ class TkSgmresInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters_total", C.c_int32), ("cycles", C.c_int32),
                 ("true_relres", C.c_double), ("seconds", C.c_double), ("hist_cap", C.c_int32),
                 ("hist_len", C.c_int32), ("hist_sketched", C.POINTER(C.c_double)),
-                ("hist_true", C.POINTER(C.c_double)), ("hist_ranks", C.POINTER(C.c_int32))]
+                ("hist_true", C.POINTER(C.c_double)), ("hist_ranks", C.POINTER(C.c_int32)),
+                ("hist_cycle_seconds", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -84,6 +85,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.tsgmres_backward_workspace.argtypes = [P(TkKronOp), P(TkTucker), P(TkBlockSum), P(TkSgmresParams), P(SZ)]
     lib.tucker_norm.argtypes = [P(TkBlockSum), P(C.c_double), VP, SZ, VP]
     lib.tucker_norm_workspace.argtypes = [P(TkBlockSum), P(SZ)]
+    lib.tk_kernel_timer.argtypes = [C.c_int32, C.c_int32]
+    lib.tk_kernel_timer_read.argtypes = [C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)]
     lib.tk_last_error.restype = C.c_char_p
     lib.tk_version.restype = C.c_int
     for name in EXPORTS:

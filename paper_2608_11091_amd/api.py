@@ -24,7 +24,7 @@ from . import _abi
 from ._abi import TK_MAX_D, TkBlockSum, TkKronOp, TkRoundParams, TkSgmresInfo, TkSgmresParams, TkTucker, check
 
 __all__ = ["Tucker", "KronOp", "SolveParams", "apply_op", "sketch", "rhosvd", "norm", "solve", "backward",
-           "TuckerSGMRESLoss", "storage_floats"]
+           "TuckerSGMRESLoss", "storage_floats", "kernel_timer", "kernel_timer_read", "solve_workspace_bytes"]
 
 
 def _stream():
@@ -254,20 +254,23 @@ def _info(hist_cap: int):
     hs = (C.c_double * hist_cap)()
     ht = (C.c_double * hist_cap)()
     hr = (C.c_int32 * (hist_cap * TK_MAX_D))()
+    hc = (C.c_double * hist_cap)()
     info.hist_cap = hist_cap
     info.hist_sketched = hs
     info.hist_true = ht
     info.hist_ranks = hr
-    return info, (hs, ht, hr)
+    info.hist_cycle_seconds = hc
+    return info, (hs, ht, hr, hc)
 
 
 def _info_dict(info, keep, d):
-    hs, ht, hr = keep
+    hs, ht, hr, hc = keep
     n = info.hist_len
     return dict(status=int(info.status), status_name=_abi.STATUS.get(int(info.status), "?"),
                 iters=int(info.iters_total), cycles=int(info.cycles), true_relres=float(info.true_relres),
                 seconds=float(info.seconds), hist=[hs[i] for i in range(n)],
                 true_hist=[ht[i] for i in range(int(info.cycles))],
+                cycle_seconds=[hc[i] for i in range(int(info.cycles))],
                 ranks=[tuple(hr[i * TK_MAX_D + k] for k in range(d)) for i in range(n)])
 
 
@@ -358,6 +361,23 @@ class TuckerSGMRESLoss(torch.autograd.Function):
         p["lambda"] = lam
         p["backward_info"] = info
         return g * torch.from_numpy(dalpha), None
+
+
+KERNEL_CLASSES = {"gemm": 0, "jacobi": 1, "qr": 2, "krp": 3}
+
+
+def kernel_timer(kind: str, enable: bool) -> None:
+    """Enable/disable (and clear) HIP-event timing of one kernel class."""
+    check(_abi.load().tk_kernel_timer(KERNEL_CLASSES[kind], int(enable)))
+
+
+def kernel_timer_read(kind: str):
+    """(launches, total kernel milliseconds, algorithmic flops) since enabling."""
+    n = C.c_int64()
+    ms = C.c_double()
+    fl = C.c_double()
+    check(_abi.load().tk_kernel_timer_read(KERNEL_CLASSES[kind], C.byref(n), C.byref(ms), C.byref(fl)))
+    return int(n.value), float(ms.value), float(fl.value)
 
 
 def storage_floats(n: Sequence[int], ranks: Sequence[int]) -> int:

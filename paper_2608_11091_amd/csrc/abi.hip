@@ -313,6 +313,9 @@ void fill_info(const SolveInfo& si, tk_sgmres_info* info, int d) {
   }
   if (info->hist_true)
     for (int i = 0; i < std::min<int>(int(si.hist_true.size()), info->hist_cap); ++i) info->hist_true[i] = si.hist_true[i];
+  if (info->hist_cycle_seconds)
+    for (int i = 0; i < std::min<int>(int(si.hist_time.size()), info->hist_cap); ++i)
+      info->hist_cycle_seconds[i] = si.hist_time[i];
 }
 
 int do_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* prm, const double* const* S,
@@ -575,6 +578,23 @@ int tucker_norm_workspace(const tk_block_sum* x, size_t* bytes) {
     const int r = do_norm(x, nullptr, ar, nullptr);
     if (bytes) *bytes = ar.used();
     return r;
+  });
+}
+
+int tk_kernel_timer(int32_t kind, int32_t enable) {
+  return guarded([&] {
+    TK_CHECK(kind >= 0 && kind < kKcCount, kErrInvalidArg, "unknown kernel class");
+    timer_enable(kind, enable != 0);
+    return 0;
+  });
+}
+int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, double* flops) {
+  return guarded([&] {
+    TK_CHECK(kind >= 0 && kind < kKcCount && launches && total_ms, kErrInvalidArg, "bad timer query");
+    double f = 0.0;
+    timer_read(kind, launches, total_ms, &f);
+    if (flops) *flops = f;
+    return 0;
   });
 }
 

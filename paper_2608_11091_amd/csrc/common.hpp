@@ -123,6 +123,15 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
   return s;
 }
 
+// Optional HIP-event timing of one kernel class (for live roofline numbers):
+// when enabled, launches of that class record an event pair on their stream.
+enum KernelClass : int { kKcGemm = 0, kKcJacobi = 1, kKcQr = 2, kKcKrp = 3, kKcLs = 4, kKcCount = 5 };
+bool timer_on(int kind);
+void timer_begin(int kind, hipStream_t st, double flops = 0.0);
+void timer_end(int kind, hipStream_t st);
+void timer_enable(int kind, bool on);
+void timer_read(int kind, int64_t* launches, double* total_ms, double* total_flops);
+
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 inline int64_t ipow(int64_t b, int e) {
   int64_t r = 1;

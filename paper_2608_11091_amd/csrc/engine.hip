@@ -75,6 +75,9 @@ void emit_gemm(Seq& q, Planner& pl, GemmDesc<T>&& g) {
   const int* nb = g.nb;
   auto ngf = g.ngroups_of;
   const bool tb = g.terms_are_blocks;
+  std::vector<int> nterm;
+  for (auto& gr : g.groups) nterm.push_back(gr.t1 - gr.t0);
+  const double mnk2 = 2.0 * g.M * g.N * g.K;
   q.steps.push_back([=](hipStream_t st) {
     GemmLaunch<T> l = L;
     l.terms = bl->at<GemmTerm<T>>(toff);
@@ -82,6 +85,11 @@ void emit_gemm(Seq& q, Planner& pl, GemmDesc<T>&& g) {
     if (nb) {
       if (ngf) l.ngroups = std::min(ng, ngf(*nb));
       if (tb) l.max_terms = *nb;
+    }
+    if (timer_on(kKcGemm)) {
+      double f = 0.0;
+      for (int i = 0; i < l.ngroups; ++i) f += mnk2 * std::min(nterm[i], l.max_terms);
+      l.flops = f;
     }
     gemm_run(l, st);
   });

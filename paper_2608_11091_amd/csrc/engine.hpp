@@ -172,7 +172,7 @@ struct SolveCfg {
 struct SolveInfo {
   int status = 1, iters = 0, cycles = 0;
   double true_relres = 1.0, seconds = 0.0;
-  std::vector<double> hist_sketched, hist_true;
+  std::vector<double> hist_sketched, hist_true, hist_time;
   std::vector<int> hist_ranks;  // d per iteration
 };
 

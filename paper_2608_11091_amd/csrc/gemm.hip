@@ -163,6 +163,7 @@ void gemm_run(const GemmLaunch<T>& g, hipStream_t st) {
   if (g.ngroups <= 0 || g.M <= 0 || g.N <= 0) return;
   dim3 grid(ceil_div(g.M, BM), ceil_div(g.N, BN), g.ngroups * g.splits);
   T* part = g.splits > 1 ? g.partial : nullptr;
+  timer_begin(kKcGemm, st, g.flops);
 #define TK_GEMM_CASE(TA, TB)                                                                          \
   if (g.ta == TA && g.tb == TB)                                                                       \
     hipLaunchKernelGGL((gemm_kernel<T, TA, TB>), grid, dim3(NT), 0, st, g.M, g.N, g.K, g.lda, g.ldb, g.ldc, \
@@ -179,6 +180,7 @@ void gemm_run(const GemmLaunch<T>& g, hipStream_t st) {
     hipLaunchKernelGGL((splitk_reduce<T>), rg, dim3(256), 0, st, g.M, g.N, g.ldc, g.groups, g.beta, g.splits, part);
     TK_LAUNCH_CHECK();
   }
+  timer_end(kKcGemm, st);
 }
 
 template void gemm_run<double>(const GemmLaunch<double>&, hipStream_t);

@@ -151,14 +151,120 @@ __global__ __launch_bounds__(QR_NT) void qr_kernel(const QrTask* __restrict__ ta
   }
 }
 
+constexpr int CH_NT = 256;
+constexpr int CH_MAX = 64;
+
+// Right-looking Cholesky of one small Gram in LDS (one workgroup per task).
+__global__ __launch_bounds__(CH_NT) void chol_kernel(const CholTask* __restrict__ tasks, int cap,
+                                                     const int* __restrict__ m_dev, double shift) {
+  __shared__ double G[CH_MAX][CH_MAX + 1];
+  __shared__ double red[CH_NT / kWave];
+  __shared__ double piv_s;
+  __shared__ int dead[CH_MAX];
+  const CholTask tk_ = tasks[blockIdx.x];
+  const int tid = threadIdx.x;
+  int m = m_dev ? *m_dev : cap;
+  m = min(m, cap);
+  for (int e = tid; e < cap * cap; e += CH_NT) {
+    const int i = e % cap, j = e / cap;
+    G[i][j] = (i < m && j < m) ? tk_.G[i + (size_t)j * cap] : 0.0;
+  }
+  __syncthreads();
+  const double tr = block_sum(tid < m ? G[tid][tid] : 0.0, red);
+  const double s = shift * tr;
+  const double dtol = 1e-15 * tr;
+  if (tid < m) G[tid][tid] += s;
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    if (tid == 0) {
+      const double pv = G[k][k];
+      const bool dk = !(pv > dtol);
+      dead[k] = dk;
+      piv_s = dk ? 0.0 : sqrt(pv);
+    }
+    __syncthreads();
+    const double rkk = piv_s;
+    const bool dk = dead[k];
+    // row k of R: R[k][j] = G[k][j] / rkk (j > k)
+    if (tid > k && tid < m) G[k][tid] = dk ? 0.0 : G[k][tid] / rkk;
+    if (tid == 0) G[k][k] = rkk;
+    __syncthreads();
+    if (!dk) {
+      for (int e = tid; e < (m - k - 1) * (m - k - 1); e += CH_NT) {
+        const int i = k + 1 + e % (m - k - 1), j = k + 1 + e / (m - k - 1);
+        if (i <= j) G[i][j] -= G[k][i] * G[k][j];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < cap * cap; e += CH_NT) {
+    const int i = e % cap, j = e / cap;
+    tk_.R[i + (size_t)j * cap] = (i < m && j < m && i <= j) ? G[i][j] : 0.0;
+  }
+}
+
+constexpr int TR_NT = 128;
+
+// Q = Y R^{-1}: each thread owns one row of Y in registers (compile-time
+// column indices) and runs the forward substitution q R = y.
+__global__ __launch_bounds__(TR_NT) void trsm_rows_kernel(const TrsmTask* __restrict__ tasks, int n, int cap,
+                                                          const int* __restrict__ m_dev) {
+  __shared__ double R[CH_MAX][CH_MAX + 1];
+  const TrsmTask tk_ = tasks[blockIdx.y];
+  const int tid = threadIdx.x;
+  int m = m_dev ? *m_dev : cap;
+  m = min(m, cap);
+  for (int e = tid; e < cap * cap; e += TR_NT) {
+    const int i = e % cap, j = e / cap;
+    R[i][j] = tk_.R[i + (size_t)j * cap];
+  }
+  __syncthreads();
+  const int row = blockIdx.x * TR_NT + tid;
+  if (row >= n) return;
+  double q[CH_MAX];
+#pragma unroll
+  for (int j = 0; j < CH_MAX; ++j) q[j] = (j < m) ? tk_.Y[row + (size_t)j * n] : 0.0;
+#pragma unroll
+  for (int j = 0; j < CH_MAX; ++j) {
+    if (j < m) {
+      double acc = q[j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) acc -= q[k] * R[k][j];
+      const double rjj = R[j][j];
+      q[j] = rjj != 0.0 ? acc / rjj : 0.0;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < CH_MAX; ++j)
+    if (j < cap) tk_.Q[row + (size_t)j * n] = (j < m) ? q[j] : 0.0;
+}
+
 }  // namespace
+
+void chol_batched(const CholTask* tasks_d, int ntasks, int cap, const int* m_dev, double shift, hipStream_t st) {
+  if (ntasks <= 0) return;
+  TK_CHECK(cap <= CH_MAX, kErrUnsupported, "Cholesky-QR: more than 64 columns");
+  timer_begin(kKcQr, st);
+  hipLaunchKernelGGL(chol_kernel, dim3(ntasks), dim3(CH_NT), 0, st, tasks_d, cap, m_dev, shift);
+  TK_LAUNCH_CHECK();
+  timer_end(kKcQr, st);
+}
+
+void trsm_rows(const TrsmTask* tasks_d, int ntasks, int n, int cap, const int* m_dev, hipStream_t st) {
+  if (ntasks <= 0) return;
+  TK_CHECK(cap <= CH_MAX, kErrUnsupported, "Cholesky-QR: more than 64 columns");
+  hipLaunchKernelGGL(trsm_rows_kernel, dim3(ceil_div(n, TR_NT), ntasks), dim3(TR_NT), 0, st, tasks_d, n, cap, m_dev);
+  TK_LAUNCH_CHECK();
+}
 
 void qr_batched(const QrTask* tasks_d, int ntasks, int n, int cap, const int* m_dev, hipStream_t st) {
   if (ntasks <= 0) return;
   TK_CHECK(n <= QR_NT, kErrUnsupported, "Householder QR: more than 512 rows");
   TK_CHECK(cap <= QR_MC, kErrUnsupported, "Householder QR: more than 64 columns");
+  timer_begin(kKcQr, st);
   hipLaunchKernelGGL(qr_kernel, dim3(ntasks), dim3(QR_NT), 0, st, tasks_d, n, cap, m_dev);
   TK_LAUNCH_CHECK();
+  timer_end(kKcQr, st);
 }
 
 }  // namespace tk

@@ -140,6 +140,58 @@ void iter_status(const double* sumsq2, const int* ls_flags, const double* res_k,
   TK_LAUNCH_CHECK();
 }
 
+// ---- kernel-class timers
+namespace {
+struct TimerState {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  double flops = 0.0;
+};
+TimerState g_timers[kKcCount];
+}  // namespace
+
+bool timer_on(int kind) { return kind >= 0 && kind < kKcCount && g_timers[kind].on; }
+
+void timer_begin(int kind, hipStream_t st, double flops) {
+  if (!timer_on(kind)) return;
+  g_timers[kind].flops += flops;
+  hipEvent_t a, b;
+  TK_HIP(hipEventCreate(&a));
+  TK_HIP(hipEventCreate(&b));
+  TK_HIP(hipEventRecord(a, st));
+  g_timers[kind].ev.emplace_back(a, b);
+}
+
+void timer_end(int kind, hipStream_t st) {
+  if (!timer_on(kind) || g_timers[kind].ev.empty()) return;
+  TK_HIP(hipEventRecord(g_timers[kind].ev.back().second, st));
+}
+
+void timer_enable(int kind, bool on) {
+  TimerState& t = g_timers[kind];
+  for (auto& e : t.ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  t.ev.clear();
+  t.flops = 0.0;
+  t.on = on;
+}
+
+void timer_read(int kind, int64_t* launches, double* total_ms, double* total_flops) {
+  TimerState& t = g_timers[kind];
+  double tot = 0.0;
+  for (auto& e : t.ev) {
+    TK_HIP(hipEventSynchronize(e.second));
+    float ms = 0.f;
+    TK_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+    tot += ms;
+  }
+  *launches = int64_t(t.ev.size());
+  *total_ms = tot;
+  *total_flops = t.flops;
+}
+
 template void zero_sum_fixup<double>(const double*, const double*, int, const int*, int, double* const*, double*,
                                      size_t, int*, hipStream_t);
 template void zero_sum_fixup<float>(const double*, const double*, int, const int*, int, float* const*, float*, size_t,

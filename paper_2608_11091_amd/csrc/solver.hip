@@ -429,6 +429,7 @@ void solver_run(Solver& s, TT<double>& x_out, SolveInfo& info, hipStream_t st) {
     rnorm = std::sqrt(read_scalar(s, s.rnorm2, st));
     if (!std::isfinite(rnorm)) throw Error{kErrNonFinite, "non-finite residual norm"};
     info.hist_true.push_back(rnorm / bnorm);
+    info.hist_time.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     if (rnorm <= cfg.tol * bnorm) {
       status = kOk;
       break;

@@ -225,8 +225,10 @@ void krp_reduce(const KrpTask<T>* tasks_d, int ntasks, int m, const int* z, int 
     zz.v[j] = z[j];
     TK_CHECK(z[j] <= KRP_ZMAX, kErrUnsupported, "Khatri-Rao reduction: mode size above 128");
   }
+  timer_begin(kKcKrp, st);
   hipLaunchKernelGGL((krp_kernel<T>), dim3(S, ntasks), dim3(KRP_NT), 0, st, tasks_d, m, zz, P, S);
   TK_LAUNCH_CHECK();
+  timer_end(kKcKrp, st);
 }
 
 template <typename T>
