@@ -488,17 +488,52 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     }
     emit_gemm(q, pl, std::move(g));
   }
-  // --- 3. economy QR of every Y_k (FP64)
+  // --- 3. orthonormal basis of every range sketch Y_k (FP64): shifted
+  // Cholesky-QR in three passes (Y -> Q -> Y -> Q ping-pong).  Pass 1 is
+  // shifted by 11 (m s + s(s+1)) u tr(Y^T Y), so it never breaks down; pass 2
+  // drops only columns at the underflow floor; pass 3 sees a nearly
+  // orthonormal input, where a pivot below 1/4 can only come from a
+  // rounding-noise column of a rank-deficient Y, and zeroes it.  Live columns
+  // come out orthonormal to working accuracy and span range(Y) down to
+  // rounding level.
+  double* Gq = ar.alloc<double>(size_t(d) * sc * sc);
+  double* Rq = ar.alloc<double>(size_t(d) * sc * sc);
   for (auto& modes : modes_by_n<T>(sh)) {
     const int n = sh.n[modes[0]];
-    std::vector<QrTask> qt;
-    for (int k : modes) {
-      emit_cast<T>(q, Y[k], Y64[k], size_t(n) * sc);
-      qt.push_back(QrTask{Y64[k], Q64[k], nullptr, nullptr});
+    for (int k : modes) emit_cast<T>(q, Y[k], Y64[k], size_t(n) * sc);
+    std::vector<CholTask> ct;
+    for (int k : modes) ct.push_back(CholTask{Gq + size_t(k) * sc * sc, Rq + size_t(k) * sc * sc});
+    const size_t coff = blob.add(ct);
+    const int nt = int(ct.size());
+    const double shift1 = 11.0 * (double(n) * sc + double(sc) * (sc + 1)) * 0x1p-53;
+    for (int pass = 0; pass < 3; ++pass) {
+      std::vector<const double*> src;
+      std::vector<double*> dst;
+      for (int k : modes) {
+        src.push_back(pass == 1 ? Q64[k] : Y64[k]);
+        dst.push_back(pass == 1 ? Y64[k] : Q64[k]);
+      }
+      GemmDesc<double> g;
+      g.ta = true;
+      g.tb = false;
+      g.M = sc;
+      g.N = sc;
+      g.K = n;
+      g.lda = n;
+      g.ldb = n;
+      g.ldc = sc;
+      for (size_t i = 0; i < modes.size(); ++i) g.group1(Gq + size_t(modes[i]) * sc * sc, src[i], src[i]);
+      emit_gemm(q, pl, std::move(g));
+      const double sh_p = pass == 0 ? shift1 : 0.0;
+      const double drel = pass == 1 ? 1e-30 : 0.0, dabs = pass == 2 ? 0.25 : 0.0;
+      q.steps.push_back(
+          [=](hipStream_t st) { chol_batched(bl->at<CholTask>(coff), nt, sc, s_dev, sh_p, drel, dabs, st); });
+      std::vector<TrsmTask> tt;
+      for (size_t i = 0; i < modes.size(); ++i)
+        tt.push_back(TrsmTask{src[i], Rq + size_t(modes[i]) * sc * sc, dst[i]});
+      const size_t toff = blob.add(tt);
+      q.steps.push_back([=](hipStream_t st) { trsm_rows(bl->at<TrsmTask>(toff), nt, n, sc, s_dev, st); });
     }
-    const size_t off = blob.add(qt);
-    const int nt = int(qt.size());
-    q.steps.push_back([=](hipStream_t st) { qr_batched(bl->at<QrTask>(off), nt, n, sc, s_dev, st); });
     if (!std::is_same<T, double>::value)
       for (int k : modes) {
         double* src = Q64[k];

@@ -72,14 +72,16 @@ void qr_batched(const QrTask* tasks_d, int ntasks, int n, int cap, const int* m_
 
 // ---- Cholesky-QR pieces (range-finder QR of RoundSum) ------------------------
 // R = chol(G + s I) for the leading m x m block of a cap x cap Gram (m =
-// min(*m_dev, cap)), with s = shift * trace(G).  A pivot <= 1e-15 * trace(G)
-// marks a numerically dependent column: its row and column of R are zeroed
-// and the triangular solve below produces a zero basis column for it.
+// min(*m_dev, cap)), with s = shift * trace(G).  A pivot that is not above
+// max(dead_rel * trace(G), dead_abs) marks a numerically dependent column: its
+// row of R is zeroed and the triangular solve below turns it into a zero
+// basis column.
 struct CholTask {
   const double* G;  // cap x cap, col-major
   double* R;        // cap x cap, col-major (upper triangle)
 };
-void chol_batched(const CholTask* tasks_d, int ntasks, int cap, const int* m_dev, double shift, hipStream_t st);
+void chol_batched(const CholTask* tasks_d, int ntasks, int cap, const int* m_dev, double shift, double dead_rel,
+                  double dead_abs, hipStream_t st);
 // Q = Y R^{-1} row by row (R upper triangular from chol_batched); columns
 // >= m and dead columns of Q are zero.  Y, Q: n x cap col-major (ld n).
 struct TrsmTask {

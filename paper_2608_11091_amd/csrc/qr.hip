@@ -156,7 +156,8 @@ constexpr int CH_MAX = 64;
 
 // Right-looking Cholesky of one small Gram in LDS (one workgroup per task).
 __global__ __launch_bounds__(CH_NT) void chol_kernel(const CholTask* __restrict__ tasks, int cap,
-                                                     const int* __restrict__ m_dev, double shift) {
+                                                     const int* __restrict__ m_dev, double shift, double dead_rel,
+                                                     double dead_abs) {
   __shared__ double G[CH_MAX][CH_MAX + 1];
   __shared__ double red[CH_NT / kWave];
   __shared__ double piv_s;
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const CholTask* __restrict_
   __syncthreads();
   const double tr = block_sum(tid < m ? G[tid][tid] : 0.0, red);
   const double s = shift * tr;
-  const double dtol = 1e-15 * tr;
+  const double dtol = fmax(dead_rel * tr, dead_abs);
   if (tid < m) G[tid][tid] += s;
   __syncthreads();
   for (int k = 0; k < m; ++k) {
@@ -241,11 +242,12 @@ __global__ __launch_bounds__(TR_NT) void trsm_rows_kernel(const TrsmTask* __rest
 
 }  // namespace
 
-void chol_batched(const CholTask* tasks_d, int ntasks, int cap, const int* m_dev, double shift, hipStream_t st) {
+void chol_batched(const CholTask* tasks_d, int ntasks, int cap, const int* m_dev, double shift, double dead_rel,
+                  double dead_abs, hipStream_t st) {
   if (ntasks <= 0) return;
   TK_CHECK(cap <= CH_MAX, kErrUnsupported, "Cholesky-QR: more than 64 columns");
   timer_begin(kKcQr, st);
-  hipLaunchKernelGGL(chol_kernel, dim3(ntasks), dim3(CH_NT), 0, st, tasks_d, cap, m_dev, shift);
+  hipLaunchKernelGGL(chol_kernel, dim3(ntasks), dim3(CH_NT), 0, st, tasks_d, cap, m_dev, shift, dead_rel, dead_abs);
   TK_LAUNCH_CHECK();
   timer_end(kKcQr, st);
 }

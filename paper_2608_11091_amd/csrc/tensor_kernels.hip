@@ -104,15 +104,54 @@ __global__ void weights_kernel(const double* coef, const double* sumsq, int n, d
   if (i < n) w[i] = fabs(coef ? coef[i] : 1.0) * sqrt(sumsq[i]);
 }
 
+// One workgroup per dot product; 16-byte loads, four independent
+// accumulators per thread so that a wave keeps several loads in flight.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using V = float4; static constexpr int W = 4; };
+template <> struct Vec16<double> { using V = double2; static constexpr int W = 2; };
+
 template <typename T>
-__global__ void dot_kernel(const T* const* xs, const T* const* ys, size_t len, double scale, double* out) {
-  __shared__ double red[4];
+__device__ __forceinline__ double vdot(const typename Vec16<T>::V& a, const typename Vec16<T>::V& b);
+template <>
+__device__ __forceinline__ double vdot<float>(const float4& a, const float4& b) {
+  return double(a.x) * double(b.x) + double(a.y) * double(b.y) + double(a.z) * double(b.z) + double(a.w) * double(b.w);
+}
+template <>
+__device__ __forceinline__ double vdot<double>(const double2& a, const double2& b) {
+  return a.x * b.x + a.y * b.y;
+}
+
+constexpr int DOT_NT = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(DOT_NT) void dot_kernel(const T* const* xs, const T* const* ys, size_t len, double scale,
+                                                     double* out) {
+  __shared__ double red[DOT_NT / kWave];
+  using V = typename Vec16<T>::V;
+  constexpr int W = Vec16<T>::W;
   const T* x = xs[blockIdx.x];
   const T* y = ys[blockIdx.x];
-  double acc = 0.0;
-  for (size_t e = threadIdx.x; e < len; e += blockDim.x) acc += double(x[e]) * double(y[e]);
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) out[blockIdx.x] = scale * s;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  size_t head = 0;
+  if (((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15) == 0) {
+    const V* xv = reinterpret_cast<const V*>(x);
+    const V* yv = reinterpret_cast<const V*>(y);
+    const size_t nv = len / W;
+    size_t e = threadIdx.x;
+    for (; e + 3 * DOT_NT < nv; e += 4 * DOT_NT) {
+      const V x0 = xv[e], x1 = xv[e + DOT_NT], x2 = xv[e + 2 * DOT_NT], x3 = xv[e + 3 * DOT_NT];
+      const V y0 = yv[e], y1 = yv[e + DOT_NT], y2 = yv[e + 2 * DOT_NT], y3 = yv[e + 3 * DOT_NT];
+      a0 += vdot<T>(x0, y0);
+      a1 += vdot<T>(x1, y1);
+      a2 += vdot<T>(x2, y2);
+      a3 += vdot<T>(x3, y3);
+    }
+    for (; e < nv; e += DOT_NT) a0 += vdot<T>(xv[e], yv[e]);
+    head = nv * W;
+  }
+  for (size_t e = head + threadIdx.x; e < len; e += DOT_NT) a1 += double(x[e]) * double(y[e]);
+  const double sum = block_sum((a0 + a1) + (a2 + a3), red);
+  if (threadIdx.x == 0) out[blockIdx.x] = scale * sum;
 }
 
 template <typename T>
@@ -247,7 +286,7 @@ template <typename T>
 void dot_batched(const T* const* xs, const T* const* ys, size_t len, int n, double scale, double* out,
                  hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((dot_kernel<T>), dim3(n), dim3(256), 0, st, xs, ys, len, scale, out);
+  hipLaunchKernelGGL((dot_kernel<T>), dim3(n), dim3(DOT_NT), 0, st, xs, ys, len, scale, out);
   TK_LAUNCH_CHECK();
 }
 

