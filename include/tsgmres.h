@@ -176,12 +176,16 @@ int tucker_norm(const tk_block_sum* x, double* out, void* ws, size_t ws_bytes, v
 int tucker_norm_workspace(const tk_block_sum* x, size_t* bytes);
 
 /* Kernel-class timers for performance reporting (not thread-safe; for
- * benchmarks).  kind: 0 GEMM, 1 Jacobi eigensolver, 2 Householder QR,
- * 3 Khatri-Rao reduction.  Enabling (or disabling) clears the record; while
+ * benchmarks).  kind: 0 GEMM, 1 symmetric eigensolver with eigenvectors
+ * (Jacobi), 2 QR (Cholesky-QR / Householder), 3 Khatri-Rao reduction,
+ * 4 sketched least-squares update, 5 eigenvalues-only solver (tridiagonal
+ * reduction + bisection).  Enabling (or disabling) clears the record; while
  * enabled, every launch of the class records a HIP event pair on its stream.
  * tk_kernel_timer_read synchronises those events and returns the launch count,
- * the summed kernel time in milliseconds and (GEMM class; optional, may be
- * NULL) the summed algorithmic flops 2*M*N*K per product of those launches. */
+ * the summed kernel time in milliseconds and (optional, may be NULL) the
+ * summed algorithmic flops of those launches: 2*M*N*K per GEMM product,
+ * 9*N^3 per eigendecomposition with vectors, (4/3)*N^3 per eigenvalues-only
+ * solve (N = launch order), 0 for the other classes. */
 int tk_kernel_timer(int32_t kind, int32_t enable);
 int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, double* flops);
 

@@ -108,8 +108,10 @@ void ls_init(const LsState& st_, int s, hipStream_t st) {
 void ls_add_column(const LsState& st_, int s, int kmax, int k, double conv_tol, double breakdown_tol,
                    hipStream_t st) {
   TK_CHECK(kmax <= 64, kErrUnsupported, "sketched least squares: more than 64 iterations per cycle");
+  timer_begin(kKcLs, st);
   hipLaunchKernelGGL(ls_add_kernel, dim3(1), dim3(LS_NT), 0, st, st_, s, kmax, k, conv_tol, breakdown_tol);
   TK_LAUNCH_CHECK();
+  timer_end(kKcLs, st);
 }
 
 }  // namespace tk

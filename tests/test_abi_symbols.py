@@ -34,6 +34,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_storage_helper_matches_worked_example():
-    # Deblurring RHS of Sec. 4.3: dense 128x128x64 vs Tucker rank (80, 57, 3)
+    # Deblurring right-hand side of Sec. 4.3 (fixture tests/golden/storage_example.json)
+    import json
+    import os
     from paper_2608_11091_amd.api import storage_floats
-    assert storage_floats((128, 128, 64), (80, 57, 3)) == 31408
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "storage_example.json")))
+    assert storage_floats(g["n"], g["ranks"]) == g["tucker_floats"]
