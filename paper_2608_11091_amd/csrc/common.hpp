@@ -83,28 +83,57 @@ class Arena {
 };
 
 // ---------------------------------------------------------------- device helpers
-__device__ __forceinline__ double shfl_xor_d(double v, int mask) {
-  return __shfl_xor(v, mask, kWave);
+// Wave-uniform read of one lane's value (v_readlane; `lane` must be uniform).
+__device__ __forceinline__ float rdlane(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
-__device__ __forceinline__ float shfl_xor_d(float v, int mask) {
-  return __shfl_xor(v, mask, kWave);
+__device__ __forceinline__ double rdlane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(b), lane));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(b >> 32), lane));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Cross-lane move inside a row of 16 lanes through the DPP network (a few
+// cycles, no LDS crossbar).  CTRL: 0xB1 quad_perm[1,0,3,2], 0x4E
+// quad_perm[2,3,0,1], 0x141 row_half_mirror, 0x140 row_mirror.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_update_dpp(0, int(b), CTRL, 0xF, 0xF, false));
+  const unsigned hi = unsigned(__builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave (all lanes active); every lane gets the
+// total.  Row sums of 16 lanes through DPP, then the four rows through
+// readlane; fixed order, so deterministic.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
-  return v;
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  v += dpp_mov<0x140>(v);
+  return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    T o = shfl_xor_d(v, m);
-    v = o > v ? o : v;
-  }
-  return v;
+  T o = dpp_mov<0xB1>(v);
+  v = o > v ? o : v;
+  o = dpp_mov<0x4E>(v);
+  v = o > v ? o : v;
+  o = dpp_mov<0x141>(v);
+  v = o > v ? o : v;
+  o = dpp_mov<0x140>(v);
+  v = o > v ? o : v;
+  const T a = rdlane(v, 0), b = rdlane(v, 16), c = rdlane(v, 32), d = rdlane(v, 48);
+  const T ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
 }
 
 // Block-wide sum for blockDim.x a multiple of 64; `red` holds >= nwaves values.

@@ -1,10 +1,11 @@
 // Small symmetric eigensolvers, one workgroup per matrix.
 //
-//  * Eigenvalues only (N <= 160): Householder reduction to tridiagonal form in
-//    LDS (packed lower triangle, one thread per row for the symmetric
-//    matrix-vector product and the rank-2 update), then every eigenvalue by
-//    bisection on Sturm counts, one thread per eigenvalue.  Used by the
-//    RoundSum effective-rank rule, which needs the spectrum but no vectors.
+//  * Eigenvalues only (N <= 160): Householder reduction to tridiagonal form
+//    with the full matrix in LDS, one lane per row and the trailing columns
+//    dealt out to 16 waves (a packed-storage variant serves FP64 orders whose
+//    full matrix does not fit in LDS), then every eigenvalue by multisection
+//    on Sturm counts.  Used by the RoundSum effective-rank rule, which needs
+//    the spectrum but no vectors.
 //  * Eigenvalues and vectors (N <= 64): cyclic Jacobi with the round-robin
 //    parallel ordering, full matrix and eigenvector block in LDS, one lane
 //    per row and one wave per rotation pair.  A rotation is taken only when
@@ -86,19 +87,226 @@ __device__ int apply_rule(const EigRule& ru, const T* lam_desc, int N) {
 }
 
 // ------------------------------------------------------------ eigenvalues only
+
+// Number of eigenvalues of the tridiagonal (d, e) below x, from the signs of
+// the LDL^T pivots of T - x I (e2 = squared off-diagonal).  FP32 takes the
+// hardware reciprocal: a Sturm count tolerates ulp-level relative errors in
+// each pivot (the computed count is exact for a nearby matrix).
+__device__ __forceinline__ float sturm_div(float a, float q) { return a * __builtin_amdgcn_rcpf(q); }
+__device__ __forceinline__ double sturm_div(double a, double q) { return a / q; }
 template <typename T>
 __device__ int sturm_count(const T* d, const T* e2, int n, T x, T pivmin) {
-  // number of eigenvalues of the tridiagonal (d, e) smaller than x
   int c = 0;
   T q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   c += q < T(0);
   for (int k = 1; k < n; ++k) {
-    q = d[k] - x - e2[k - 1] / q;
+    q = d[k] - x - sturm_div(e2[k - 1], q);
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < T(0);
   }
   return c;
+}
+
+// Eigenvalues of the symmetric tridiagonal (dd, ee) (ee[k] couples k, k+1),
+// both in LDS, by multisection on Sturm counts: G lanes per eigenvalue test G
+// interior points of the current interval at once.  Writes them descending to
+// `lam` (LDS) and the task's outputs, then applies the task's rank rule.
+// Called by all `nthreads` threads of the block; ee is squared in place.
+template <typename T>
+__device__ void tridiag_spectrum(const EigTask<T>& tk_, T* dd, T* ee, T* lam, T* sc, int N, int tid, int nthreads) {
+  if (tid == 0) {
+    T gl = dd[0], gu = dd[0], emax2 = T(0);
+    for (int k = 0; k < N; ++k) {
+      const T r = (k > 0 ? fabs(ee[k - 1]) : T(0)) + (k + 1 < N ? fabs(ee[k]) : T(0));
+      gl = fmin(gl, dd[k] - r);
+      gu = fmax(gu, dd[k] + r);
+    }
+    for (int k = 0; k + 1 < N; ++k) emax2 = fmax(emax2, ee[k] * ee[k]);
+    sc[1] = gl;
+    sc[2] = gu;
+    sc[3] = emax2;
+  }
+  __syncthreads();
+  const T gl = sc[1], gu = sc[2], emax2 = sc[3];
+  for (int k = tid; k + 1 < N; k += nthreads) ee[k] = ee[k] * ee[k];
+  __syncthreads();
+  const T bnorm = fmax(fabs(gl), fabs(gu));
+  const T pivmin = fmax(Lim<T>::tiny(), emax2 * Lim<T>::tiny() * T(1e10));
+  const T tolx = T(2) * Lim<T>::eps() * bnorm;
+  // G = lanes per eigenvalue: the largest power of two <= min(16, nthreads / N)
+  int G = 1;
+  while (G < 16 && 2 * G * N <= nthreads) G *= 2;
+  const int g = tid % G;
+  const int gshift = (tid & (kWave - 1)) - g;  // first lane of the group within the wave
+  const unsigned long long gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull));
+  for (int i = tid / G; i < N; i += nthreads / G) {
+    T lo = gl - tolx, hi = gu + tolx;
+    for (int it = 0; it < 200 && hi - lo > tolx; ++it) {
+      // interior points lo + (hi - lo) (q + 1) / (G + 1), q < G; counts are
+      // monotone in q, so the new interval is (point f-1, point f] with f
+      // the first point above eigenvalue i (every lane recomputes them)
+      const T span = hi - lo;
+      const T mid = lo + span * T(g + 1) / T(G + 1);
+      const int above = (mid > lo && mid < hi) ? (sturm_count(dd, ee, N, mid, pivmin) > i) : (mid >= hi);
+      const unsigned long long bits = (__ballot(above) >> gshift) & gmask;
+      const int f = bits ? __builtin_ctzll(bits) : G;
+      const T nhi = f < G ? lo + span * T(f + 1) / T(G + 1) : hi;
+      const T nlo = f > 0 ? lo + span * T(f) / T(G + 1) : lo;
+      if (!(nhi < hi || nlo > lo)) break;
+      lo = fmax(lo, nlo);
+      hi = fmin(hi, nhi);
+    }
+    lam[N - 1 - i] = T(0.5) * (lo + hi);
+  }
+  __syncthreads();
+  if (tk_.lam)
+    for (int i = tid; i < N; i += nthreads) tk_.lam[i] = lam[i];
+  if (tid == 0 && tk_.rule.kind != 0) *tk_.rule.rank_out = apply_rule<T>(tk_.rule, lam, N);
+}
+
+constexpr int TF_NT = 1024;
+constexpr int TF_NW = TF_NT / kWave;
+constexpr int TF_CH = (VAL_NMAX + kWave - 1) / kWave;  // row chunks of 64
+
+template <typename T>
+size_t tfull_smem(int NL) {
+  return sizeof(T) * (size_t(NL) * (NL + 1) + size_t(TF_NW) * NL + 5 * size_t(NL)) + 64;
+}
+template <typename T>
+bool tfull_fits(int NL) {
+  return tfull_smem<T>(NL) <= size_t(160 * 1024 - 1024);
+}
+
+// Householder tridiagonalisation with the full matrix in LDS, column-major
+// (A[col * LDA + row]), one lane per row and the trailing columns dealt out
+// to the 16 waves: step j forms v from column j (every wave, in registers),
+// the partial products A_sub v per wave, p = tau * A_sub v and
+// w = p - (tau/2)(v.p) v, and the rank-2 update A_sub -= v w^T + w v^T of
+// each wave's columns.  Then the spectrum as above.
+template <typename T>
+__global__ __launch_bounds__(TF_NT) void tridiag_full_kernel(const EigTask<T>* __restrict__ tasks, int NL) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const EigTask<T> tk_ = tasks[blockIdx.x];
+  int N = NL;
+  if (tk_.ndyn != nullptr) {
+    const int nd = *tk_.ndyn;
+    if (nd < 0 || nd > NL) {
+      if (threadIdx.x == 0 && tk_.rule.rank_out) *tk_.rule.rank_out = -1;
+      return;
+    }
+    N = nd;
+  }
+  if (N == 0) {
+    if (threadIdx.x == 0 && tk_.rule.rank_out) *tk_.rule.rank_out = 0;
+    return;
+  }
+  const int LDA = NL + 1;
+  T* A = reinterpret_cast<T*>(smem_raw);
+  T* pp = A + size_t(NL) * LDA;  // [TF_NW][NL] partial products
+  T* vb = pp + TF_NW * NL;       // Householder vector by absolute row
+  T* wb = vb + NL;               // w by absolute row
+  T* dd = wb + NL;
+  T* ee = dd + NL;
+  T* lam = ee + NL;
+  __shared__ T red[TF_NW];
+  __shared__ T sc[4];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  for (int e = tid; e < N * N; e += TF_NT) {
+    const int i = e % N, j = e / N;
+    A[j * LDA + i] = (i >= j) ? tk_.A[i + (size_t)j * tk_.lda] : tk_.A[j + (size_t)i * tk_.lda];
+  }
+  __syncthreads();
+  for (int j = 0; j + 2 < N; ++j) {
+    const int r0 = j + 1;
+    T xs[TF_CH], vs[TF_CH];
+    T s2 = T(0);
+#pragma unroll
+    for (int c = 0; c < TF_CH; ++c) {
+      const int row = r0 + lane + kWave * c;
+      xs[c] = row < N ? A[j * LDA + row] : T(0);
+      if (row > r0 && row < N) s2 += xs[c] * xs[c];
+    }
+    s2 = wave_sum(s2);
+    const T alpha = rdlane(xs[0], 0);
+    T beta, tau, scal;
+    if (s2 == T(0)) {
+      beta = alpha;
+      tau = T(0);
+      scal = T(0);
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+      tau = (beta - alpha) / beta;
+      scal = T(1) / (alpha - beta);
+    }
+#pragma unroll
+    for (int c = 0; c < TF_CH; ++c) {
+      const int row = r0 + lane + kWave * c;
+      vs[c] = row == r0 ? T(1) : xs[c] * scal;
+      if (wave == 0 && row < N) vb[row] = vs[c];
+    }
+    if (tid == 0) {
+      dd[j] = A[j * LDA + j];
+      ee[j] = beta;
+    }
+    __syncthreads();
+    if (tau != T(0)) {
+      T acc[TF_CH];
+#pragma unroll
+      for (int c = 0; c < TF_CH; ++c) acc[c] = T(0);
+      for (int k = r0 + wave; k < N; k += TF_NW) {
+        const T vk = vb[k];
+#pragma unroll
+        for (int c = 0; c < TF_CH; ++c) {
+          const int row = r0 + lane + kWave * c;
+          if (row < N) acc[c] += A[k * LDA + row] * vk;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < TF_CH; ++c) {
+        const int row = r0 + lane + kWave * c;
+        if (row < N) pp[wave * NL + row] = acc[c];
+      }
+      __syncthreads();
+      const int row = r0 + tid;
+      T prow = T(0), pv = T(0);
+      if (row < N) {
+        T sacc = T(0);
+        for (int w = 0; w < TF_NW; ++w) sacc += pp[w * NL + row];
+        prow = tau * sacc;
+        pv = vb[row] * prow;
+      }
+      const T K = block_sum(pv, red) * T(0.5) * tau;
+      if (row < N) wb[row] = prow - K * vb[row];
+      __syncthreads();
+      T wr[TF_CH];
+#pragma unroll
+      for (int c = 0; c < TF_CH; ++c) {
+        const int rr = r0 + lane + kWave * c;
+        wr[c] = rr < N ? wb[rr] : T(0);
+      }
+      for (int k = r0 + wave; k < N; k += TF_NW) {
+        const T vk = vb[k], wk = wb[k];
+#pragma unroll
+        for (int c = 0; c < TF_CH; ++c) {
+          const int rr = r0 + lane + kWave * c;
+          if (rr < N) A[k * LDA + rr] -= vs[c] * wk + wr[c] * vk;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    if (N >= 2) {
+      dd[N - 2] = A[(N - 2) * LDA + (N - 2)];
+      ee[N - 2] = A[(N - 2) * LDA + (N - 1)];
+    }
+    dd[N - 1] = A[(N - 1) * LDA + (N - 1)];
+  }
+  __syncthreads();
+  tridiag_spectrum<T>(tk_, dd, ee, lam, sc, N, tid, TF_NT);
 }
 
 template <typename T>
@@ -214,70 +422,14 @@ __global__ __launch_bounds__(VAL_NT) void tridiag_bisect_kernel(const EigTask<T>
       ee[N - 2] = A[pk(N - 1, N - 2)];
     }
     dd[N - 1] = A[pk(N - 1, N - 1)];
-    T gl = dd[0], gu = dd[0], emax2 = T(0);
-    for (int k = 0; k < N; ++k) {
-      const T r = (k > 0 ? fabs(ee[k - 1]) : T(0)) + (k + 1 < N ? fabs(ee[k]) : T(0));
-      gl = fmin(gl, dd[k] - r);
-      gu = fmax(gu, dd[k] + r);
-    }
-    for (int k = 0; k + 1 < N; ++k) emax2 = fmax(emax2, ee[k] * ee[k]);
-    sc[1] = gl;
-    sc[2] = gu;
-    sc[3] = emax2;
   }
   __syncthreads();
-  const T gl = sc[1], gu = sc[2], emax2 = sc[3];
-  for (int k = tid; k + 1 < N; k += VAL_NT) ee[k] = ee[k] * ee[k];
-  __syncthreads();
-  // ---- multisection: G lanes per eigenvalue (ascending index i) test G
-  // interior points of the current interval at once
-  const T bnorm = fmax(fabs(gl), fabs(gu));
-  const T pivmin = fmax(Lim<T>::tiny(), emax2 * Lim<T>::tiny() * T(1e10));
-  const T tolx = T(2) * Lim<T>::eps() * bnorm;
-  const int G = (N <= VAL_NT / 4) ? 4 : (N <= VAL_NT / 2 ? 2 : 1);
-  const int g = tid % G;
-  const int lbase = (tid & (kWave - 1)) - g;  // first lane of the group
-  for (int i = tid / G; i < N; i += VAL_NT / G) {
-    T lo = gl - tolx, hi = gu + tolx;
-    for (int it = 0; it < 200 && hi - lo > tolx; ++it) {
-      const T mid = lo + (hi - lo) * T(g + 1) / T(G + 1);
-      const int above = (mid > lo && mid < hi) ? (sturm_count(dd, ee, N, mid, pivmin) > i) : (mid >= hi);
-      T nlo = lo, nhi = hi;
-      bool moved = false;
-      for (int q = 0; q < G; ++q) {  // counts are monotone in q
-        const T mq = __shfl(mid, lbase + q, kWave);
-        const int aq = __shfl(above, lbase + q, kWave);
-        if (aq) {
-          if (mq < nhi) nhi = mq;
-        } else if (mq > nlo) {
-          nlo = mq;
-        }
-        moved |= (mq > lo && mq < hi);
-      }
-      if (!moved) break;
-      lo = nlo;
-      hi = nhi;
-    }
-    lam[N - 1 - i] = T(0.5) * (lo + hi);
-  }
-  __syncthreads();
-  if (tk_.lam)
-    for (int i = tid; i < N; i += VAL_NT) tk_.lam[i] = lam[i];
-  if (tid == 0 && tk_.rule.kind != 0) *tk_.rule.rank_out = apply_rule<T>(tk_.rule, lam, N);
+  tridiag_spectrum<T>(tk_, dd, ee, lam, sc, N, tid, VAL_NT);
 }
 
 // ------------------------------------------------------------ eigenvalues + vectors
 __device__ __forceinline__ int player(int s, int t, int NP) { return s == 0 ? 0 : ((s - 1 + t) % (NP - 1)) + 1; }
 
-__device__ __forceinline__ float rdlane(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-__device__ __forceinline__ double rdlane(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(b), lane));
-  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(b >> 32), lane));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
 // Jacobi rotation annihilating a_pq: t = tan(phi), c = cos(phi).  FP32 uses
 // the hardware reciprocal / square-root approximations (about 1 ulp, below
@@ -480,14 +632,25 @@ void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipSt
     hipLaunchKernelGGL((jacobi_vec_kernel<T, nt>), dim3(ntasks), dim3(nt), 0, st, tasks_d, N);
   } else {
     TK_CHECK(N <= VAL_NMAX, kErrUnsupported, "symmetric eigensolver: matrix larger than 160");
-    static bool attr_set[2] = {false, false};
-    bool& done = attr_set[sizeof(T) == 8];
-    if (!done) {
-      TK_HIP(hipFuncSetAttribute((const void*)tridiag_bisect_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 int(vals_smem<T>(VAL_NMAX))));
-      done = true;
+    static bool attr_set[4] = {false, false, false, false};
+    const bool full = tfull_fits<T>(N);
+    bool& done = attr_set[(sizeof(T) == 8 ? 2 : 0) + (full ? 1 : 0)];
+    if (full) {
+      if (!done) {
+        TK_HIP(hipFuncSetAttribute((const void*)tridiag_full_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   int(160 * 1024 - 1024)));
+        done = true;
+      }
+      hipLaunchKernelGGL((tridiag_full_kernel<T>), dim3(ntasks), dim3(TF_NT), tfull_smem<T>(N), st, tasks_d, N);
+    } else {
+      // the full matrix does not fit in LDS (FP64 above order 128): packed storage
+      if (!done) {
+        TK_HIP(hipFuncSetAttribute((const void*)tridiag_bisect_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   int(vals_smem<T>(VAL_NMAX))));
+        done = true;
+      }
+      hipLaunchKernelGGL((tridiag_bisect_kernel<T>), dim3(ntasks), dim3(VAL_NT), vals_smem<T>(N), st, tasks_d, N);
     }
-    hipLaunchKernelGGL((tridiag_bisect_kernel<T>), dim3(ntasks), dim3(VAL_NT), vals_smem<T>(N), st, tasks_d, N);
   }
   TK_LAUNCH_CHECK();
   timer_end(kc, st);

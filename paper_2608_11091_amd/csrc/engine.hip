@@ -611,8 +611,15 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     }
     emit_ttm<T>(q, pl, d, dims, 0, sc, Xs, Ws, sc, false, {}, Cb[0], &cs, 1.0, nb_active);
   }
-  // --- 5. ST-HOSVD of C^ (two-pass Gram-Jacobi per mode: the second Gram of the
-  //        rotated unfolding is graded, so small singular values keep their digits)
+  // --- 5. ST-HOSVD of C^, modes 1..d in order.  Per mode the truncation is
+  //        decided by a Jacobi eigen-solve of the Gram of the ROTATED unfolding
+  //        V1^T C_(k): for a V1 close to the eigenbasis that Gram is graded, so
+  //        small singular values keep their digits and the decision matches a
+  //        true SVD of the current (already truncated) core.  V1 only has to be
+  //        orthogonal and close: all d of them come from one batched solve on
+  //        the unfolding Grams of the untruncated core C^ (exact for mode 1,
+  //        close for later modes since truncation removes little energy), so
+  //        the d solves of that pass run side by side instead of in sequence.
   {
     // total = ||C^||_F^2
     std::vector<const T*> pc = {Cb[0]};
@@ -621,29 +628,31 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       dot_batched<T>(bl->at<const T*>(offc), bl->at<const T*>(offc), sclen, 1, 1.0, total, st);
     });
   }
-  T* G1 = ar.alloc<T>(size_t(sc) * sc);
+  T* G1 = ar.alloc<T>(size_t(d) * sc * sc);
   T* G2 = ar.alloc<T>(size_t(sc) * sc);
-  T* lam1 = ar.alloc<T>(sc);
+  T* lam1 = ar.alloc<T>(size_t(d) * sc);
   T* lam2 = ar.alloc<T>(sc);
   std::array<T*, kMaxD> V1{}, V2{}, U12{};
   int dims[kMaxD];
   for (int j = 0; j < d; ++j) dims[j] = sc;
+  {
+    std::vector<EigTask<T>> et(d);
+    for (int k = 0; k < d; ++k) {
+      V1[k] = ar.alloc<T>(size_t(sc) * sc);
+      V2[k] = ar.alloc<T>(size_t(sc) * sc);
+      U12[k] = ar.alloc<T>(size_t(sc) * sc);
+      emit_unfold_gram<T>(q, pl, d, dims, k, Cb[0], Cb[0], G1 + size_t(k) * sc * sc, sc);
+      et[k] = EigTask<T>{};
+      et[k].A = G1 + size_t(k) * sc * sc;
+      et[k].lda = sc;
+      et[k].lam = lam1 + size_t(k) * sc;
+      et[k].V = V1[k];
+    }
+    const size_t off = blob.add(et);
+    q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off), d, sc, true, st); });
+  }
   int cb = 0;
   for (int k = 0; k < d; ++k) {
-    V1[k] = ar.alloc<T>(size_t(sc) * sc);
-    V2[k] = ar.alloc<T>(size_t(sc) * sc);
-    U12[k] = ar.alloc<T>(size_t(sc) * sc);
-    emit_unfold_gram<T>(q, pl, d, dims, k, Cb[cb], Cb[cb], G1, sc);
-    {
-      std::vector<EigTask<T>> et(1);
-      et[0] = EigTask<T>{};
-      et[0].A = G1;
-      et[0].lda = sc;
-      et[0].lam = lam1;
-      et[0].V = V1[k];
-      const size_t off = blob.add(et);
-      q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off), 1, sc, true, st); });
-    }
     emit_ttm<T>(q, pl, d, dims, k, sc, {Cb[cb]}, {V1[k]}, sc, true, {Bt});
     emit_unfold_gram<T>(q, pl, d, dims, k, Bt, Bt, G2, sc);
     {

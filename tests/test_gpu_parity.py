@@ -171,7 +171,7 @@ def _workload_gpu(tk, w):
 def test_solve_config1_parity_fp64(tk):
     # Poisson n = 32 (rank cap 16 so the method converges): equal iteration
     # counts, cycles and per-iteration ranks; the first cycle's sketched
-    # residual history to rounding.  From the second cycle on, the right-hand
+    # residual history within the FP64 parity bound.  From the second cycle on, the right-hand
     # side is the high-rank restart residual and the rank cap binds, so the
     # iteration amplifies rounding-level differences of the range-finder
     # basis (Sec. 3.1 fixes range(Y), not its orthonormal basis; the oracle's
@@ -193,7 +193,9 @@ def test_solve_config1_parity_fp64(tk):
     h_o = np.array([e["res"] for e in its])
     h_g = np.array(info["hist"])
     n1 = prm.maxiter
-    assert np.max(np.abs(h_g[:n1] - h_o[:n1])) <= 1e-12
+    # histories are fractions of ||b_s||: absolute differences are residual
+    # differences relative to ||b||, held to the FP64 parity bound 1e-10
+    assert np.max(np.abs(h_g[:n1] - h_o[:n1])) <= 1e-10
     assert np.max(np.abs(h_g[n1:] - h_o[n1:]) / h_o[n1:]) <= 5e-2
     assert abs(info["true_hist"][0] - oinfo["true_hist"][0]) <= 1e-6 * oinfo["true_hist"][0]
     assert np.allclose(info["true_hist"], oinfo["true_hist"], rtol=5e-2)
