@@ -11,7 +11,7 @@ Steps, in the paper's order:
   4. core projection ``C^ = sum_i G^(i) x_k (U^_k^T U_k^(i))``;
   5. ST-HOSVD of C^ to the tolerance eps.
 
-Readings where the paper leaves a choice (each listed in the design doc):
+Readings where the paper leaves a choice:
   * weights are |c_i| ||G^(i)||_F (the coefficient of a summand scales its
     energy); the Gram is formed on the smaller side (R_k x R_k or n_k x n_k);
   * eigenvalues below ``delta * lambda_max`` (delta = 1e-12, ~30x above the

@@ -12,7 +12,7 @@ Alg. 2 step by step (one cycle, ``sgmres_cycle``):
       if res_k < eta * tol: stop
   X = RoundSum(sum_i y_i V_i)
 
-Readings (listed in the design doc): classical one-pass orthogonalisation (all
+Readings where the paper leaves a choice: classical one-pass orthogonalisation (all
 coefficients from the same W, one RoundSum of 1 + window blocks); y_k is
 computed before the breakdown test; breakdown when ||W|| <= 1e-14 ||RoundSum(L V_k)||
 or the new diagonal of the least-squares R factor is <= 1e-14 ||M||_F; the
@@ -24,7 +24,11 @@ x_0 = 0, r_0 = B; per cycle solve L d = r_c to relative tolerance
 ``tol ||B|| / ||r_c||`` (floored), ``x <- RoundSum(x + d)``, then the exact FP64
 residual ``||B - L(x)|| / ||B||`` (QR of concatenated factors) decides;
 ``r_{c+1} = RoundSum(B - L(x))``.  Two cycles in a row that reduce the true
-residual by less than 10% stop the solve with a rank-floor status.
+residual by less than 10% stop the solve with a rank-floor status.  These
+outer RoundSums use the full sketch width cap + p: the effective-rank rule of
+Sec. 3.1 sizes the sketch from the weighted factor Gram, where a correction d
+far smaller than x (or a residual far smaller than B and L(x)) sits below the
+Gram's rounding level and would be left to the p oversampling columns.
 """
 from __future__ import annotations
 
@@ -136,7 +140,7 @@ def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False
     """Restarted Tucker sGMRES with FP64 iterative refinement."""
     t0 = time.perf_counter()
     eps_out = prm.eps_outer if prm.eps_outer is not None else 1e-2 * prm.tol
-    rpo = RoundParams(eps=eps_out, cap=prm.cap, p=prm.p)
+    rpo = RoundParams(eps=eps_out, cap=prm.cap, p=prm.p, force_s=prm.cap + prm.p)
     rep = _Replay(prm.replay)
     bnorm = exact_norm([(1.0, B)])
     if x0 is None:

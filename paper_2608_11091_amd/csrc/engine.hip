@@ -488,59 +488,81 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     }
     emit_gemm(q, pl, std::move(g));
   }
-  // --- 3. orthonormal basis of every range sketch Y_k (FP64): shifted
-  // Cholesky-QR in three passes (Y -> Q -> Y -> Q ping-pong).  Pass 1 is
+  // --- 3. orthonormal basis of every range sketch Y_k (FP64): Householder QR
+  // when the configuration asks for it, otherwise shifted Cholesky-QR in three
+  // passes (Y -> Q -> Y -> Q ping-pong).  Pass 1 is
   // shifted by 11 (m s + s(s+1)) u tr(Y^T Y), so it never breaks down; pass 2
   // drops only columns at the underflow floor; pass 3 sees a nearly
   // orthonormal input, where a pivot below 1/4 can only come from a
   // rounding-noise column of a rank-deficient Y, and zeroes it.  Live columns
   // come out orthonormal to working accuracy and span range(Y) down to
   // rounding level.
-  double* Gq = ar.alloc<double>(size_t(d) * sc * sc);
-  double* Rq = ar.alloc<double>(size_t(d) * sc * sc);
-  for (auto& modes : modes_by_n<T>(sh)) {
-    const int n = sh.n[modes[0]];
-    for (int k : modes) emit_cast<T>(q, Y[k], Y64[k], size_t(n) * sc);
-    std::vector<CholTask> ct;
-    for (int k : modes) ct.push_back(CholTask{Gq + size_t(k) * sc * sc, Rq + size_t(k) * sc * sc});
-    const size_t coff = blob.add(ct);
-    const int nt = int(ct.size());
-    const double shift1 = 11.0 * (double(n) * sc + double(sc) * (sc + 1)) * 0x1p-53;
-    for (int pass = 0; pass < 3; ++pass) {
-      std::vector<const double*> src;
-      std::vector<double*> dst;
+  if (cfg.householder) {
+    for (auto& modes : modes_by_n<T>(sh)) {
+      const int n = sh.n[modes[0]];
+      std::vector<QrTask> qt;
       for (int k : modes) {
-        src.push_back(pass == 1 ? Q64[k] : Y64[k]);
-        dst.push_back(pass == 1 ? Y64[k] : Q64[k]);
+        emit_cast<T>(q, Y[k], Y64[k], size_t(n) * sc);
+        qt.push_back(QrTask{Y64[k], Q64[k], nullptr, nullptr});
       }
-      GemmDesc<double> g;
-      g.ta = true;
-      g.tb = false;
-      g.M = sc;
-      g.N = sc;
-      g.K = n;
-      g.lda = n;
-      g.ldb = n;
-      g.ldc = sc;
-      for (size_t i = 0; i < modes.size(); ++i) g.group1(Gq + size_t(modes[i]) * sc * sc, src[i], src[i]);
-      emit_gemm(q, pl, std::move(g));
-      const double sh_p = pass == 0 ? shift1 : 0.0;
-      const double drel = pass == 1 ? 1e-30 : 0.0, dabs = pass == 2 ? 0.25 : 0.0;
-      q.steps.push_back(
-          [=](hipStream_t st) { chol_batched(bl->at<CholTask>(coff), nt, sc, s_dev, sh_p, drel, dabs, st); });
-      std::vector<TrsmTask> tt;
-      for (size_t i = 0; i < modes.size(); ++i)
-        tt.push_back(TrsmTask{src[i], Rq + size_t(modes[i]) * sc * sc, dst[i]});
-      const size_t toff = blob.add(tt);
-      q.steps.push_back([=](hipStream_t st) { trsm_rows(bl->at<TrsmTask>(toff), nt, n, sc, s_dev, st); });
+      const size_t off = blob.add(qt);
+      const int nt = int(qt.size());
+      q.steps.push_back([=](hipStream_t st) { qr_batched(bl->at<QrTask>(off), nt, n, sc, s_dev, st); });
+      if (!std::is_same<T, double>::value)
+        for (int k : modes) {
+          double* src = Q64[k];
+          T* dst = Uh[k];
+          const size_t len = size_t(n) * sc;
+          q.steps.push_back([=](hipStream_t st) { cast_copy<double, T>(src, dst, len, st); });
+        }
     }
-    if (!std::is_same<T, double>::value)
-      for (int k : modes) {
-        double* src = Q64[k];
-        T* dst = Uh[k];
-        const size_t len = size_t(n) * sc;
-        q.steps.push_back([=](hipStream_t st) { cast_copy<double, T>(src, dst, len, st); });
+  } else {
+    double* Gq = ar.alloc<double>(size_t(d) * sc * sc);
+    double* Rq = ar.alloc<double>(size_t(d) * sc * sc);
+    for (auto& modes : modes_by_n<T>(sh)) {
+      const int n = sh.n[modes[0]];
+      for (int k : modes) emit_cast<T>(q, Y[k], Y64[k], size_t(n) * sc);
+      std::vector<CholTask> ct;
+      for (int k : modes) ct.push_back(CholTask{Gq + size_t(k) * sc * sc, Rq + size_t(k) * sc * sc});
+      const size_t coff = blob.add(ct);
+      const int nt = int(ct.size());
+      const double shift1 = 11.0 * (double(n) * sc + double(sc) * (sc + 1)) * 0x1p-53;
+      for (int pass = 0; pass < 3; ++pass) {
+        std::vector<const double*> src;
+        std::vector<double*> dst;
+        for (int k : modes) {
+          src.push_back(pass == 1 ? Q64[k] : Y64[k]);
+          dst.push_back(pass == 1 ? Y64[k] : Q64[k]);
+        }
+        GemmDesc<double> g;
+        g.ta = true;
+        g.tb = false;
+        g.M = sc;
+        g.N = sc;
+        g.K = n;
+        g.lda = n;
+        g.ldb = n;
+        g.ldc = sc;
+        for (size_t i = 0; i < modes.size(); ++i) g.group1(Gq + size_t(modes[i]) * sc * sc, src[i], src[i]);
+        emit_gemm(q, pl, std::move(g));
+        const double sh_p = pass == 0 ? shift1 : 0.0;
+        const double drel = pass == 1 ? 1e-30 : 0.0, dabs = pass == 2 ? 0.25 : 0.0;
+        q.steps.push_back(
+            [=](hipStream_t st) { chol_batched(bl->at<CholTask>(coff), nt, sc, s_dev, sh_p, drel, dabs, st); });
+        std::vector<TrsmTask> tt;
+        for (size_t i = 0; i < modes.size(); ++i)
+          tt.push_back(TrsmTask{src[i], Rq + size_t(modes[i]) * sc * sc, dst[i]});
+        const size_t toff = blob.add(tt);
+        q.steps.push_back([=](hipStream_t st) { trsm_rows(bl->at<TrsmTask>(toff), nt, n, sc, s_dev, st); });
       }
+      if (!std::is_same<T, double>::value)
+        for (int k : modes) {
+          double* src = Q64[k];
+          T* dst = Uh[k];
+          const size_t len = size_t(n) * sc;
+          q.steps.push_back([=](hipStream_t st) { cast_copy<double, T>(src, dst, len, st); });
+        }
+    }
   }
   // --- 4. core projection C^ = sum_b c_b G_b x_k (U^_k^T U_bk)
   T* Wb = ar.alloc<T>(size_t(nb) * d * sc * rc);
@@ -910,6 +932,7 @@ void plan_inner(Seq& q, Planner& pl, const Shape& sh, const std::vector<TT<T>>& 
 
 // ====================================================================== exact norm
 void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>& in, double* out_norm2) {
+  constexpr double kCutTol = 64.0 * 0x1p-53;
   const int d = sh.d, rc = sh.rc, nb = in.size();
   Arena& ar = pl.ar;
   Blob* bl = &pl.blob;
@@ -940,6 +963,7 @@ void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>
   double* Xt = ar.alloc<double>(size_t(*std::max_element(sh.n, sh.n + d)) * rc);
   double* Ct = ar.alloc<double>(size_t(Md) * rc);
   double* Rt = ar.alloc<double>(size_t(rc) * rc);
+  double* R2t = ar.alloc<double>(size_t(rc) * rc);
   double* coef = ar.alloc<double>(nb);
   const size_t off_cptr = pl.blob.add(in.cptr), off_cs = pl.blob.add(in.cscale);
   q.steps.push_back([=](hipStream_t st) {
@@ -1010,13 +1034,77 @@ void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>
       } else {
         q.steps.push_back([=](hipStream_t st) { mat_recap<double>(F, n, n, rc, Xt, n, n, rc, st); });
       }
-      std::vector<QrTask> qt = {QrTask{Xt, Q + size_t(i) * rc * n, Rt, facr[k][i]}};
+      double* Qi = Q + size_t(i) * rc * n;
+      // rank-revealing QR of the remainder: columns left with <= 64 u of their
+      // norm in the factor lie (numerically) inside the earlier blocks' span
+      // and are cut; what is cut is below the rounding of the core sum itself
+      std::vector<QrPivTask> qt = {QrPivTask{Xt, F, Qi, Rt, facr[k][i]}};
       const size_t off = pl.blob.add(qt);
       double* Rdiag = Rblk + size_t(i) * rc;
-      q.steps.push_back([=](hipStream_t st) {
-        qr_batched(bl->at<QrTask>(off), 1, n, rc, nullptr, st);
-        mat_recap<double>(Rt, rc, rc, rc, Rdiag, Md, rc, rc, st);
-      });
+      if (i == 0) {
+        q.steps.push_back([=](hipStream_t st) {
+          qr_piv_batched(bl->at<QrPivTask>(off), 1, n, rc, kCutTol, st);
+          mat_recap<double>(Rt, rc, rc, rc, Rdiag, Md, rc, rc, st);
+        });
+        continue;
+      }
+      q.steps.push_back([=](hipStream_t st) { qr_piv_batched(bl->at<QrPivTask>(off), 1, n, rc, kCutTol, st); });
+      // Re-orthogonalise the new block's basis against the previous blocks: a
+      // kept column with remainder norm rho comes out of its QR orthogonal to
+      // the earlier blocks only to about u / rho.  With T = Q_prev^T Q_i and
+      // Q_i - Q_prev T = Q_i' R'': F = Q_prev (C + T R_i) + Q_i' (R'' R_i).
+      const int Kq = i * rc;
+      {  // T = Q_prev^T Q_i -> Ct
+        GemmDesc<double> g;
+        g.ta = true;
+        g.M = Kq;
+        g.N = rc;
+        g.K = n;
+        g.lda = n;
+        g.ldb = n;
+        g.ldc = Md;
+        g.group1(Ct, Q, Qi);
+        emit_gemm(q, pl, std::move(g));
+      }
+      q.steps.push_back([=](hipStream_t st) { mat_recap<double>(Qi, n, n, rc, Xt, n, n, rc, st); });
+      {  // X = Q_i - Q_prev T
+        GemmDesc<double> g;
+        g.M = n;
+        g.N = rc;
+        g.K = Kq;
+        g.lda = n;
+        g.ldb = Md;
+        g.ldc = n;
+        g.beta = 1.0;
+        g.group1(Xt, Q, Ct, nullptr, nullptr, nullptr, -1.0);
+        emit_gemm(q, pl, std::move(g));
+      }
+      std::vector<QrPivTask> qt2 = {QrPivTask{Xt, Qi, Qi, R2t, facr[k][i]}};
+      const size_t off2 = pl.blob.add(qt2);
+      q.steps.push_back([=](hipStream_t st) { qr_piv_batched(bl->at<QrPivTask>(off2), 1, n, rc, kCutTol, st); });
+      {  // R[0:Kq, block i] += T R_i
+        GemmDesc<double> g;
+        g.M = Kq;
+        g.N = rc;
+        g.K = rc;
+        g.lda = Md;
+        g.ldb = rc;
+        g.ldc = Md;
+        g.beta = 1.0;
+        g.group1(Rblk, Ct, Rt);
+        emit_gemm(q, pl, std::move(g));
+      }
+      {  // diagonal block R'' R_i
+        GemmDesc<double> g;
+        g.M = rc;
+        g.N = rc;
+        g.K = rc;
+        g.lda = rc;
+        g.ldb = rc;
+        g.ldc = Md;
+        g.group1(Rdiag, R2t, Rt);
+        emit_gemm(q, pl, std::move(g));
+      }
     }
   }
   // core = sum_b c_b G_b x_k R_k[:, block(b, k)]   (Md^d)

@@ -98,6 +98,10 @@ struct RoundCfg {
   int eig_max = 160;
   int force_s = -1;
   int force_r[kMaxD] = {-1, -1, -1, -1};
+  // range-finder basis by Householder QR (orthonormal to O(u)) instead of the
+  // three-pass Cholesky-QR (O(10-100 u)); used where the sum must be rounded to
+  // full FP64 accuracy (the refinement update and residual)
+  bool householder = false;
 };
 
 // Planning context: arena + shared table blob.

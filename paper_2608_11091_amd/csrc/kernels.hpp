@@ -70,6 +70,19 @@ struct QrTask {
 };
 void qr_batched(const QrTask* tasks_d, int ntasks, int n, int cap, const int* m_dev, hipStream_t st);
 
+// Column-pivoted Householder QR with a rank cut (n <= 512, cap <= 64): columns
+// whose remainder falls to <= drop_tol times their reference norm are left
+// out of the basis.  Q: live basis columns in pivot order (zeros after);
+// R[j][c]: coefficient of input column c on basis column j (cap x cap).
+struct QrPivTask {
+  const double* Y;    // n x cap, ld n
+  const double* ref;  // n x cap, ld n: reference columns for the cut
+  double* Q;          // n x cap, ld n
+  double* R;          // cap x cap
+  const int* m;       // active columns (device), or null = cap
+};
+void qr_piv_batched(const QrPivTask* tasks_d, int ntasks, int n, int cap, double drop_tol, hipStream_t st);
+
 // ---- Cholesky-QR pieces (range-finder QR of RoundSum) ------------------------
 // R = chol(G + s I) for the leading m x m block of a cap x cap Gram (m =
 // min(*m_dev, cap)), with s = shift * trace(G).  A pivot that is not above

@@ -151,6 +151,160 @@ __global__ __launch_bounds__(QR_NT) void qr_kernel(const QrTask* __restrict__ ta
   }
 }
 
+// Column-pivoted Householder QR with a rank cut, for the per-factor blocks of
+// the exact norm.  Each step picks the unchosen column with the largest
+// remaining norm relative to its reference norm (the factor column before
+// projection); once that ratio is <= drop_tol every remaining column is
+// numerically inside the span already built, and the factorisation stops.
+// Outputs Q (live columns in pivot order, zeros after) and R with
+// R[j][c] = coefficient of input column c on basis column j, so that
+// Y = Q R up to the dropped remainders.  Column bookkeeping uses 64-bit masks
+// (uniform across the block), so all register indices stay static.
+__global__ __launch_bounds__(QR_NT) void qr_piv_kernel(const QrPivTask* __restrict__ tasks, int n, int cap,
+                                                       double drop_tol) {
+  __shared__ double red[QR_NW][QR_MC];
+  __shared__ double wv[QR_MC];
+  __shared__ double fref2[QR_MC];
+  __shared__ double tau_s[QR_MC];
+  __shared__ double r2[2][QR_NW];
+  __shared__ int piv_s[QR_MC];
+  __shared__ int inv_s[QR_MC];
+  __shared__ int ctl;
+  const QrPivTask tk_ = tasks[blockIdx.x];
+  const int row = threadIdx.x;
+  const int lane = row & 63, wid = row >> 6;
+  int m = tk_.m ? *tk_.m : cap;
+  m = min(m, cap);
+  const int kmax = min(m, n);
+
+  double a[QR_MC];
+#pragma unroll
+  for (int c = 0; c < QR_MC; ++c) a[c] = (row < n && c < m) ? tk_.Y[row + (size_t)c * n] : 0.0;
+  column_sums(
+      [&](int c) {
+        const double v = (row < n && c < m) ? tk_.ref[row + (size_t)c * n] : 0.0;
+        return v * v;
+      },
+      red, fref2);
+
+  unsigned long long unch = m >= 64 ? ~0ull : ((1ull << m) - 1ull);
+  int nlive = 0;
+  for (int j = 0; j < kmax; ++j) {
+    // squared norms (rows >= j) of the unchosen columns
+    column_sums([&](int c) { return (((unch >> c) & 1ull) && row >= j) ? a[c] * a[c] : 0.0; }, red, wv);
+    if (row == 0) {
+      int best = -1;
+      double br = 0.0;
+      for (int c = 0; c < m; ++c) {
+        if (!((unch >> c) & 1ull) || !(fref2[c] > 0.0)) continue;
+        const double rel = wv[c] / fref2[c];
+        if (rel > br) {
+          br = rel;
+          best = c;
+        }
+      }
+      ctl = (best >= 0 && br > drop_tol * drop_tol) ? best : -1;
+    }
+    __syncthreads();
+    const int p = ctl;
+    if (p < 0) break;
+    unch &= ~(1ull << p);
+    double xj = 0.0;
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c) xj = (c == p) ? a[c] : xj;
+    double va = (row == j) ? xj : 0.0;
+    double vn = (row > j) ? xj * xj : 0.0;
+    va = wave_sum(va);
+    vn = wave_sum(vn);
+    if (lane == 0) {
+      r2[0][wid] = va;
+      r2[1][wid] = vn;
+    }
+    __syncthreads();
+    double alpha = 0.0, xnorm2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < QR_NW; ++q) {
+      alpha += r2[0][q];
+      xnorm2 += r2[1][q];
+    }
+    double beta, tau, scal;
+    if (xnorm2 == 0.0) {
+      beta = alpha;
+      tau = 0.0;
+      scal = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    const double vr = (row == j) ? 1.0 : (row > j ? xj * scal : 0.0);
+    if (tau != 0.0) {
+      column_sums([&](int c) { return ((unch >> c) & 1ull) ? vr * a[c] : 0.0; }, red, wv);
+      const double tv = tau * vr;
+#pragma unroll
+      for (int c = 0; c < QR_MC; ++c)
+        if ((unch >> c) & 1ull) a[c] -= tv * wv[c];
+    } else {
+      __syncthreads();  // keep r2 reads ahead of the next step's writes
+    }
+    const double nj = (row == j) ? beta : (row > j ? vr : xj);
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c) a[c] = (c == p) ? nj : a[c];
+    if (row == 0) {
+      tau_s[j] = tau;
+      piv_s[j] = p;
+    }
+    nlive = j + 1;
+  }
+  __syncthreads();
+
+  // ---------------- R: row j holds the coefficients on basis column j of every
+  // input column chosen at step >= j or never chosen
+  if (tk_.R != nullptr && row < cap) {
+    unsigned long long ok = unch;
+    for (int jj = row; jj < nlive; ++jj) ok |= 1ull << piv_s[jj];
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c)
+      if (c < cap) tk_.R[row + (size_t)c * cap] = (row < nlive && c < m && ((ok >> c) & 1ull)) ? a[c] : 0.0;
+  }
+
+  // ---------------- Q, backward accumulation in place (reflector j stored in column piv[j])
+  unsigned long long later = 0ull;
+  for (int j = nlive - 1; j >= 0; --j) {
+    const int p = piv_s[j];
+    const double tau = tau_s[j];
+    double xj = 0.0;
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c) xj = (c == p) ? a[c] : xj;
+    const double vr = (row == j) ? 1.0 : (row > j ? xj : 0.0);
+    if (later != 0ull && tau != 0.0) {
+      column_sums([&](int c) { return ((later >> c) & 1ull) ? vr * a[c] : 0.0; }, red, wv);
+      const double tv = tau * vr;
+#pragma unroll
+      for (int c = 0; c < QR_MC; ++c)
+        if ((later >> c) & 1ull) a[c] -= tv * wv[c];
+    }
+    const double nj = (row == j) ? 1.0 - tau : (row > j ? -tau * xj : 0.0);
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c) a[c] = (c == p) ? nj : a[c];
+    later |= 1ull << p;
+  }
+  // basis column j sits in register column piv[j]: write it through the
+  // inverse permutation, then zero the columns beyond the rank
+  if (row < QR_MC) inv_s[row] = -1;
+  __syncthreads();
+  if (row < nlive) inv_s[piv_s[row]] = row;
+  __syncthreads();
+  if (row < n) {
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c) {
+      const int j = inv_s[c];
+      if (j >= 0) tk_.Q[row + (size_t)j * n] = a[c];
+    }
+    for (int j = nlive; j < cap; ++j) tk_.Q[row + (size_t)j * n] = 0.0;
+  }
+}
+
 constexpr int CH_NT = 256;
 constexpr int CH_MAX = 64;
 
@@ -265,6 +419,15 @@ void qr_batched(const QrTask* tasks_d, int ntasks, int n, int cap, const int* m_
   TK_CHECK(cap <= QR_MC, kErrUnsupported, "Householder QR: more than 64 columns");
   timer_begin(kKcQr, st);
   hipLaunchKernelGGL(qr_kernel, dim3(ntasks), dim3(QR_NT), 0, st, tasks_d, n, cap, m_dev);
+  TK_LAUNCH_CHECK();
+  timer_end(kKcQr, st);
+}
+
+void qr_piv_batched(const QrPivTask* tasks_d, int ntasks, int n, int cap, double drop_tol, hipStream_t st) {
+  if (ntasks <= 0) return;
+  TK_CHECK(n <= QR_NT && cap <= QR_MC, kErrUnsupported, "pivoted QR: more than 512 rows or 64 columns");
+  timer_begin(kKcQr, st);
+  hipLaunchKernelGGL(qr_piv_kernel, dim3(ntasks), dim3(QR_NT), 0, st, tasks_d, n, cap, drop_tol);
   TK_LAUNCH_CHECK();
   timer_end(kKcQr, st);
 }

@@ -291,6 +291,13 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
   // ---- cycle in the requested precision
   RoundCfg outer;
   outer.eps = 1e-2 * cfg.tol;
+  // full sketch width in the refinement RoundSums: a correction far below x
+  // (a residual far below B and L(x)) is invisible to the effective-rank rule,
+  // whose Gram of weighted factors puts it under its rounding level
+  outer.force_s = sh.sc();
+  // and Householder range-finder bases: the rounding of x + d must keep x to
+  // O(u), or the residual floors at about kappa * 1e-14 (Cholesky-QR bases)
+  outer.householder = true;
   if (cfg.form == 0) {
     s.c64 = std::make_unique<Cycle<double>>();
     auto& c = *s.c64;
@@ -348,7 +355,16 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
   }
   // the first right-hand side is the orthonormalised B
   emit_copy_tt<double>(s.s_setup, sh, s.bo, s.r);
-  emit_copy_tt<double>(s.s_first_x, sh, s.d64, s.x[0]);
+  if (cfg.form != 0) {
+    // FP32 form: the first iterate is the FP64 rounding of the cycle's solution,
+    // like every later update x <- RoundSum(x + d), so that x always carries
+    // FP64-orthonormal factors
+    Blocks<double> fb;
+    fb.add(s.d64, nullptr, 1.0);
+    plan_roundsum<double>(s.s_first_x, pl, sh, fb, outer, omega, s.x[0], nullptr);
+  } else {
+    emit_copy_tt<double>(s.s_first_x, sh, s.d64, s.x[0]);
+  }
   if (x0) {
     s.have_x0 = true;
     emit_copy_tt<double>(s.s_x0, sh, *x0, s.x[0]);

@@ -102,6 +102,34 @@ def test_exact_norm_parity_and_cancellation(tk):
     assert abs(got2 / ref2 - 1.0) < 1e-12
 
 
+def test_exact_norm_rank_deficient_concatenation(tk):
+    # B - L(x) for x = (1 + 1e-8) x8, x8 the rank-8 HOSVD of the exact solution
+    # on a 16-point grid: the distinct factors (B's, x's and L x's) hold
+    # 1 + 8 + 8 columns in R^16, partly inside each other's span, and the sum
+    # cancels to 1e-8 of its blocks.  The block-wise orthogonalisation must
+    # still give the norm of the sum: without re-orthogonalising each block's
+    # basis against the earlier ones it is off by ~5e-3 here; the noise floor
+    # of any FP64 evaluation (dense, oracle) is ~3e-7.
+    from workloads import laplacian_1d
+    n = 16
+    L = laplacian_1d(n)
+    terms = [(float(1.0 + 0.3 * k), [L if j == k else None for j in range(3)]) for k in range(3)]
+    eye = np.eye(n)
+    A = sum(c * np.kron(np.kron(As[0] if As[0] is not None else eye, As[1] if As[1] is not None else eye),
+                        As[2] if As[2] is not None else eye) for c, As in terms)
+    b = np.ones(n) / 4.0
+    xd = np.linalg.solve(A, np.kron(np.kron(b, b), b)).reshape(n, n, n)
+    # compress x to rank 8 per mode (HOSVD), then the residual of that tensor
+    Us = [np.linalg.svd(O.unfold(xd, k), full_matrices=False)[0][:, :8] for k in range(3)]
+    core = O.multi_ttm(xd, [u.T for u in Us]) * (1.0 + 1e-8)
+    X8 = O.Tucker(core, Us)
+    B = O.Tucker(np.ones((1, 1, 1)), [b.reshape(n, 1)] * 3)
+    blocks = [(1.0, B)] + [(-c, T) for c, T in O.apply_op(terms, X8)]
+    ref = O.exact_norm(blocks)
+    got = tk.norm([(c, _gpu(tk, T)) for c, T in blocks])
+    assert abs(got / ref - 1.0) <= 1e-5, (got, ref)
+
+
 def _roundsum_case(rng, n, nb, r, decay=True):
     blocks = []
     for b in range(nb):
