@@ -53,6 +53,32 @@ NOTE = {
 }
 
 
+# HBM traffic of the dominant kernel per launch, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes over this benchmark (each scaled by what the counter reads
+# for a plain copy of known size), valid only for the kernel sources it was
+# measured on: reported as null once any of them changes.
+TRAFFIC = {
+    "jacobi": dict(bytes_per_launch=48399.0,
+                   sources={"paper_2608_11091_amd/csrc/eig.hip":
+                            "cda94ee6d8da2decc55140cf608d38efb87432c0ce821ce0b758a62da0630495",
+                            "paper_2608_11091_amd/csrc/common.hpp":
+                            "8d6d9d994a251521ce45a3795fcac58bda48148c1b1ac227f5fcc0afc2e6fa9b"},
+                   profile="profiles/jacobi_vec_traffic_deblur3d_n512.md"),
+}
+
+
+def _traffic(cls):
+    import hashlib
+    t = TRAFFIC.get(cls)
+    if t is None:
+        return None, None
+    for rel, sha in t["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != sha:
+                return None, None
+    return t["bytes_per_launch"], t["profile"]
+
+
 def _cm(torch, M):
     import numpy as np
     return torch.from_numpy(np.ascontiguousarray(M.T)).cuda()
@@ -90,6 +116,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the run, launch a plain elementwise copy of this many MiB three times "
+                         "(a kernel of known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU path",
@@ -129,7 +158,7 @@ def main():
     torch.cuda.synchronize()
     classes = {}
     for k in CLASSES:
-        n_, ms_, fl_ = tk.kernel_timer_read(k)
+        n_, ms_, fl_, _ = tk.kernel_timer_read(k)
         tk.kernel_timer(k, False)
         classes[k] = dict(launches=n_, total_ms=ms_, avg_us=(ms_ * 1e3 / n_) if n_ else 0.0)
     dom = max(classes, key=lambda k: classes[k]["total_ms"])
@@ -144,7 +173,7 @@ def main():
         infos32.append(i32)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    launches, kms, kflops = tk.kernel_timer_read(dom)
+    launches, kms, kflops, kbytes = tk.kernel_timer_read(dom)
     tk.kernel_timer(dom, False)
 
     iters32 = sum(i["iters"] for i in infos32)
@@ -181,9 +210,11 @@ def main():
     avg_ms = kms / max(launches, 1)
     achieved = (kflops / (kms * 1e-3)) / 1e12 if kms > 0 else 0.0
     bound, peak = BOUND[dom]
+    traffic, traffic_src = _traffic(dom)
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": traffic, "traffic_source": traffic_src,
                 "kernel": KERNEL_NAME[dom], "launches": launches, "avg_launch_us": avg_ms * 1e3,
+                "algorithmic_bytes_per_launch": kbytes / max(launches, 1),
                 "algorithmic_unit": UNIT[dom],
                 "note": NOTE[dom]}
     out = {
@@ -214,6 +245,14 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)   # one elementwise kernel: reads nb bytes, writes nb bytes
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nb
     print(json.dumps(out))
 
 

@@ -182,12 +182,15 @@ int tucker_norm_workspace(const tk_block_sum* x, size_t* bytes);
  * reduction + bisection).  Enabling (or disabling) clears the record; while
  * enabled, every launch of the class records a HIP event pair on its stream.
  * tk_kernel_timer_read synchronises those events and returns the launch count,
- * the summed kernel time in milliseconds and (optional, may be NULL) the
- * summed algorithmic flops of those launches: 2*M*N*K per GEMM product,
- * 9*N^3 per eigendecomposition with vectors, (4/3)*N^3 per eigenvalues-only
- * solve (N = launch order), 0 for the other classes. */
+ * the summed kernel time in milliseconds and (each optional, may be NULL) the
+ * summed algorithmic flops and HBM bytes of those launches.  Flops: 2*M*N*K per
+ * GEMM product, 9*N^3 per eigendecomposition with vectors, (4/3)*N^3 per
+ * eigenvalues-only solve (N = launch order), 0 for the other classes.  Bytes
+ * (eigensolvers only, 0 for the other classes): per matrix, the N*N input read
+ * once plus the N eigenvalues written, plus the N*N eigenvectors written when
+ * they are computed, in the launch's element size. */
 int tk_kernel_timer(int32_t kind, int32_t enable);
-int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, double* flops);
+int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, double* flops, double* bytes);
 
 /* Message of the last error on this thread ("" if none). */
 const char* tk_last_error(void);

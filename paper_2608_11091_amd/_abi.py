@@ -86,7 +86,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.tucker_norm.argtypes = [P(TkBlockSum), P(C.c_double), VP, SZ, VP]
     lib.tucker_norm_workspace.argtypes = [P(TkBlockSum), P(SZ)]
     lib.tk_kernel_timer.argtypes = [C.c_int32, C.c_int32]
-    lib.tk_kernel_timer_read.argtypes = [C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)]
+    lib.tk_kernel_timer_read.argtypes = [C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.tk_last_error.restype = C.c_char_p
     lib.tk_version.restype = C.c_int
     for name in EXPORTS:

@@ -372,12 +372,15 @@ def kernel_timer(kind: str, enable: bool) -> None:
 
 
 def kernel_timer_read(kind: str):
-    """(launches, total kernel milliseconds, algorithmic flops) since enabling."""
+    """(launches, total kernel milliseconds, algorithmic flops, algorithmic
+    bytes) since enabling."""
     n = C.c_int64()
     ms = C.c_double()
     fl = C.c_double()
-    check(_abi.load().tk_kernel_timer_read(KERNEL_CLASSES[kind], C.byref(n), C.byref(ms), C.byref(fl)))
-    return int(n.value), float(ms.value), float(fl.value)
+    by = C.c_double()
+    check(_abi.load().tk_kernel_timer_read(KERNEL_CLASSES[kind], C.byref(n), C.byref(ms), C.byref(fl),
+                                           C.byref(by)))
+    return int(n.value), float(ms.value), float(fl.value), float(by.value)
 
 
 def storage_floats(n: Sequence[int], ranks: Sequence[int]) -> int:

@@ -588,12 +588,13 @@ int tk_kernel_timer(int32_t kind, int32_t enable) {
     return 0;
   });
 }
-int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, double* flops) {
+int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, double* flops, double* bytes) {
   return guarded([&] {
     TK_CHECK(kind >= 0 && kind < kKcCount && launches && total_ms, kErrInvalidArg, "bad timer query");
-    double f = 0.0;
-    timer_read(kind, launches, total_ms, &f);
+    double f = 0.0, b = 0.0;
+    timer_read(kind, launches, total_ms, &f, &b);
     if (flops) *flops = f;
+    if (bytes) *bytes = b;
     return 0;
   });
 }

@@ -156,10 +156,10 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
 // when enabled, launches of that class record an event pair on their stream.
 enum KernelClass : int { kKcGemm = 0, kKcJacobi = 1, kKcQr = 2, kKcKrp = 3, kKcLs = 4, kKcEigVals = 5, kKcCount = 6 };
 bool timer_on(int kind);
-void timer_begin(int kind, hipStream_t st, double flops = 0.0);
+void timer_begin(int kind, hipStream_t st, double flops = 0.0, double bytes = 0.0);
 void timer_end(int kind, hipStream_t st);
 void timer_enable(int kind, bool on);
-void timer_read(int kind, int64_t* launches, double* total_ms, double* total_flops);
+void timer_read(int kind, int64_t* launches, double* total_ms, double* total_flops, double* total_bytes);
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 inline int64_t ipow(int64_t b, int e) {

@@ -454,20 +454,25 @@ __device__ __forceinline__ void jac_rot(double app, double aqq, double apq, doub
 
 // One lane per matrix row, one wave per rotation pair.  A round applies the
 // N/2 disjoint rotations of the round-robin ordering as A <- J^T (A J): first
-// the column pairs (p, q) in place (and V <- V J), then the row pairs in place
-// (rows of different pairs are disjoint), with the 2x2 pivot blocks set to
-// their exact diagonal form.  Every wave computes all angles of the round in
-// its lanes (identical arithmetic, so identical decisions in every wave) and
-// fetches the ones of its pairs with readlane; a wave issues the loads of all
-// its pairs before any store, and there are two barriers per round.
+// the column pairs (p, q) from A into the second buffer B = A J (and V <- V J
+// in place), then the row pairs from B back into A (rows of different pairs
+// are disjoint), with the 2x2 pivot blocks set to their exact diagonal form.
+// Every wave computes all angles of the round in its lanes from A, which no
+// wave writes between the row phase of one round and the row phase of the
+// next, so every wave sees the same values and takes identical decisions
+// (which pairs rotate, whether the round and the sweep rotate anything); a
+// round in which no pair rotates is skipped by all waves together, barriers
+// included.  A wave issues the loads of all its pairs before any store, and an
+// executed round has two barriers.
 template <typename T, int JV_NT>
 __global__ __launch_bounds__(JV_NT) void jacobi_vec_kernel(const EigTask<T>* __restrict__ tasks, int N) {
   constexpr int JV_NW = JV_NT / kWave;
   constexpr int JV_PPW = (VEC_NMAX / 2) / JV_NW;  // pair slots per wave
   constexpr int LD = VEC_NMAX + 1;
-  __shared__ T AV[2][VEC_NMAX][LD];  // A = AV[0], V = AV[1], both [col][row]
+  __shared__ T AV[3][VEC_NMAX][LD];  // A = AV[0], V = AV[1], B = AV[2], all [col][row]
   auto& A = AV[0];
   auto& V = AV[1];
+  auto& B = AV[2];
   __shared__ int rank_s;
   __shared__ int posv[VEC_NMAX];
   __shared__ T lam_s[VEC_NMAX];
@@ -485,6 +490,7 @@ __global__ __launch_bounds__(JV_NT) void jacobi_vec_kernel(const EigTask<T>* __r
     T a = T(0);
     if (i < N && j < N) a = (i >= j) ? tk_.A[i + (size_t)j * tk_.lda] : tk_.A[j + (size_t)i * tk_.lda];
     A[j][i] = a;
+    B[j][i] = T(0);
     V[j][i] = (i == j) ? T(1) : T(0);
   }
   __syncthreads();
@@ -519,6 +525,7 @@ __global__ __launch_bounds__(JV_NT) void jacobi_vec_kernel(const EigTask<T>* __r
       if (++s2 == NP - 1) s2 = 0;
       const unsigned long long fm = __ballot(flag);
       anyrot |= fm;
+      if (fm == 0) continue;  // wave-uniform and equal in every wave (see above)
       int P_[JV_PPW], Q_[JV_PPW];
       T C_[JV_PPW], S_[JV_PPW];
 #pragma unroll
@@ -539,12 +546,12 @@ __global__ __launch_bounds__(JV_NT) void jacobi_vec_kernel(const EigTask<T>* __r
           vp[i] = V[P_[i]][lane];
           vq[i] = V[Q_[i]][lane];
         }
-        // slots without a real pair (P == Q) store back unchanged values (c = 1, s = 0)
+        // slots without a real pair (P == Q) copy unchanged values (c = 1, s = 0)
 #pragma unroll
         for (int i = 0; i < JV_PPW; ++i) {
           const T cc = C_[i], ss = S_[i];
-          A[P_[i]][lane] = cc * ap[i] - ss * aq[i];
-          A[Q_[i]][lane] = ss * ap[i] + cc * aq[i];
+          B[P_[i]][lane] = cc * ap[i] - ss * aq[i];
+          B[Q_[i]][lane] = ss * ap[i] + cc * aq[i];
           V[P_[i]][lane] = cc * vp[i] - ss * vq[i];
           V[Q_[i]][lane] = ss * vp[i] + cc * vq[i];
         }
@@ -555,8 +562,8 @@ __global__ __launch_bounds__(JV_NT) void jacobi_vec_kernel(const EigTask<T>* __r
         T bp[JV_PPW], bq[JV_PPW];
 #pragma unroll
         for (int i = 0; i < JV_PPW; ++i) {
-          bp[i] = A[lane][P_[i]];
-          bq[i] = A[lane][Q_[i]];
+          bp[i] = B[lane][P_[i]];
+          bq[i] = B[lane][Q_[i]];
         }
 #pragma unroll
         for (int i = 0; i < JV_PPW; ++i) {
@@ -624,7 +631,8 @@ void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipSt
   // reduction behind the eigenvalues-only path
   const int kc = want_v ? kKcJacobi : kKcEigVals;
   const double nn = double(N);
-  timer_begin(kc, st, double(ntasks) * (want_v ? 9.0 : 4.0 / 3.0) * nn * nn * nn);
+  timer_begin(kc, st, double(ntasks) * (want_v ? 9.0 : 4.0 / 3.0) * nn * nn * nn,
+              double(ntasks) * sizeof(T) * ((want_v ? 2.0 : 1.0) * nn * nn + nn));
   if (want_v) {
     TK_CHECK(N <= VEC_NMAX, kErrUnsupported, "symmetric eigensolver: eigenvectors above size 64");
     // measured on gfx950 (N = 53): 16 waves for FP32, 8 for FP64 (register pressure)

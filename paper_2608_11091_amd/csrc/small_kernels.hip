@@ -146,15 +146,17 @@ struct TimerState {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   double flops = 0.0;
+  double bytes = 0.0;
 };
 TimerState g_timers[kKcCount];
 }  // namespace
 
 bool timer_on(int kind) { return kind >= 0 && kind < kKcCount && g_timers[kind].on; }
 
-void timer_begin(int kind, hipStream_t st, double flops) {
+void timer_begin(int kind, hipStream_t st, double flops, double bytes) {
   if (!timer_on(kind)) return;
   g_timers[kind].flops += flops;
+  g_timers[kind].bytes += bytes;
   hipEvent_t a, b;
   TK_HIP(hipEventCreate(&a));
   TK_HIP(hipEventCreate(&b));
@@ -175,10 +177,11 @@ void timer_enable(int kind, bool on) {
   }
   t.ev.clear();
   t.flops = 0.0;
+  t.bytes = 0.0;
   t.on = on;
 }
 
-void timer_read(int kind, int64_t* launches, double* total_ms, double* total_flops) {
+void timer_read(int kind, int64_t* launches, double* total_ms, double* total_flops, double* total_bytes) {
   TimerState& t = g_timers[kind];
   double tot = 0.0;
   for (auto& e : t.ev) {
@@ -190,6 +193,7 @@ void timer_read(int kind, int64_t* launches, double* total_ms, double* total_flo
   *launches = int64_t(t.ev.size());
   *total_ms = tot;
   *total_flops = t.flops;
+  *total_bytes = t.bytes;
 }
 
 template void zero_sum_fixup<double>(const double*, const double*, int, const int*, int, double* const*, double*,
