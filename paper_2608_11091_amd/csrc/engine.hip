@@ -218,6 +218,40 @@ void emit_cast<float>(Seq& q, const float* src, double* dst, size_t len) {
   q.steps.push_back([=](hipStream_t st) { cast_copy<float, double>(src, dst, len, st); });
 }
 
+// Fork/join of a plan section onto the side stream: the section starts after
+// everything issued before it on the caller's stream, and the caller's stream
+// waits for the section at the join.  The events live as long as the plan.
+struct ForkJoin {
+  hipEvent_t fork = nullptr, join = nullptr;
+  ForkJoin() {
+    TK_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    TK_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  }
+  ~ForkJoin() {
+    (void)hipEventSynchronize(join);  // a plan may be dropped right after it was issued
+    (void)hipEventDestroy(fork);
+    (void)hipEventDestroy(join);
+  }
+  ForkJoin(const ForkJoin&) = delete;
+  ForkJoin& operator=(const ForkJoin&) = delete;
+};
+
+// Moves steps [from, end) of q onto the side stream between a fork and the
+// join record; the returned step makes the caller's stream wait for them.
+std::function<void(hipStream_t)> fork_steps(Seq& q, size_t from) {
+  auto fj = std::make_shared<ForkJoin>();
+  std::vector<std::function<void(hipStream_t)>> sec(q.steps.begin() + from, q.steps.end());
+  q.steps.resize(from);
+  q.steps.push_back([fj, sec](hipStream_t st) {
+    hipStream_t side = side_stream();
+    TK_HIP(hipEventRecord(fj->fork, st));
+    TK_HIP(hipStreamWaitEvent(side, fj->fork, 0));
+    for (auto& f : sec) f(side);
+    TK_HIP(hipEventRecord(fj->join, side));
+  });
+  return [fj](hipStream_t st) { TK_HIP(hipStreamWaitEvent(st, fj->join, 0)); };
+}
+
 }  // namespace
 
 // ====================================================================== RoundSum
@@ -274,8 +308,16 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     zero_threshold(w, nbA(), zero_tol, zthr, st);
   });
 
-  // --- 1. effective-rank heuristic (Gram eigenvalues) -> sketch width
-  if (cfg.force_s < 0) {
+  // --- 1. effective-rank heuristic (Gram eigenvalues) -> sketch width.  With
+  //        Cholesky-QR the rule runs on the side stream beside steps 2-3: the
+  //        range sketch is formed at the full capacity width sc, and the QR runs
+  //        over all sc columns (Cholesky-QR is nested: the leading s columns
+  //        of Q only depend on the leading s columns of Y), so only the
+  //        zeroing of the columns beyond s waits for the rule.
+  const bool rule = cfg.force_s < 0;
+  const bool overlap = rule && !cfg.householder;
+  const size_t rule_from = q.steps.size();
+  if (rule) {
     for (auto& modes : modes_by_n<T>(sh)) {
       const int n = sh.n[modes[0]];
       if (n <= cfg.eig_max) {
@@ -366,10 +408,15 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       }
     }
   }
-  {
-    const int p = sh.p, cap = sh.cap, fs = cfg.force_s;
-    q.steps.push_back([=](hipStream_t st) { sketch_width(rt, d, p, cap, fs, s_dev, st); });
-  }
+  std::function<void(hipStream_t)> join;
+  const int p_ = sh.p, cap_ = sh.cap, fs_ = cfg.force_s;
+  auto emit_width = [&]() {
+    q.steps.push_back([=](hipStream_t st) { sketch_width(rt, d, p_, cap_, fs_, s_dev, st); });
+  };
+  if (overlap)
+    join = fork_steps(q, rule_from);
+  else
+    emit_width();
 
   // --- 2. Khatri-Rao range sketch Y_k = sum_b c_b U_bk MTTKRP(G_b; M_b, k)
   T* Mb = ar.alloc<T>(size_t(nb) * d * rc * sc);
@@ -547,13 +594,14 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
         emit_gemm(q, pl, std::move(g));
         const double sh_p = pass == 0 ? shift1 : 0.0;
         const double drel = pass == 1 ? 1e-30 : 0.0, dabs = pass == 2 ? 0.25 : 0.0;
+        const int* mq = overlap ? nullptr : s_dev;
         q.steps.push_back(
-            [=](hipStream_t st) { chol_batched(bl->at<CholTask>(coff), nt, sc, s_dev, sh_p, drel, dabs, st); });
+            [=](hipStream_t st) { chol_batched(bl->at<CholTask>(coff), nt, sc, mq, sh_p, drel, dabs, st); });
         std::vector<TrsmTask> tt;
         for (size_t i = 0; i < modes.size(); ++i)
           tt.push_back(TrsmTask{src[i], Rq + size_t(modes[i]) * sc * sc, dst[i]});
         const size_t toff = blob.add(tt);
-        q.steps.push_back([=](hipStream_t st) { trsm_rows(bl->at<TrsmTask>(toff), nt, n, sc, s_dev, st); });
+        q.steps.push_back([=](hipStream_t st) { trsm_rows(bl->at<TrsmTask>(toff), nt, n, sc, mq, st); });
       }
       if (!std::is_same<T, double>::value)
         for (int k : modes) {
@@ -562,6 +610,16 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
           const size_t len = size_t(n) * sc;
           q.steps.push_back([=](hipStream_t st) { cast_copy<double, T>(src, dst, len, st); });
         }
+    }
+  }
+  if (overlap) {
+    // join the rule, then keep the leading s columns of every basis
+    q.steps.push_back(join);
+    emit_width();
+    for (int k = 0; k < d; ++k) {
+      T* u = Uh[k];
+      const int n = sh.n[k];
+      q.steps.push_back([=](hipStream_t st) { zero_cols_from<T>(u, n, n, sc, s_dev, st); });
     }
   }
   // --- 4. core projection C^ = sum_b c_b G_b x_k (U^_k^T U_bk)

@@ -53,6 +53,12 @@ void cast_copy(const A* x, B* y, size_t len, hipStream_t st);
 // outside the valid region are zero.
 template <typename T>
 void core_recap(const T* src, const int* sd, const int* sv, T* dst, const int* dd, int d, hipStream_t st);
+// Zero columns [*from_dev, cols) of a column-major rows x cols matrix.
+template <typename T>
+void zero_cols_from(T* A, int ld, int rows, int cols, const int* from_dev, hipStream_t st);
+// Side stream of the current device (created on first use: non-blocking,
+// default priority) for work that a plan runs beside the caller's stream.
+hipStream_t side_stream();
 // Copy the leading rows x cols of a column-major matrix (zero-filling dst beyond src).
 template <typename T>
 void mat_recap(const T* src, int ld_src, int rows_src, int cols_src, T* dst, int ld_dst, int rows_dst,

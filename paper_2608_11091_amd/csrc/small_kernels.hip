@@ -1,5 +1,8 @@
 // Small bookkeeping kernels: coefficient gathering, zero-sum fix-up,
 // accumulation, vector sums and the per-iteration status record.
+#include <map>
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace tk {
@@ -51,6 +54,16 @@ __global__ void sum_vectors_kernel(const T* base, size_t stride, int nb, int len
   double s = 0.0;
   for (int b = 0; b < nb; ++b) s += double(base[b * stride + l]);
   out[l] = s;
+}
+
+template <typename T>
+__global__ void zero_cols_from_kernel(T* A, int ld, int rows, int cols, const int* from_dev) {
+  const int from = max(*from_dev, 0);
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t len = size_t(rows) * cols;
+  if (e >= len) return;
+  const int c = int(e / rows), r = int(e % rows);
+  if (c >= from) A[r + size_t(c) * ld] = T(0);
 }
 
 __global__ void copy_ints_kernel(const int* src, int* dst, int n) {
@@ -122,6 +135,28 @@ template <typename T>
 void sum_vectors(const T* base, size_t stride, int nb, int len, double* out, hipStream_t st) {
   hipLaunchKernelGGL((sum_vectors_kernel<T>), dim3(ceil_div(len, 256)), dim3(256), 0, st, base, stride, nb, len, out);
   TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void zero_cols_from(T* A, int ld, int rows, int cols, const int* from_dev, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL((zero_cols_from_kernel<T>), dim3(gsz(size_t(rows) * cols)), dim3(256), 0, st, A, ld, rows, cols,
+                     from_dev);
+  TK_LAUNCH_CHECK();
+}
+
+hipStream_t side_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  TK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t s = nullptr;
+  TK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  streams[dev] = s;
+  return s;
 }
 
 void copy_ints(const int* src, int* dst, int n, hipStream_t st) {
@@ -200,6 +235,8 @@ template void zero_sum_fixup<double>(const double*, const double*, int, const in
                                      size_t, int*, hipStream_t);
 template void zero_sum_fixup<float>(const double*, const double*, int, const int*, int, float* const*, float*, size_t,
                                     int*, hipStream_t);
+template void zero_cols_from<double>(double*, int, int, int, const int*, hipStream_t);
+template void zero_cols_from<float>(float*, int, int, int, const int*, hipStream_t);
 template void mat_axpy<double>(const double*, int, double*, int, int, int, hipStream_t);
 template void mat_axpy<float>(const float*, int, float*, int, int, int, hipStream_t);
 template void sum_vectors<double>(const double*, size_t, int, int, double*, hipStream_t);
