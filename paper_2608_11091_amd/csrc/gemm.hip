@@ -27,7 +27,13 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
 }
 
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int SA = (BM * BK) / NT, SB = (BN * BK) / NT;  // staged elements per thread
 
+// Split-K: the (term, K-slab) iteration space of a group is divided evenly
+// over `splits` workgroups per output tile; each writes its partial tile and a
+// second pass sums the partials in split order.  (Summing them in the last
+// workgroup to arrive at a tile needs device-scope fences, whose L2
+// write-back across the XCDs cost more than the second launch.)
 template <typename T, bool TA, bool TB>
 __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, int ldb, int ldc,
                                                   const GemmTerm<T>* __restrict__ terms,
@@ -53,19 +59,34 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
 
-  // The (term, K-slab) iteration space of the group is split evenly over
-  // `splits` workgroups; each sums its slabs in order.
   const int t1 = min(grp.t1, grp.t0 + max_terms);
   const int nterm = max(0, t1 - grp.t0);
   const int nks = (K + BK - 1) / BK;
   const int total = nterm * nks;
   const int per = (total + splits - 1) / splits;
   const int sb = sp * per, se = min(total, sb + per);
+
+  // staging coordinates of this thread (fixed over slabs)
+  int am[SA], ak[SA], bn[SB], bk[SB];
+#pragma unroll
+  for (int i = 0; i < SA; ++i) {
+    if (!TA) { am[i] = tid & 63; ak[i] = (tid >> 6) + 4 * i; }
+    else { ak[i] = tid & 15; am[i] = (tid >> 4) + 16 * i; }
+  }
+#pragma unroll
+  for (int i = 0; i < SB; ++i) {
+    if (!TB) { bk[i] = tid & 15; bn[i] = (tid >> 4) + 16 * i; }
+    else { bn[i] = tid & 63; bk[i] = (tid >> 6) + 4 * i; }
+  }
+  // Slab s is fetched into registers one slab ahead of its use, so its global
+  // loads are in flight while the matrix cores work on slab s - 1.  A term
+  // with alpha == 0 stages zeros (its operands are never read).
   int cur = -1;
   T alpha = T(0);
   const T* Ap = nullptr;
   const T* Bp = nullptr;
-  for (int slab = sb; slab < se; ++slab) {
+  T ra[SA], rb[SB];
+  auto fetch = [&](int slab) {
     const int t = grp.t0 + slab / nks;
     const int k0 = (slab % nks) * BK;
     if (t != cur) {
@@ -79,30 +100,30 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
       Bp = tm.B;
       cur = t;
     }
-    if (alpha == T(0)) continue;
-    // stage op(A)[m0:m0+BM, k0:k0+BK] -> As[k][m]
+    const bool live = alpha != T(0);
 #pragma unroll
-    for (int i = 0; i < (BM * BK) / NT; ++i) {
-      int m, k;
-      if (!TA) { m = tid & 63; k = (tid >> 6) + 4 * i; }
-      else { k = tid & 15; m = (tid >> 4) + 16 * i; }
-      const int gm = m0 + m, gk = k0 + k;
+    for (int i = 0; i < SA; ++i) {
+      const int gm = m0 + am[i], gk = k0 + ak[i];
       T v = T(0);
-      if (gm < M && gk < K) v = TA ? Ap[gk + (size_t)gm * lda] : Ap[gm + (size_t)gk * lda];
-      As[k][m] = v * alpha;
+      if (live && gm < M && gk < K) v = (TA ? Ap[gk + (size_t)gm * lda] : Ap[gm + (size_t)gk * lda]) * alpha;
+      ra[i] = v;
     }
-    // stage op(B)[k0:k0+BK, n0:n0+BN] -> Bs[k][n]
 #pragma unroll
-    for (int i = 0; i < (BN * BK) / NT; ++i) {
-      int n, k;
-      if (!TB) { k = tid & 15; n = (tid >> 4) + 16 * i; }
-      else { n = tid & 63; k = (tid >> 6) + 4 * i; }
-      const int gn = n0 + n, gk = k0 + k;
+    for (int i = 0; i < SB; ++i) {
+      const int gn = n0 + bn[i], gk = k0 + bk[i];
       T v = T(0);
-      if (gn < N && gk < K) v = TB ? Bp[gn + (size_t)gk * ldb] : Bp[gk + (size_t)gn * ldb];
-      Bs[k][n] = v;
+      if (live && gn < N && gk < K) v = TB ? Bp[gn + (size_t)gk * ldb] : Bp[gk + (size_t)gn * ldb];
+      rb[i] = v;
     }
+  };
+  if (sb < se) fetch(sb);
+  for (int slab = sb; slab < se; ++slab) {
+#pragma unroll
+    for (int i = 0; i < SA; ++i) As[ak[i]][am[i]] = ra[i];
+#pragma unroll
+    for (int i = 0; i < SB; ++i) Bs[bk[i]][bn[i]] = rb[i];
     __syncthreads();
+    if (slab + 1 < se) fetch(slab + 1);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
