@@ -1,11 +1,9 @@
 // Small symmetric eigensolvers, one workgroup per matrix.
 //
 //  * Eigenvalues only (N <= 160): Householder reduction to tridiagonal form
-//    with the full matrix in LDS, one lane per row and the trailing columns
-//    dealt out to 16 waves (a packed-storage variant serves FP64 orders whose
-//    full matrix does not fit in LDS), then every eigenvalue by multisection
-//    on Sturm counts.  Used by the RoundSum effective-rank rule, which needs
-//    the spectrum but no vectors.
+//    with the matrix distributed over the registers of 16 waves, then every
+//    eigenvalue by multisection on Sturm counts.  Used by the RoundSum
+//    effective-rank rule, which needs the spectrum but no vectors.
 //  * Eigenvalues and vectors (N <= 64): cyclic Jacobi with the round-robin
 //    parallel ordering, full matrix and eigenvector block in LDS, one lane
 //    per row and one wave per rotation pair.  A rotation is taken only when
@@ -22,9 +20,7 @@ namespace tk {
 
 namespace {
 
-constexpr int VAL_NT = 512;
 constexpr int VAL_NMAX = 160;
-constexpr int TG = 4;  // threads per row in the tridiagonal reduction
 constexpr int VEC_NMAX = 64;
 
 template <typename T> struct Lim;
@@ -36,8 +32,6 @@ template <> struct Lim<float> {
   static __device__ constexpr float eps() { return FLT_EPSILON; }
   static __device__ constexpr float tiny() { return 1e-37f; }
 };
-
-__device__ __forceinline__ int pk(int i, int j) { return i >= j ? (i * (i + 1)) / 2 + j : (j * (j + 1)) / 2 + i; }
 
 // Rank rules on a descending spectrum; returns the rank (run by one thread).
 template <typename T>
@@ -165,28 +159,27 @@ __device__ void tridiag_spectrum(const EigTask<T>& tk_, T* dd, T* ee, T* lam, T*
   if (tid == 0 && tk_.rule.kind != 0) *tk_.rule.rank_out = apply_rule<T>(tk_.rule, lam, N);
 }
 
-constexpr int TF_NT = 1024;
-constexpr int TF_NW = TF_NT / kWave;
-constexpr int TF_CH = (VAL_NMAX + kWave - 1) / kWave;  // row chunks of 64
+// Householder tridiagonalisation with the matrix in registers: lane l of
+// wave w of W holds the entries (l + 64 a, w + W b), a < 3, so the rank-2
+// update of a step touches only registers and LDS carries vectors and partial
+// sums, never the matrix.  Step j: the wave holding column j forms v (the
+// Householder vector of the part below the diagonal) and tau; every thread
+// forms its partial products of A_sub v and of v^T A_sub v, which are summed
+// across the waves through LDS into p = tau A_sub v and
+// w = p - (tau^2 / 2)(v^T A_sub v) v; every thread applies
+// A_sub -= v w^T + w v^T to its entries.  Vectors alternate between two LDS
+// buffers with the step parity.  Then the spectrum as above.
+constexpr int TRG_RR = (VAL_NMAX + kWave - 1) / kWave;  // rows per thread
 
+// 16 waves (FP64 spills some registers; 8 waves with twice the entries per
+// thread spill more)
 template <typename T>
-size_t tfull_smem(int NL) {
-  return sizeof(T) * (size_t(NL) * (NL + 1) + size_t(TF_NW) * NL + 5 * size_t(NL)) + 64;
-}
-template <typename T>
-bool tfull_fits(int NL) {
-  return tfull_smem<T>(NL) <= size_t(160 * 1024 - 1024);
-}
+constexpr int trg_nt() { return 1024; }
 
-// Householder tridiagonalisation with the full matrix in LDS, column-major
-// (A[col * LDA + row]), one lane per row and the trailing columns dealt out
-// to the 16 waves: step j forms v from column j (every wave, in registers),
-// the partial products A_sub v per wave, p = tau * A_sub v and
-// w = p - (tau/2)(v.p) v, and the rank-2 update A_sub -= v w^T + w v^T of
-// each wave's columns.  Then the spectrum as above.
-template <typename T>
-__global__ __launch_bounds__(TF_NT) void tridiag_full_kernel(const EigTask<T>* __restrict__ tasks, int NL) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+template <typename T, int TRG_NT>
+__global__ __launch_bounds__(TRG_NT) void tridiag_reg_kernel(const EigTask<T>* __restrict__ tasks, int NL) {
+  constexpr int TRG_NW = TRG_NT / kWave;                   // waves
+  constexpr int TRG_RC = (VAL_NMAX + TRG_NW - 1) / TRG_NW;  // columns per thread
   const EigTask<T> tk_ = tasks[blockIdx.x];
   int N = NL;
   if (tk_.ndyn != nullptr) {
@@ -201,36 +194,53 @@ __global__ __launch_bounds__(TF_NT) void tridiag_full_kernel(const EigTask<T>* _
     if (threadIdx.x == 0 && tk_.rule.rank_out) *tk_.rule.rank_out = 0;
     return;
   }
-  const int LDA = NL + 1;
-  T* A = reinterpret_cast<T*>(smem_raw);
-  T* pp = A + size_t(NL) * LDA;  // [TF_NW][NL] partial products
-  T* vb = pp + TF_NW * NL;       // Householder vector by absolute row
-  T* wb = vb + NL;               // w by absolute row
-  T* dd = wb + NL;
-  T* ee = dd + NL;
-  T* lam = ee + NL;
-  __shared__ T red[TF_NW];
+  __shared__ T vb[2][VAL_NMAX], wb[2][VAL_NMAX];
+  __shared__ T pp[TRG_NW][VAL_NMAX];
+  __shared__ T qs[TRG_NW];
+  __shared__ T tau_s[2];
+  __shared__ T dd[VAL_NMAX], ee[VAL_NMAX], lam[VAL_NMAX];
   __shared__ T sc[4];
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-  for (int e = tid; e < N * N; e += TF_NT) {
-    const int i = e % N, j = e / N;
-    A[j * LDA + i] = (i >= j) ? tk_.A[i + (size_t)j * tk_.lda] : tk_.A[j + (size_t)i * tk_.lda];
+  for (int e = tid; e < 2 * VAL_NMAX; e += TRG_NT) {
+    vb[e / VAL_NMAX][e % VAL_NMAX] = T(0);
+    wb[e / VAL_NMAX][e % VAL_NMAX] = T(0);
   }
-  __syncthreads();
-  for (int j = 0; j + 2 < N; ++j) {
-    const int r0 = j + 1;
-    T xs[TF_CH], vs[TF_CH];
+  T a[TRG_RR][TRG_RC];
+#pragma unroll
+  for (int i = 0; i < TRG_RR; ++i)
+#pragma unroll
+    for (int k = 0; k < TRG_RC; ++k) {
+      const int r = lane + kWave * i, c = wave + TRG_NW * k;
+      T v = T(0);
+      if (r < N && c < N) v = (r >= c) ? tk_.A[r + (size_t)c * tk_.lda] : tk_.A[c + (size_t)r * tk_.lda];
+      a[i][k] = v;
+    }
+  // Householder vector of column jj from this wave's registers (called by the
+  // wave holding column jj only; jj + 2 < N)
+  auto householder = [&](int jj) {
+    const int buf = jj & 1;
+    const int r0 = jj + 1;
+    const int kb = jj / TRG_NW;  // uniform
+    T x[TRG_RR];
     T s2 = T(0);
 #pragma unroll
-    for (int c = 0; c < TF_CH; ++c) {
-      const int row = r0 + lane + kWave * c;
-      xs[c] = row < N ? A[j * LDA + row] : T(0);
-      if (row > r0 && row < N) s2 += xs[c] * xs[c];
+    for (int i = 0; i < TRG_RR; ++i) {
+      T v = T(0);
+#pragma unroll
+      for (int k = 0; k < TRG_RC; ++k)
+        if (k == kb) v = a[i][k];
+      x[i] = v;
+      const int r = lane + kWave * i;
+      if (r > r0 && r < N) s2 += v * v;
     }
     s2 = wave_sum(s2);
-    const T alpha = rdlane(xs[0], 0);
+    T xa = T(0);
+#pragma unroll
+    for (int i = 0; i < TRG_RR; ++i)
+      if (i == r0 / kWave) xa = x[i];
+    const T alpha = rdlane(xa, r0 & (kWave - 1));
     T beta, tau, scal;
     if (s2 == T(0)) {
       beta = alpha;
@@ -242,189 +252,91 @@ __global__ __launch_bounds__(TF_NT) void tridiag_full_kernel(const EigTask<T>* _
       scal = T(1) / (alpha - beta);
     }
 #pragma unroll
-    for (int c = 0; c < TF_CH; ++c) {
-      const int row = r0 + lane + kWave * c;
-      vs[c] = row == r0 ? T(1) : xs[c] * scal;
-      if (wave == 0 && row < N) vb[row] = vs[c];
+    for (int i = 0; i < TRG_RR; ++i) {
+      const int r = lane + kWave * i;
+      if (r >= r0 && r < N) vb[buf][r] = r == r0 ? T(1) : x[i] * scal;
+      if (r == jj) dd[jj] = x[i];
     }
-    if (tid == 0) {
-      dd[j] = A[j * LDA + j];
-      ee[j] = beta;
+    if (lane == 0) {
+      tau_s[buf] = tau;
+      ee[jj] = beta;
     }
-    __syncthreads();
-    if (tau != T(0)) {
-      T acc[TF_CH];
-#pragma unroll
-      for (int c = 0; c < TF_CH; ++c) acc[c] = T(0);
-      for (int k = r0 + wave; k < N; k += TF_NW) {
-        const T vk = vb[k];
-#pragma unroll
-        for (int c = 0; c < TF_CH; ++c) {
-          const int row = r0 + lane + kWave * c;
-          if (row < N) acc[c] += A[k * LDA + row] * vk;
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < TF_CH; ++c) {
-        const int row = r0 + lane + kWave * c;
-        if (row < N) pp[wave * NL + row] = acc[c];
-      }
-      __syncthreads();
-      const int row = r0 + tid;
-      T prow = T(0), pv = T(0);
-      if (row < N) {
-        T sacc = T(0);
-        for (int w = 0; w < TF_NW; ++w) sacc += pp[w * NL + row];
-        prow = tau * sacc;
-        pv = vb[row] * prow;
-      }
-      const T K = block_sum(pv, red) * T(0.5) * tau;
-      if (row < N) wb[row] = prow - K * vb[row];
-      __syncthreads();
-      T wr[TF_CH];
-#pragma unroll
-      for (int c = 0; c < TF_CH; ++c) {
-        const int rr = r0 + lane + kWave * c;
-        wr[c] = rr < N ? wb[rr] : T(0);
-      }
-      for (int k = r0 + wave; k < N; k += TF_NW) {
-        const T vk = vb[k], wk = wb[k];
-#pragma unroll
-        for (int c = 0; c < TF_CH; ++c) {
-          const int rr = r0 + lane + kWave * c;
-          if (rr < N) A[k * LDA + rr] -= vs[c] * wk + wr[c] * vk;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  if (tid == 0) {
-    if (N >= 2) {
-      dd[N - 2] = A[(N - 2) * LDA + (N - 2)];
-      ee[N - 2] = A[(N - 2) * LDA + (N - 1)];
-    }
-    dd[N - 1] = A[(N - 1) * LDA + (N - 1)];
-  }
-  __syncthreads();
-  tridiag_spectrum<T>(tk_, dd, ee, lam, sc, N, tid, TF_NT);
-}
-
-template <typename T>
-__global__ __launch_bounds__(VAL_NT) void tridiag_bisect_kernel(const EigTask<T>* __restrict__ tasks, int NL) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const EigTask<T> tk_ = tasks[blockIdx.x];
-  int N = NL;
-  if (tk_.ndyn != nullptr) {
-    const int nd = *tk_.ndyn;
-    if (nd < 0 || nd > NL) {
-      if (threadIdx.x == 0 && tk_.rule.rank_out) *tk_.rule.rank_out = -1;
-      return;
-    }
-    N = nd;
-  }
-  if (N == 0) {
-    if (threadIdx.x == 0 && tk_.rule.rank_out) *tk_.rule.rank_out = 0;
-    return;
-  }
-  T* A = reinterpret_cast<T*>(smem_raw);  // packed lower, NL(NL+1)/2
-  const int NPK = NL * (NL + 1) / 2;
-  T* v = A + NPK;        // NL
-  T* p = v + NL;         // NL
-  T* dd = p + NL;        // NL diagonal
-  T* ee = dd + NL;       // NL off-diagonal (squared later)
-  T* lam = ee + NL;      // NL eigenvalues (descending)
-  __shared__ T red[VAL_NT / kWave];
-  __shared__ T sc[4];
-  const int tid = threadIdx.x;
-  const int sub = tid % TG, rloc = tid / TG;
-  for (int i = tid; i < N; i += VAL_NT)
-    for (int j = 0; j <= i; ++j) A[pk(i, j)] = tk_.A[i + (size_t)j * tk_.lda];
-  __syncthreads();
-  // ---- Householder tridiagonalisation (lower): columns j = 0 .. N-3
+  };
   for (int j = 0; j + 2 < N; ++j) {
-    const int m = N - j - 1;  // trailing size; rows j+1 .. N-1
-    T xi = T(0);
-    if (tid < m) xi = A[pk(j + 1 + tid, j)];
-    const T s2 = block_sum(tid > 0 && tid < m ? xi * xi : T(0), red);
-    if (tid == 0) sc[0] = xi;  // alpha
+    const int buf = j & 1;
+    const int r0 = j + 1;
+    if (wave == (j & (TRG_NW - 1))) householder(j);
     __syncthreads();
-    const T alpha = sc[0];
-    T beta, tau, scal;
-    if (s2 == T(0)) {
-      beta = alpha;
-      tau = T(0);
-      scal = T(0);
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + s2), alpha);
-      tau = (beta - alpha) / beta;
-      scal = T(1) / (alpha - beta);
+    const T tau = tau_s[buf];
+    if (tau == T(0)) continue;  // the same value in every thread: nothing to apply
+    // unconditional loads (in-bounds indices; the buffers hold finite values)
+    // times a 0/1 mask, so that all loads issue before a single wait
+    T vr[TRG_RR], vc[TRG_RC];
+#pragma unroll
+    for (int i = 0; i < TRG_RR; ++i) {
+      const int r = lane + kWave * i;
+      vr[i] = vb[buf][min(r, VAL_NMAX - 1)] * T(r >= r0 && r < N);
     }
-    if (tid < m) v[tid] = (tid == 0) ? T(1) : xi * scal;
-    if (tid == 0) {
-      dd[j] = A[pk(j, j)];
-      ee[j] = beta;
+#pragma unroll
+    for (int k = 0; k < TRG_RC; ++k) {
+      const int c = wave + TRG_NW * k;
+      vc[k] = vb[buf][c] * T(c >= r0 && c < N);
+    }
+    // ---- partial products over this wave's columns
+    T q = T(0);
+#pragma unroll
+    for (int i = 0; i < TRG_RR; ++i) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < TRG_RC; ++k) acc += a[i][k] * vc[k];
+      q += vr[i] * acc;
+      const int r = lane + kWave * i;
+      if (r < N) pp[wave][r] = acc;
+    }
+    q = wave_sum(q);
+    if (lane == 0) qs[wave] = q;
+    __syncthreads();
+    if (tid >= r0 && tid < N) {
+      T sacc = T(0), vav = T(0);
+#pragma unroll
+      for (int w = 0; w < TRG_NW; ++w) {
+        sacc += pp[w][tid];
+        vav += qs[w];
+      }
+      const T K = T(0.5) * tau * tau * vav;
+      wb[buf][tid] = tau * sacc - K * vb[buf][tid];
     }
     __syncthreads();
-    if (tau != T(0)) {
-      // p = tau * A_sub v: TG threads per row of the trailing block
-      for (int r0 = 0; r0 < m; r0 += VAL_NT / TG) {
-        const int r = r0 + rloc;
-        T acc = T(0);
-        if (r < m) {
-          const int gi = j + 1 + r;
-          const int base = (gi * (gi + 1)) / 2 + (j + 1);
-          auto ix = [&](int k) {
-            const int col = j + 1 + k;
-            return k <= r ? base + k : (col * (col + 1)) / 2 + gi;
-          };
-          int k = sub;
-          for (; k + 3 * TG < m; k += 4 * TG) {
-            const T a0 = A[ix(k)], a1 = A[ix(k + TG)], a2 = A[ix(k + 2 * TG)], a3 = A[ix(k + 3 * TG)];
-            const T v0 = v[k], v1 = v[k + TG], v2 = v[k + 2 * TG], v3 = v[k + 3 * TG];
-            acc += (a0 * v0 + a1 * v1) + (a2 * v2 + a3 * v3);
-          }
-          for (; k < m; k += TG) acc += A[ix(k)] * v[k];
-        }
-        acc += __shfl_xor(acc, 1, kWave);
-        acc += __shfl_xor(acc, 2, kWave);
-        if (r < m && sub == 0) p[r] = tau * acc;
-      }
-      __syncthreads();
-      const T kk = block_sum(tid < m ? v[tid] * p[tid] : T(0), red) * T(0.5) * tau;
-      if (tid < m) p[tid] = p[tid] - kk * v[tid];  // w = p - K v
-      __syncthreads();
-      // A_sub -= v w^T + w v^T (lower part), TG threads per row
-      for (int r0 = 0; r0 < m; r0 += VAL_NT / TG) {
-        const int r = r0 + rloc;
-        if (r < m) {
-          const int gi = j + 1 + r;
-          const int base = (gi * (gi + 1)) / 2 + (j + 1);
-          const T vi = v[r], wi = p[r];
-          int k = sub;
-          for (; k + 3 * TG <= r; k += 4 * TG) {
-            const T a0 = A[base + k], a1 = A[base + k + TG], a2 = A[base + k + 2 * TG], a3 = A[base + k + 3 * TG];
-            const T p0 = p[k], p1 = p[k + TG], p2 = p[k + 2 * TG], p3 = p[k + 3 * TG];
-            const T v0 = v[k], v1 = v[k + TG], v2 = v[k + 2 * TG], v3 = v[k + 3 * TG];
-            A[base + k] = a0 - (vi * p0 + wi * v0);
-            A[base + k + TG] = a1 - (vi * p1 + wi * v1);
-            A[base + k + 2 * TG] = a2 - (vi * p2 + wi * v2);
-            A[base + k + 3 * TG] = a3 - (vi * p3 + wi * v3);
-          }
-          for (; k <= r; k += TG) A[base + k] -= vi * p[k] + wi * v[k];
-        }
-      }
-      __syncthreads();
+    // ---- rank-2 update of this thread's entries
+    T wr[TRG_RR], wc[TRG_RC];
+#pragma unroll
+    for (int i = 0; i < TRG_RR; ++i) {
+      const int r = lane + kWave * i;
+      wr[i] = wb[buf][min(r, VAL_NMAX - 1)] * T(r >= r0 && r < N);
     }
-  }
-  if (tid == 0) {
-    if (N >= 2) {
-      dd[N - 2] = A[pk(N - 2, N - 2)];
-      ee[N - 2] = A[pk(N - 1, N - 2)];
+#pragma unroll
+    for (int k = 0; k < TRG_RC; ++k) {
+      const int c = wave + TRG_NW * k;
+      wc[k] = wb[buf][c] * T(c >= r0 && c < N);
     }
-    dd[N - 1] = A[pk(N - 1, N - 1)];
+#pragma unroll
+    for (int i = 0; i < TRG_RR; ++i)
+#pragma unroll
+      for (int k = 0; k < TRG_RC; ++k) a[i][k] -= vr[i] * wc[k] + wr[i] * vc[k];
+    __syncthreads();
   }
+  // last 2 x 2 block: diagonal entries and the coupling, from their holders
+#pragma unroll
+  for (int i = 0; i < TRG_RR; ++i)
+#pragma unroll
+    for (int k = 0; k < TRG_RC; ++k) {
+      const int r = lane + kWave * i, c = wave + TRG_NW * k;
+      if (N >= 2 && r == N - 2 && c == N - 2) dd[N - 2] = a[i][k];
+      if (N >= 2 && r == N - 1 && c == N - 2) ee[N - 2] = a[i][k];
+      if (r == N - 1 && c == N - 1) dd[N - 1] = a[i][k];
+    }
   __syncthreads();
-  tridiag_spectrum<T>(tk_, dd, ee, lam, sc, N, tid, VAL_NT);
+  tridiag_spectrum<T>(tk_, dd, ee, lam, sc, N, tid, TRG_NT);
 }
 
 // ------------------------------------------------------------ eigenvalues + vectors
@@ -616,10 +528,6 @@ __global__ __launch_bounds__(JV_NT) void jacobi_vec_kernel(const EigTask<T>* __r
     }
 }
 
-template <typename T>
-size_t vals_smem(int N) {
-  return sizeof(T) * (size_t(N) * (N + 1) / 2 + 5 * size_t(N)) + 64;
-}
 
 }  // namespace
 
@@ -640,25 +548,7 @@ void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipSt
     hipLaunchKernelGGL((jacobi_vec_kernel<T, nt>), dim3(ntasks), dim3(nt), 0, st, tasks_d, N);
   } else {
     TK_CHECK(N <= VAL_NMAX, kErrUnsupported, "symmetric eigensolver: matrix larger than 160");
-    static bool attr_set[4] = {false, false, false, false};
-    const bool full = tfull_fits<T>(N);
-    bool& done = attr_set[(sizeof(T) == 8 ? 2 : 0) + (full ? 1 : 0)];
-    if (full) {
-      if (!done) {
-        TK_HIP(hipFuncSetAttribute((const void*)tridiag_full_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   int(160 * 1024 - 1024)));
-        done = true;
-      }
-      hipLaunchKernelGGL((tridiag_full_kernel<T>), dim3(ntasks), dim3(TF_NT), tfull_smem<T>(N), st, tasks_d, N);
-    } else {
-      // the full matrix does not fit in LDS (FP64 above order 128): packed storage
-      if (!done) {
-        TK_HIP(hipFuncSetAttribute((const void*)tridiag_bisect_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   int(vals_smem<T>(VAL_NMAX))));
-        done = true;
-      }
-      hipLaunchKernelGGL((tridiag_bisect_kernel<T>), dim3(ntasks), dim3(VAL_NT), vals_smem<T>(N), st, tasks_d, N);
-    }
+    hipLaunchKernelGGL((tridiag_reg_kernel<T, trg_nt<T>()>), dim3(ntasks), dim3(trg_nt<T>()), 0, st, tasks_d, N);
   }
   TK_LAUNCH_CHECK();
   timer_end(kc, st);

@@ -308,16 +308,24 @@ __global__ __launch_bounds__(QR_NT) void qr_piv_kernel(const QrPivTask* __restri
 constexpr int CH_NT = 256;
 constexpr int CH_MAX = 64;
 
-// Right-looking Cholesky of one small Gram in LDS (one workgroup per task).
+// Right-looking Cholesky of one small Gram in LDS (one workgroup per task),
+// one barrier per step: every thread derives the pivot of step k from G[k][k]
+// itself, and the trailing update G[i][j] -= G[k][i] G[k][j] / pivot (k < i
+// <= j, lane = column j, waves stride over the rows i) reads row k unscaled,
+// which no thread writes after step k.  Row k of R = row k / sqrt(pivot) is
+// formed at the end.  A pivot that is not above max(dead_rel tr, dead_abs)
+// marks a dead column: its row of R is zero and it updates nothing.
 __global__ __launch_bounds__(CH_NT) void chol_kernel(const CholTask* __restrict__ tasks, int cap,
                                                      const int* __restrict__ m_dev, double shift, double dead_rel,
                                                      double dead_abs) {
+  constexpr int NW = CH_NT / kWave;
   __shared__ double G[CH_MAX][CH_MAX + 1];
-  __shared__ double red[CH_NT / kWave];
-  __shared__ double piv_s;
-  __shared__ int dead[CH_MAX];
+  __shared__ double red[NW];
+  __shared__ double rk_s[CH_MAX];
   const CholTask tk_ = tasks[blockIdx.x];
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
   int m = m_dev ? *m_dev : cap;
   m = min(m, cap);
   for (int e = tid; e < cap * cap; e += CH_NT) {
@@ -330,31 +338,25 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const CholTask* __restrict_
   const double dtol = fmax(dead_rel * tr, dead_abs);
   if (tid < m) G[tid][tid] += s;
   __syncthreads();
+  const int j = lane;  // this thread's column of the trailing update
   for (int k = 0; k < m; ++k) {
-    if (tid == 0) {
-      const double pv = G[k][k];
-      const bool dk = !(pv > dtol);
-      dead[k] = dk;
-      piv_s = dk ? 0.0 : sqrt(pv);
-    }
-    __syncthreads();
-    const double rkk = piv_s;
-    const bool dk = dead[k];
-    // row k of R: R[k][j] = G[k][j] / rkk (j > k)
-    if (tid > k && tid < m) G[k][tid] = dk ? 0.0 : G[k][tid] / rkk;
-    if (tid == 0) G[k][k] = rkk;
-    __syncthreads();
-    if (!dk) {
-      for (int e = tid; e < (m - k - 1) * (m - k - 1); e += CH_NT) {
-        const int i = k + 1 + e % (m - k - 1), j = k + 1 + e / (m - k - 1);
-        if (i <= j) G[i][j] -= G[k][i] * G[k][j];
-      }
+    const double pv = G[k][k];
+    const bool dk = !(pv > dtol);
+    if (tid == 0) rk_s[k] = dk ? 0.0 : sqrt(pv);
+    if (!dk && j > k && j < m) {
+      const double f = G[k][j] / pv;
+      for (int i = k + 1 + wave; i <= j; i += NW) G[i][j] -= G[k][i] * f;
     }
     __syncthreads();
   }
   for (int e = tid; e < cap * cap; e += CH_NT) {
-    const int i = e % cap, j = e / cap;
-    tk_.R[i + (size_t)j * cap] = (i < m && j < m && i <= j) ? G[i][j] : 0.0;
+    const int i = e % cap, jj = e / cap;
+    double r = 0.0;
+    if (i < m && jj < m && i <= jj) {
+      const double rkk = rk_s[i];
+      r = rkk == 0.0 ? 0.0 : (i == jj ? rkk : G[i][jj] / rkk);
+    }
+    tk_.R[i + (size_t)jj * cap] = r;
   }
 }
 
