@@ -31,6 +31,11 @@
  *     Nothing throws across the ABI.  The error message is thread-local.
  *   - Limits of this build: 2 <= d <= 4, n_k <= 512, rank_cap + oversample
  *     <= 64, sketch size s <= 256, maxiter <= 64.
+ *   - Forms: tensors cross the ABI in FP64.  TK_FORM_FP32 runs a call in the
+ *     arithmetic of the solver's FP32 form: operands are rounded to FP32 on
+ *     entry, products, Gram matrices, eigensolves and contractions run in
+ *     FP32 (matrix cores with FP32 accumulation), the range-sketch QR of a
+ *     RoundSum stays FP64, and results are widened to FP64 on exit.
  */
 #ifndef TSGMRES_H_
 #define TSGMRES_H_
@@ -94,6 +99,7 @@ typedef struct {
   int32_t oversample;       /* p: sketch width = min(max_k r~_k + p, rank_cap + p) */
   int32_t force_s;          /* >= 0: use this sketch width (rank replay) */
   int32_t force_ranks[TK_MAX_D]; /* >= 0: use these output ranks (rank replay) */
+  int32_t form;             /* tk_form of the arithmetic (see "Forms" above) */
 } tk_round_params;
 
 /* Restarted Tucker sGMRES parameters (Alg. 2 inputs plus restarts). */
@@ -128,17 +134,17 @@ typedef struct {
  * mode k with A_j^(k) != NULL writes AU[j*d+k] = A_j^(k) U_k (transpose = 0)
  * or A_j^(k)^T U_k (transpose = 1) into caller buffers of n_k x x->rcap[k];
  * L(x) is then the block sum of terms alpha_j * (core; AU or U).  AU entries
- * of identity factors are ignored (may be NULL). */
-int tucker_apply_op(const tk_kron_op* op, const tk_tucker* x, int32_t transpose, double* const* AU, void* ws,
-                    size_t ws_bytes, void* stream);
-int tucker_apply_op_workspace(const tk_kron_op* op, const tk_tucker* x, size_t* bytes);
+ * of identity factors are ignored (may be NULL).  form: tk_form. */
+int tucker_apply_op(const tk_kron_op* op, const tk_tucker* x, int32_t transpose, int32_t form, double* const* AU,
+                    void* ws, size_t ws_bytes, void* stream);
+int tucker_apply_op_workspace(const tk_kron_op* op, const tk_tucker* x, int32_t form, size_t* bytes);
 
 /* Khatri-Rao sketch (Alg. 2, sketch of B and of each W): out[l] =
  * (S_1[:,l] kron ... kron S_d[:,l])^T vec(sum_b coef_b X_b), l < s; out is a
- * device vector of length s. */
-int tucker_sketch(const tk_block_sum* x, const double* const* S, int64_t s, double* out, void* ws, size_t ws_bytes,
-                  void* stream);
-int tucker_sketch_workspace(const tk_block_sum* x, int64_t s, size_t* bytes);
+ * device vector of length s.  form: tk_form (the sketch vector is FP64 either way). */
+int tucker_sketch(const tk_block_sum* x, const double* const* S, int64_t s, int32_t form, double* out, void* ws,
+                  size_t ws_bytes, void* stream);
+int tucker_sketch_workspace(const tk_block_sum* x, int64_t s, int32_t form, size_t* bytes);
 
 /* RoundSum (Sec. 3.1): randomized RHOSVD recompression of a block sum into
  * `out` (ranks written to out->r; out->rcap must hold them).  *s_out (host,

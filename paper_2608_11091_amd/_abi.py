@@ -41,7 +41,7 @@ class TkKronOp(C.Structure):
 
 class TkRoundParams(C.Structure):
     _fields_ = [("eps", C.c_double), ("tau", C.c_double), ("rank_cap", C.c_int32), ("oversample", C.c_int32),
-                ("force_s", C.c_int32), ("force_ranks", C.c_int32 * TK_MAX_D)]
+                ("force_s", C.c_int32), ("force_ranks", C.c_int32 * TK_MAX_D), ("form", C.c_int32)]
 
 
 class TkSgmresParams(C.Structure):
@@ -71,10 +71,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         raise RuntimeError(f"{path} is not built; run `python -m paper_2608_11091_amd.build`")
     lib = C.CDLL(path)
     P, VP, SZ = C.POINTER, C.c_void_p, C.c_size_t
-    lib.tucker_apply_op.argtypes = [P(TkKronOp), P(TkTucker), C.c_int32, P(VP), VP, SZ, VP]
-    lib.tucker_apply_op_workspace.argtypes = [P(TkKronOp), P(TkTucker), P(SZ)]
-    lib.tucker_sketch.argtypes = [P(TkBlockSum), P(VP), C.c_int64, VP, VP, SZ, VP]
-    lib.tucker_sketch_workspace.argtypes = [P(TkBlockSum), C.c_int64, P(SZ)]
+    lib.tucker_apply_op.argtypes = [P(TkKronOp), P(TkTucker), C.c_int32, C.c_int32, P(VP), VP, SZ, VP]
+    lib.tucker_apply_op_workspace.argtypes = [P(TkKronOp), P(TkTucker), C.c_int32, P(SZ)]
+    lib.tucker_sketch.argtypes = [P(TkBlockSum), P(VP), C.c_int64, C.c_int32, VP, VP, SZ, VP]
+    lib.tucker_sketch_workspace.argtypes = [P(TkBlockSum), C.c_int64, C.c_int32, P(SZ)]
     lib.tucker_rhosvd.argtypes = [P(TkBlockSum), P(TkRoundParams), P(VP), P(TkTucker), P(C.c_int32), VP, SZ, VP]
     lib.tucker_rhosvd_workspace.argtypes = [P(TkBlockSum), P(TkRoundParams), P(SZ)]
     lib.tsgmres_solve.argtypes = [P(TkKronOp), P(TkTucker), P(TkSgmresParams), P(VP), P(VP), P(TkTucker),

@@ -150,8 +150,9 @@ def _ptr_array(ts: Sequence[Optional[torch.Tensor]]):
     return (C.c_void_p * len(ts))(*[_ptr(t) for t in ts])
 
 
-def apply_op(op: KronOp, x: Tucker, transpose: bool = False):
-    """Factor products of ``L(x)``; returns the block list ``[(alpha_j, Tucker)]``."""
+def apply_op(op: KronOp, x: Tucker, transpose: bool = False, form: int = 0):
+    """Factor products of ``L(x)``; returns the block list ``[(alpha_j, Tucker)]``.
+    ``form`` 1 computes them in FP32 (results widened to FP64)."""
     lib = _abi.load()
     d = x.d
     AU = []
@@ -161,9 +162,9 @@ def apply_op(op: KronOp, x: Tucker, transpose: bool = False):
     xs = x.struct()
     out = _ptr_array([t for row in AU for t in row])
     nb = C.c_size_t()
-    check(lib.tucker_apply_op_workspace(C.byref(ops), C.byref(xs), C.byref(nb)))
+    check(lib.tucker_apply_op_workspace(C.byref(ops), C.byref(xs), int(form), C.byref(nb)))
     ws = _workspace(nb.value, x.core.device)
-    check(lib.tucker_apply_op(C.byref(ops), C.byref(xs), int(transpose), out, C.c_void_p(ws.data_ptr()),
+    check(lib.tucker_apply_op(C.byref(ops), C.byref(xs), int(transpose), int(form), out, C.c_void_p(ws.data_ptr()),
                               nb.value, _stream()))
     blocks = []
     for j, As in enumerate(op.A):
@@ -172,29 +173,33 @@ def apply_op(op: KronOp, x: Tucker, transpose: bool = False):
     return blocks
 
 
-def sketch(blocks, S: Sequence[torch.Tensor]) -> torch.Tensor:
-    """Khatri-Rao sketch ``S^T vec(sum_b c_b X_b)`` (length s)."""
+def sketch(blocks, S: Sequence[torch.Tensor], form: int = 0) -> torch.Tensor:
+    """Khatri-Rao sketch ``S^T vec(sum_b c_b X_b)`` (length s); ``form`` 1
+    computes it in FP32."""
     lib = _abi.load()
     bs, keep = _blocks_struct(blocks)
     s = int(S[0].shape[0])
     dev = blocks[0][1].core.device
     out = torch.zeros(s, dtype=torch.float64, device=dev)
     nb = C.c_size_t()
-    check(lib.tucker_sketch_workspace(C.byref(bs), s, C.byref(nb)))
+    check(lib.tucker_sketch_workspace(C.byref(bs), s, int(form), C.byref(nb)))
     ws = _workspace(nb.value, dev)
-    check(lib.tucker_sketch(C.byref(bs), _ptr_array(S), s, C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()),
-                            nb.value, _stream()))
+    check(lib.tucker_sketch(C.byref(bs), _ptr_array(S), s, int(form), C.c_void_p(out.data_ptr()),
+                            C.c_void_p(ws.data_ptr()), nb.value, _stream()))
     return out
 
 
 def rhosvd(blocks, omega: Sequence[torch.Tensor], eps: float, cap: int, p: int = 5, tau: float = -1.0,
-           force_s: int = -1, force_ranks: Optional[Sequence[int]] = None, out_rcap: Optional[Sequence[int]] = None):
-    """RoundSum of a block sum; returns ``(Tucker, s)``."""
+           force_s: int = -1, force_ranks: Optional[Sequence[int]] = None, out_rcap: Optional[Sequence[int]] = None,
+           form: int = 0):
+    """RoundSum of a block sum; returns ``(Tucker, s)``.  ``form`` 1 runs it in
+    the FP32 form's arithmetic (FP64 range-sketch QR)."""
     lib = _abi.load()
     bs, keep = _blocks_struct(blocks)
     x0 = blocks[0][1]
     prm = TkRoundParams()
     prm.eps, prm.tau, prm.rank_cap, prm.oversample, prm.force_s = eps, tau, cap, p, force_s
+    prm.form = int(form)
     for k in range(TK_MAX_D):
         prm.force_ranks[k] = -1 if force_ranks is None or k >= len(force_ranks) else int(force_ranks[k])
     rc = tuple(out_rcap) if out_rcap is not None else (cap,) * x0.d

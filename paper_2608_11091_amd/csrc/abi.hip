@@ -111,6 +111,29 @@ void export_tt(const Shape& sh, const TT<double>& t, tk_tucker* u, hipStream_t s
   TK_HIP(hipStreamSynchronize(st));
 }
 
+// Element-type conversion of an internal tensor (capacity layout) and of a
+// plain device array, as plan steps.
+template <typename S, typename D>
+void emit_cast_tt(Seq& q, const Shape& sh, const TT<S>& src, const TT<D>& dst) {
+  const size_t cl = sh.core_len();
+  const int d = sh.d;
+  std::array<size_t, kMaxD> fl{};
+  for (int k = 0; k < d; ++k) fl[k] = size_t(sh.n[k]) * sh.rc;
+  q.steps.push_back([=](hipStream_t st) {
+    cast_copy<S, D>(src.core, dst.core, cl, st);
+    for (int k = 0; k < d; ++k) cast_copy<S, D>(src.U[k], dst.U[k], fl[k], st);
+    copy_ints(src.rank, dst.rank, d, st);
+  });
+}
+const float* emit_to_f32(Seq& q, Arena& ar, const double* src, size_t len) {
+  float* dst = ar.alloc<float>(len);
+  q.steps.push_back([=](hipStream_t st) { cast_copy<double, float>(src, dst, len, st); });
+  return dst;
+}
+void check_form(int form) {
+  TK_CHECK(form == TK_FORM_FP64 || form == TK_FORM_FP32, kErrUnsupported, "unknown form");
+}
+
 void finish_blob(Arena& ar, Blob& blob, hipStream_t st) {
   blob.dev = ar.alloc<unsigned char>(std::max<size_t>(blob.host.size(), 16));
   if (!ar.measuring())
@@ -128,22 +151,36 @@ Shape shape_of(int d, const int64_t* n, int rc, int cap, int p) {
 }
 
 // ---------------------------------------------------------------- apply
-int do_apply(const tk_kron_op* op, const tk_tucker* x, int transpose, double* const* AU, Arena& ar, hipStream_t st) {
+int do_apply(const tk_kron_op* op, const tk_tucker* x, int transpose, int form, double* const* AU, Arena& ar,
+             hipStream_t st) {
   TK_CHECK(x != nullptr, kErrInvalidArg, "x is NULL");
   check_dims(x->d, x->n);
   check_op(op, x->d, x->n);
   check_tucker(x, "x", x->d, x->n);
+  check_form(form);
   const int d = x->d;
   Blob blob;
   Planner pl(ar, blob);
   Seq q;
+  std::array<const float*, kMaxD> U32{};
+  if (form == TK_FORM_FP32)
+    for (int k = 0; k < d; ++k) U32[k] = emit_to_f32(q, ar, x->U[k], size_t(x->n[k]) * x->rcap[k]);
   for (int j = 0; j < op->nterms; ++j)
     for (int k = 0; k < d; ++k) {
       const double* A = op->A[j * d + k];
       if (!A) continue;
       TK_CHECK(AU != nullptr && AU[j * d + k] != nullptr, kErrInvalidArg, "missing output buffer for a factor product");
       const int n = int(x->n[k]), rcap = int(x->rcap[k]);
-      plan_gemm<double>(q, pl, !transpose, false, n, rcap, n, A, n, x->U[k], n, AU[j * d + k], n, 1.0, 0.0);
+      if (form == TK_FORM_FP32) {
+        const float* A32 = emit_to_f32(q, ar, A, size_t(n) * n);
+        float* P32 = ar.alloc<float>(size_t(n) * rcap);
+        plan_gemm<float>(q, pl, !transpose, false, n, rcap, n, A32, n, U32[k], n, P32, n, 1.0, 0.0);
+        double* dst = AU[j * d + k];
+        const size_t len = size_t(n) * rcap;
+        q.steps.push_back([=](hipStream_t st) { cast_copy<float, double>(P32, dst, len, st); });
+      } else {
+        plan_gemm<double>(q, pl, !transpose, false, n, rcap, n, A, n, x->U[k], n, AU[j * d + k], n, 1.0, 0.0);
+      }
     }
   finish_blob(ar, blob, st);
   if (ar.measuring()) return 0;
@@ -183,9 +220,22 @@ Imported import_blocks(Seq& q, Arena& ar, const tk_block_sum* in, int cap, int p
   return im;
 }
 
-int do_sketch(const tk_block_sum* x, const double* const* S, int64_t s, double* out, Arena& ar, hipStream_t st) {
+// The imported blocks rounded to FP32 (same coefficients).
+Blocks<float> blocks_f32(Seq& q, Arena& ar, const Imported& im) {
+  Blocks<float> out;
+  for (size_t b = 0; b < im.t.size(); ++b) {
+    TT<float> t = alloc_tt<float>(ar, im.sh);
+    emit_cast_tt<double, float>(q, im.sh, im.t[b], t);
+    out.add(t, nullptr, im.blocks.cscale[b]);
+  }
+  return out;
+}
+
+int do_sketch(const tk_block_sum* x, const double* const* S, int64_t s, int form, double* out, Arena& ar,
+              hipStream_t st) {
   TK_CHECK(S != nullptr && out != nullptr, kErrInvalidArg, "sketch factors or output missing");
   TK_CHECK(s >= 1 && s <= 65535, kErrInvalidArg, "sketch size out of range");
+  check_form(form);
   Blob blob;
   Planner pl(ar, blob);
   Seq q;
@@ -195,7 +245,14 @@ int do_sketch(const tk_block_sum* x, const double* const* S, int64_t s, double* 
     TK_CHECK(S[k] != nullptr, kErrInvalidArg, "sketch factor is NULL");
     Sk[k] = S[k];
   }
-  plan_sketch<double>(q, pl, im.sh, im.blocks, Sk, int(s), out);
+  if (form == TK_FORM_FP32) {
+    std::array<const float*, kMaxD> S32{};
+    for (int k = 0; k < im.sh.d; ++k) S32[k] = emit_to_f32(q, ar, Sk[k], size_t(im.sh.n[k]) * s);
+    Blocks<float> b32 = blocks_f32(q, ar, im);
+    plan_sketch<float>(q, pl, im.sh, b32, S32, int(s), out);
+  } else {
+    plan_sketch<double>(q, pl, im.sh, im.blocks, Sk, int(s), out);
+  }
   finish_blob(ar, blob, st);
   if (ar.measuring()) return 0;
   q.run(st);
@@ -228,15 +285,26 @@ int do_rhosvd(const tk_block_sum* in, const tk_round_params* prm, const double* 
   TK_CHECK(omega != nullptr, kErrInvalidArg, "omega is NULL");
   for (int k = 0; k < sh.d; ++k) om[k] = omega[k];
   if (out) check_dims(out->d, out->n);
+  check_form(prm->form);
   TT<double> o = alloc_tt<double>(ar, sh);
-  RoundSumOut<double> ro = plan_roundsum<double>(q, pl, sh, im.blocks, cfg, om, o, nullptr);
+  int* s_dev = nullptr;
+  if (prm->form == TK_FORM_FP32) {
+    std::array<const float*, kMaxD> om32{};
+    for (int k = 0; k < sh.d; ++k) om32[k] = emit_to_f32(q, ar, om[k], size_t(sh.n[k]) * sh.sc());
+    Blocks<float> b32 = blocks_f32(q, ar, im);
+    TT<float> o32 = alloc_tt<float>(ar, sh);
+    s_dev = plan_roundsum<float>(q, pl, sh, b32, cfg, om32, o32, nullptr).s_dev;
+    emit_cast_tt<float, double>(q, sh, o32, o);
+  } else {
+    s_dev = plan_roundsum<double>(q, pl, sh, im.blocks, cfg, om, o, nullptr).s_dev;
+  }
   finish_blob(ar, blob, st);
   if (ar.measuring()) return 0;
   TK_CHECK(out != nullptr && out->d == sh.d, kErrInvalidArg, "output tensor missing or of wrong order");
   for (int k = 0; k < sh.d; ++k) TK_CHECK(out->n[k] == sh.n[k], kErrShape, "output mode size mismatch");
   q.run(st);
   if (s_out) {
-    TK_HIP(hipMemcpyAsync(s_out, ro.s_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    TK_HIP(hipMemcpyAsync(s_out, s_dev, sizeof(int), hipMemcpyDeviceToHost, st));
   }
   export_tt(sh, o, out, st);
   return 0;
@@ -466,41 +534,41 @@ static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 
 extern "C" {
 
-int tucker_apply_op(const tk_kron_op* op, const tk_tucker* x, int32_t transpose, double* const* AU, void* ws,
-                    size_t ws_bytes, void* stream) {
+int tucker_apply_op(const tk_kron_op* op, const tk_tucker* x, int32_t transpose, int32_t form, double* const* AU,
+                    void* ws, size_t ws_bytes, void* stream) {
   return guarded([&] {
     TK_CHECK(ws != nullptr || ws_bytes == 0, kErrInvalidArg, "workspace pointer is NULL");
     Arena ar(ws ? ws : reinterpret_cast<void*>(uintptr_t(1)), ws_bytes);
-    return do_apply(op, x, transpose, AU, ar, as_stream(stream));
+    return do_apply(op, x, transpose, form, AU, ar, as_stream(stream));
   });
 }
-int tucker_apply_op_workspace(const tk_kron_op* op, const tk_tucker* x, size_t* bytes) {
+int tucker_apply_op_workspace(const tk_kron_op* op, const tk_tucker* x, int32_t form, size_t* bytes) {
   return guarded([&] {
     Arena ar(nullptr, 0);
     double* dummy[TK_MAX_D * 64] = {};
     for (auto& p : dummy) p = reinterpret_cast<double*>(uintptr_t(0x1000));
-    const int r = do_apply(op, x, 0, dummy, ar, nullptr);
+    const int r = do_apply(op, x, 0, form, dummy, ar, nullptr);
     if (bytes) *bytes = ar.used();
     return r;
   });
 }
 
-int tucker_sketch(const tk_block_sum* x, const double* const* S, int64_t s, double* out, void* ws, size_t ws_bytes,
-                  void* stream) {
+int tucker_sketch(const tk_block_sum* x, const double* const* S, int64_t s, int32_t form, double* out, void* ws,
+                  size_t ws_bytes, void* stream) {
   return guarded([&] {
     TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
     Arena ar(ws, ws_bytes);
-    return do_sketch(x, S, s, out, ar, as_stream(stream));
+    return do_sketch(x, S, s, form, out, ar, as_stream(stream));
   });
 }
-int tucker_sketch_workspace(const tk_block_sum* x, int64_t s, size_t* bytes) {
+int tucker_sketch_workspace(const tk_block_sum* x, int64_t s, int32_t form, size_t* bytes) {
   return guarded([&] {
     Arena ar(nullptr, 0);
     const double* S[TK_MAX_D] = {reinterpret_cast<const double*>(uintptr_t(0x1000)),
                                  reinterpret_cast<const double*>(uintptr_t(0x1000)),
                                  reinterpret_cast<const double*>(uintptr_t(0x1000)),
                                  reinterpret_cast<const double*>(uintptr_t(0x1000))};
-    const int r = do_sketch(x, S, s, reinterpret_cast<double*>(uintptr_t(0x1000)), ar, nullptr);
+    const int r = do_sketch(x, S, s, form, reinterpret_cast<double*>(uintptr_t(0x1000)), ar, nullptr);
     if (bytes) *bytes = ar.used();
     return r;
   });
