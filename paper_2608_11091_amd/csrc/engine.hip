@@ -1017,11 +1017,7 @@ void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>
   }
   TK_CHECK(rc <= 64, kErrUnsupported, "exact norm: rank capacity above 64");
   const int Md = m * rc;
-  std::vector<double*> Qk(d), Rk(d);
-  double* Xt = ar.alloc<double>(size_t(*std::max_element(sh.n, sh.n + d)) * rc);
-  double* Ct = ar.alloc<double>(size_t(Md) * rc);
-  double* Rt = ar.alloc<double>(size_t(rc) * rc);
-  double* R2t = ar.alloc<double>(size_t(rc) * rc);
+  std::vector<double*> Qk(d), Rk(d), Xt(d), Ct(d), Rt(d), R2t(d);
   double* coef = ar.alloc<double>(nb);
   const size_t off_cptr = pl.blob.add(in.cptr), off_cs = pl.blob.add(in.cscale);
   q.steps.push_back([=](hipStream_t st) {
@@ -1031,138 +1027,117 @@ void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>
     const int n = sh.n[k];
     Qk[k] = ar.alloc<double>(size_t(n) * Md);
     Rk[k] = ar.alloc<double>(size_t(Md) * Md);
+    Xt[k] = ar.alloc<double>(size_t(n) * rc);
+    Ct[k] = ar.alloc<double>(size_t(Md) * rc);
+    Rt[k] = ar.alloc<double>(size_t(rc) * rc);
+    R2t[k] = ar.alloc<double>(size_t(rc) * rc);
     double* R = Rk[k];
-    double* Q = Qk[k];
     q.steps.push_back([=](hipStream_t st) { fill<double>(R, size_t(Md) * Md, 0.0, st); });
-    for (int i = 0; i < int(fac[k].size()); ++i) {
-      const double* F = fac[k][i];
-      double* Rblk = R + size_t(i) * rc * Md;  // column block i
+  }
+  // Block i of every mode (modes of equal size batched into the same launches):
+  // BCGS2 against blocks 0..i-1, rank-revealing QR of the remainder, then one
+  // re-orthogonalisation of the new basis block.
+  for (auto& modes : modes_by_n<double>(sh)) {
+    const int n = sh.n[modes[0]];
+    int imax = 0;
+    for (int k : modes) imax = std::max(imax, int(fac[k].size()));
+    for (int i = 0; i < imax; ++i) {
+      std::vector<int> act;
+      for (int k : modes)
+        if (i < int(fac[k].size())) act.push_back(k);
+      const int na = int(act.size());
+      auto Rblk = [&](int k) { return Rk[k] + size_t(i) * rc * Md; };  // column block i
+      auto Qi = [&](int k) { return Qk[k] + size_t(i) * rc * n; };
+      auto Rdiag = [&](int k) { return Rblk(k) + size_t(i) * rc; };
+      // GEMM over the active modes: C_k = alpha op(A_k) B_k (+ beta C_k)
+      auto gemm = [&](bool ta, int M, int N, int K, int lda, int ldb, int ldc, double beta, double alpha,
+                      auto Cf, auto Af, auto Bf) {
+        GemmDesc<double> g;
+        g.ta = ta;
+        g.M = M;
+        g.N = N;
+        g.K = K;
+        g.lda = lda;
+        g.ldb = ldb;
+        g.ldc = ldc;
+        g.beta = beta;
+        for (int k : act) g.group1(Cf(k), Af(k), Bf(k), nullptr, nullptr, nullptr, alpha);
+        emit_gemm(q, pl, std::move(g));
+      };
+      std::vector<double*> xs;
+      std::vector<const double*> fs;
+      for (int k : act) {
+        xs.push_back(Xt[k]);
+        fs.push_back(fac[k][i]);
+      }
+      q.steps.push_back([=](hipStream_t st) {
+        for (int a2 = 0; a2 < na; ++a2) mat_recap<double>(fs[a2], n, n, rc, xs[a2], n, n, rc, st);
+      });
       if (i > 0) {
         const int Kq = i * rc;
-        {  // C1 = Q^T F -> R[0:Kq, block i]
-          GemmDesc<double> g;
-          g.ta = true;
-          g.M = Kq;
-          g.N = rc;
-          g.K = n;
-          g.lda = n;
-          g.ldb = n;
-          g.ldc = Md;
-          g.group1(Rblk, Q, F);
-          emit_gemm(q, pl, std::move(g));
+        // C1 = Q^T F -> R[0:Kq, block i];  X -= Q C1;  C2 = Q^T X;  X -= Q C2
+        gemm(true, Kq, rc, n, n, n, Md, 0.0, 1.0, Rblk, [&](int k) { return (const double*)Qk[k]; },
+             [&](int k) { return fac[k][i]; });
+        gemm(false, n, rc, Kq, n, Md, n, 1.0, -1.0, [&](int k) { return Xt[k]; },
+             [&](int k) { return (const double*)Qk[k]; }, [&](int k) { return (const double*)Rblk(k); });
+        gemm(true, Kq, rc, n, n, n, Md, 0.0, 1.0, [&](int k) { return Ct[k]; },
+             [&](int k) { return (const double*)Qk[k]; }, [&](int k) { return (const double*)Xt[k]; });
+        gemm(false, n, rc, Kq, n, Md, n, 1.0, -1.0, [&](int k) { return Xt[k]; },
+             [&](int k) { return (const double*)Qk[k]; }, [&](int k) { return (const double*)Ct[k]; });
+        std::vector<const double*> cts;
+        std::vector<double*> rbs;
+        for (int k : act) {
+          cts.push_back(Ct[k]);
+          rbs.push_back(Rblk(k));
         }
-        q.steps.push_back([=](hipStream_t st) { mat_recap<double>(F, n, n, rc, Xt, n, n, rc, st); });
-        {  // X -= Q C1
-          GemmDesc<double> g;
-          g.M = n;
-          g.N = rc;
-          g.K = Kq;
-          g.lda = n;
-          g.ldb = Md;
-          g.ldc = n;
-          g.beta = 1.0;
-          g.group1(Xt, Q, Rblk, nullptr, nullptr, nullptr, -1.0);
-          emit_gemm(q, pl, std::move(g));
-        }
-        {  // C2 = Q^T X
-          GemmDesc<double> g;
-          g.ta = true;
-          g.M = Kq;
-          g.N = rc;
-          g.K = n;
-          g.lda = n;
-          g.ldb = n;
-          g.ldc = Md;
-          g.group1(Ct, Q, Xt);
-          emit_gemm(q, pl, std::move(g));
-        }
-        {  // X -= Q C2
-          GemmDesc<double> g;
-          g.M = n;
-          g.N = rc;
-          g.K = Kq;
-          g.lda = n;
-          g.ldb = Md;
-          g.ldc = n;
-          g.beta = 1.0;
-          g.group1(Xt, Q, Ct, nullptr, nullptr, nullptr, -1.0);
-          emit_gemm(q, pl, std::move(g));
-        }
-        q.steps.push_back([=](hipStream_t st) { mat_axpy<double>(Ct, Md, Rblk, Md, Kq, rc, st); });
-      } else {
-        q.steps.push_back([=](hipStream_t st) { mat_recap<double>(F, n, n, rc, Xt, n, n, rc, st); });
+        q.steps.push_back([=](hipStream_t st) {
+          for (int a2 = 0; a2 < na; ++a2) mat_axpy<double>(cts[a2], Md, rbs[a2], Md, Kq, rc, st);
+        });
       }
-      double* Qi = Q + size_t(i) * rc * n;
       // rank-revealing QR of the remainder: columns left with <= 64 u of their
       // norm in the factor lie (numerically) inside the earlier blocks' span
       // and are cut; what is cut is below the rounding of the core sum itself
-      std::vector<QrPivTask> qt = {QrPivTask{Xt, F, Qi, Rt, facr[k][i]}};
+      std::vector<QrPivTask> qt;
+      for (int k : act) qt.push_back(QrPivTask{Xt[k], fac[k][i], Qi(k), Rt[k], facr[k][i]});
       const size_t off = pl.blob.add(qt);
-      double* Rdiag = Rblk + size_t(i) * rc;
+      q.steps.push_back([=](hipStream_t st) { qr_piv_batched(bl->at<QrPivTask>(off), na, n, rc, kCutTol, st); });
       if (i == 0) {
+        std::vector<const double*> rts;
+        std::vector<double*> rds;
+        for (int k : act) {
+          rts.push_back(Rt[k]);
+          rds.push_back(Rdiag(k));
+        }
         q.steps.push_back([=](hipStream_t st) {
-          qr_piv_batched(bl->at<QrPivTask>(off), 1, n, rc, kCutTol, st);
-          mat_recap<double>(Rt, rc, rc, rc, Rdiag, Md, rc, rc, st);
+          for (int a2 = 0; a2 < na; ++a2) mat_recap<double>(rts[a2], rc, rc, rc, rds[a2], Md, rc, rc, st);
         });
         continue;
       }
-      q.steps.push_back([=](hipStream_t st) { qr_piv_batched(bl->at<QrPivTask>(off), 1, n, rc, kCutTol, st); });
       // Re-orthogonalise the new block's basis against the previous blocks: a
       // kept column with remainder norm rho comes out of its QR orthogonal to
       // the earlier blocks only to about u / rho.  With T = Q_prev^T Q_i and
       // Q_i - Q_prev T = Q_i' R'': F = Q_prev (C + T R_i) + Q_i' (R'' R_i).
       const int Kq = i * rc;
-      {  // T = Q_prev^T Q_i -> Ct
-        GemmDesc<double> g;
-        g.ta = true;
-        g.M = Kq;
-        g.N = rc;
-        g.K = n;
-        g.lda = n;
-        g.ldb = n;
-        g.ldc = Md;
-        g.group1(Ct, Q, Qi);
-        emit_gemm(q, pl, std::move(g));
+      gemm(true, Kq, rc, n, n, n, Md, 0.0, 1.0, [&](int k) { return Ct[k]; },
+           [&](int k) { return (const double*)Qk[k]; }, [&](int k) { return (const double*)Qi(k); });
+      {
+        std::vector<const double*> qis;
+        for (int k : act) qis.push_back(Qi(k));
+        q.steps.push_back([=](hipStream_t st) {
+          for (int a2 = 0; a2 < na; ++a2) mat_recap<double>(qis[a2], n, n, rc, xs[a2], n, n, rc, st);
+        });
       }
-      q.steps.push_back([=](hipStream_t st) { mat_recap<double>(Qi, n, n, rc, Xt, n, n, rc, st); });
-      {  // X = Q_i - Q_prev T
-        GemmDesc<double> g;
-        g.M = n;
-        g.N = rc;
-        g.K = Kq;
-        g.lda = n;
-        g.ldb = Md;
-        g.ldc = n;
-        g.beta = 1.0;
-        g.group1(Xt, Q, Ct, nullptr, nullptr, nullptr, -1.0);
-        emit_gemm(q, pl, std::move(g));
-      }
-      std::vector<QrPivTask> qt2 = {QrPivTask{Xt, Qi, Qi, R2t, facr[k][i]}};
+      gemm(false, n, rc, Kq, n, Md, n, 1.0, -1.0, [&](int k) { return Xt[k]; },
+           [&](int k) { return (const double*)Qk[k]; }, [&](int k) { return (const double*)Ct[k]; });
+      std::vector<QrPivTask> qt2;
+      for (int k : act) qt2.push_back(QrPivTask{Xt[k], Qi(k), Qi(k), R2t[k], facr[k][i]});
       const size_t off2 = pl.blob.add(qt2);
-      q.steps.push_back([=](hipStream_t st) { qr_piv_batched(bl->at<QrPivTask>(off2), 1, n, rc, kCutTol, st); });
-      {  // R[0:Kq, block i] += T R_i
-        GemmDesc<double> g;
-        g.M = Kq;
-        g.N = rc;
-        g.K = rc;
-        g.lda = Md;
-        g.ldb = rc;
-        g.ldc = Md;
-        g.beta = 1.0;
-        g.group1(Rblk, Ct, Rt);
-        emit_gemm(q, pl, std::move(g));
-      }
-      {  // diagonal block R'' R_i
-        GemmDesc<double> g;
-        g.M = rc;
-        g.N = rc;
-        g.K = rc;
-        g.lda = rc;
-        g.ldb = rc;
-        g.ldc = Md;
-        g.group1(Rdiag, R2t, Rt);
-        emit_gemm(q, pl, std::move(g));
-      }
+      q.steps.push_back([=](hipStream_t st) { qr_piv_batched(bl->at<QrPivTask>(off2), na, n, rc, kCutTol, st); });
+      // R[0:Kq, block i] += T R_i;  diagonal block = R'' R_i
+      gemm(false, Kq, rc, rc, Md, rc, Md, 1.0, 1.0, Rblk, [&](int k) { return (const double*)Ct[k]; },
+           [&](int k) { return (const double*)Rt[k]; });
+      gemm(false, rc, rc, rc, rc, rc, Md, 0.0, 1.0, Rdiag, [&](int k) { return (const double*)R2t[k]; },
+           [&](int k) { return (const double*)Rt[k]; });
     }
   }
   // core = sum_b c_b G_b x_k R_k[:, block(b, k)]   (Md^d)
