@@ -448,7 +448,7 @@ __global__ __launch_bounds__(JV_NT) void jacobi_vec_kernel(const EigTask<T>* __r
         C_[i] = rdlane(c, P);
         S_[i] = rdlane(sn, P);
       }
-      // ---- columns: A <- A J, V <- V J
+      // ---- columns: B <- A J, V <- V J
       {
         T ap[JV_PPW], aq[JV_PPW], vp[JV_PPW], vq[JV_PPW];
 #pragma unroll
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(JV_NT) void jacobi_vec_kernel(const EigTask<T>* __r
         }
       }
       __syncthreads();
-      // ---- rows: A <- J^T A, pivot blocks exact
+      // ---- rows: A <- J^T B, pivot blocks exact
       {
         T bp[JV_PPW], bq[JV_PPW];
 #pragma unroll
