@@ -19,6 +19,10 @@ Parity status (see the pins in ``tests/test_oracle_*.py``):
   * sGMRES cycle / restarted solve: pinned (textbook GMRES reduction,
     residual identity, exact solutions).
   * adjoint gradients: pinned (dense gradient, finite differences).
+  * MLN-Tucker sGMRES (``oracle.mln``): pinned (dense sketches and the
+    Khatri-Rao identity, Nystrom exactness below the target rank, the
+    memory-efficient truncation identity, reduction to vector sketched GMRES
+    when the recovery is exact, a tiny Poisson solve).
   * effective-rank heuristic's choice of sketch size beyond the exactness
     test: parity unpinned (a heuristic; only its invariance and monotone
     behaviour are tested).
@@ -29,11 +33,12 @@ from .tucker import (Tucker, to_dense, ttm, multi_ttm, unfold, apply_op, transpo
 from .roundsum import RoundParams, roundsum, effective_sketch_size, st_hosvd
 from .sgmres import SGMRESParams, sgmres_cycle, solve, sketched_lstsq
 from .adjoint import adjoint_gradients, loss_and_cotangent
+from . import mln
 
 __all__ = [
     "Tucker", "to_dense", "ttm", "multi_ttm", "unfold", "apply_op", "transpose_terms",
     "dense_operator", "sketch_krp", "sketch_kron", "inner", "exact_norm", "block_dense",
     "scale", "RoundParams", "roundsum", "effective_sketch_size", "st_hosvd",
     "SGMRESParams", "sgmres_cycle", "solve", "sketched_lstsq", "adjoint_gradients",
-    "loss_and_cotangent",
+    "loss_and_cotangent", "mln",
 ]
