@@ -30,7 +30,8 @@
  *     < 0 = error (outputs unspecified, message via tk_last_error()).
  *     Nothing throws across the ABI.  The error message is thread-local.
  *   - Limits of this build: 2 <= d <= 4, n_k <= 512, rank_cap + oversample
- *     <= 64, sketch size s <= 256, maxiter <= 64.
+ *     <= 64, sketch size s <= 256, maxiter <= 64; multilinear Nystrom calls:
+ *     target rank r <= 64 and r + p <= 256.
  *   - Forms: tensors cross the ABI in FP64.  TK_FORM_FP32 runs a call in the
  *     arithmetic of the solver's FP32 form: operands are rounded to FP32 on
  *     entry, products, Gram matrices, eigensolves and contractions run in
@@ -180,6 +181,60 @@ int tsgmres_backward_workspace(const tk_kron_op* op, const tk_tucker* x, const t
  * residual).  *out (host) receives ||sum_b coef_b X_b||_F.  Ranks <= 64. */
 int tucker_norm(const tk_block_sum* x, double* out, void* ws, size_t ws_bytes, void* stream);
 int tucker_norm_workspace(const tk_block_sum* x, size_t* bytes);
+
+/* Multilinear Nystrom (MLN) sketching (Sec. 3.3).  Psi_k are n_k x (r + p)
+ * column-major device matrices (inputs, like every sketch); Omega_k of mode k
+ * is the Khatri-Rao product of the leading r columns of the other modes'
+ * Psi_j: its column l is kron_{j != k} Psi_j[:, l] over j in increasing order
+ * (the row-major unfolding order of the core convention above).  Sketched
+ * form of a tensor X: the core G_Psi = X x_1 Psi_1^T ... x_d Psi_d^T
+ * ((r + p)^d, row-major, dense) and the factor sketches F_k = X_(k) Omega_k
+ * (n_k x r, column-major). */
+typedef struct {
+  int32_t r;             /* target rank of every recovered tensor, 1..64 */
+  int32_t p;             /* oversampling: Psi_k has r + p <= 256 columns */
+  double tol;            /* stop once the sketched relative residual < eta * tol */
+  double eta;            /* sketched-residual correction factor, 0 < eta <= 1 */
+  int32_t maxiter;       /* 1..64 */
+  int32_t k_trunc;       /* window of the truncated orthogonalisation, >= 1 */
+  double breakdown_tol;  /* <= 0: 1e-14 (relative basis-norm and least-squares pivot floor) */
+  int32_t save_memory;   /* 1: memory-efficient variant, sketches outside the
+                            window kept truncated to (r_sol + p_sol)^d cores and
+                            r_sol factor columns; the solution is recovered from
+                            the truncated sketches with Psi_k[:, :r_sol + p_sol] */
+  int32_t r_sol, p_sol;  /* save_memory: 1 <= r_sol <= r, r_sol + p_sol <= r + p */
+} tk_mln_params;
+
+/* MLN sketch of a block sum x = sum_b coef_b X_b (the sketch of every block
+ * summed with its coefficient): writes core ((r + p)^d device doubles) and
+ * F[k] (n_k x r device doubles); diag (device, r + p, optional) receives the
+ * superdiagonal of the core, which equals the Khatri-Rao sketch of x with
+ * S_k = Psi_k.  Block ranks <= 128. */
+int tucker_mln_sketch(const tk_block_sum* x, const double* const* Psi, int32_t r, int32_t p, double* core,
+                      double* const* F, double* diag, void* ws, size_t ws_bytes, void* stream);
+int tucker_mln_sketch_workspace(const tk_block_sum* x, int32_t r, int32_t p, size_t* bytes);
+
+/* MLN recovery of a sketched tensor (core, F) into the Tucker tensor
+ * out = core x_1 P_1 ... x_d P_d with P_k = F_k (Psi_k^T F_k)^+, where the
+ * pseudoinverse drops the directions of Psi_k^T F_k whose column-pivoted QR
+ * remainder is at or below 1e-12 of its largest column.  out->d and out->n
+ * give the shape; out->r receives the numerical ranks (1..r); out->rcap[k]
+ * must be >= r. */
+int tucker_mln_recover(const double* core, const double* const* F, const double* const* Psi, int32_t r, int32_t p,
+                       tk_tucker* out, void* ws, size_t ws_bytes, void* stream);
+int tucker_mln_recover_workspace(int32_t d, const int64_t* n, int32_t r, int32_t p, size_t* bytes);
+
+/* MLN-Tucker sGMRES (Sec. 3.3): one run of at most maxiter iterations (no
+ * restarts) with every basis tensor kept as an MLN sketch, the superdiagonal
+ * of the sketched core as the least-squares sketch, and the solution
+ * recovered from the coefficient-weighted sum of the stored sketches.
+ * b: ranks <= r.  info (optional): status, iters_total, cycles = 1,
+ * true_relres = ||b - L(x)|| / ||b|| (exact), seconds, per-iteration
+ * hist_sketched and hist_ranks; hist_true[0] = true_relres.  Returns the
+ * status (TK_OK / TK_NOT_CONVERGED / TK_BREAKDOWN) or an error. */
+int tsgmres_mln_solve(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* prm, const double* const* Psi,
+                      tk_tucker* x, tk_sgmres_info* info, void* ws, size_t ws_bytes, void* stream);
+int tsgmres_mln_solve_workspace(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* prm, size_t* bytes);
 
 /* Kernel-class timers for performance reporting (not thread-safe; for
  * benchmarks).  kind: 0 GEMM, 1 symmetric eigensolver with eigenvectors

@@ -21,6 +21,8 @@ EXPORTS = [
     "tucker_apply_op", "tucker_apply_op_workspace", "tucker_sketch", "tucker_sketch_workspace",
     "tucker_rhosvd", "tucker_rhosvd_workspace", "tsgmres_solve", "tsgmres_solve_workspace",
     "tsgmres_backward", "tsgmres_backward_workspace", "tucker_norm", "tucker_norm_workspace",
+    "tucker_mln_sketch", "tucker_mln_sketch_workspace", "tucker_mln_recover", "tucker_mln_recover_workspace",
+    "tsgmres_mln_solve", "tsgmres_mln_solve_workspace",
     "tk_kernel_timer", "tk_kernel_timer_read", "tk_last_error", "tk_version",
 ]
 
@@ -49,6 +51,12 @@ class TkSgmresParams(C.Structure):
                 ("max_restarts", C.c_int32), ("k_trunc", C.c_int32), ("rank_cap", C.c_int32),
                 ("oversample", C.c_int32), ("s", C.c_int64), ("eps_trunc", C.c_double), ("eps_min", C.c_double),
                 ("tol_inner_floor", C.c_double), ("x0", C.POINTER(TkTucker))]
+
+
+class TkMlnParams(C.Structure):
+    _fields_ = [("r", C.c_int32), ("p", C.c_int32), ("tol", C.c_double), ("eta", C.c_double),
+                ("maxiter", C.c_int32), ("k_trunc", C.c_int32), ("breakdown_tol", C.c_double),
+                ("save_memory", C.c_int32), ("r_sol", C.c_int32), ("p_sol", C.c_int32)]
 
 
 class TkSgmresInfo(C.Structure):
@@ -85,6 +93,14 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.tsgmres_backward_workspace.argtypes = [P(TkKronOp), P(TkTucker), P(TkBlockSum), P(TkSgmresParams), P(SZ)]
     lib.tucker_norm.argtypes = [P(TkBlockSum), P(C.c_double), VP, SZ, VP]
     lib.tucker_norm_workspace.argtypes = [P(TkBlockSum), P(SZ)]
+    I32, I64 = C.c_int32, C.c_int64
+    lib.tucker_mln_sketch.argtypes = [P(TkBlockSum), P(VP), I32, I32, VP, P(VP), VP, VP, SZ, VP]
+    lib.tucker_mln_sketch_workspace.argtypes = [P(TkBlockSum), I32, I32, P(SZ)]
+    lib.tucker_mln_recover.argtypes = [VP, P(VP), P(VP), I32, I32, P(TkTucker), VP, SZ, VP]
+    lib.tucker_mln_recover_workspace.argtypes = [I32, P(I64), I32, I32, P(SZ)]
+    lib.tsgmres_mln_solve.argtypes = [P(TkKronOp), P(TkTucker), P(TkMlnParams), P(VP), P(TkTucker),
+                                      P(TkSgmresInfo), VP, SZ, VP]
+    lib.tsgmres_mln_solve_workspace.argtypes = [P(TkKronOp), P(TkTucker), P(TkMlnParams), P(SZ)]
     lib.tk_kernel_timer.argtypes = [C.c_int32, C.c_int32]
     lib.tk_kernel_timer_read.argtypes = [C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.tk_last_error.restype = C.c_char_p

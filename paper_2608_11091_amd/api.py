@@ -9,7 +9,10 @@ Layouts (see ``include/tsgmres.h``):
     row-major view of a column-major ``n_k x rcap_k`` factor;
   * operator factors: ``(n_k, n_k)`` row-major tensors or ``None``;
   * sketch factors ``S_k``: ``(s, n_k)`` (column-major ``n_k x s``) and
-    ``Omega_k``: ``(cap + p, n_k)``.
+    ``Omega_k``: ``(cap + p, n_k)``;
+  * multilinear Nystrom sketches ``Psi_k``: ``(r + p, n_k)``; factor
+    sketches ``F_k``: ``(r, n_k)`` (column-major ``n_k x r``); sketched core:
+    ``(r + p,) * d`` (C order).
 """
 from __future__ import annotations
 
@@ -21,10 +24,12 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import TK_MAX_D, TkBlockSum, TkKronOp, TkRoundParams, TkSgmresInfo, TkSgmresParams, TkTucker, check
+from ._abi import (TK_MAX_D, TkBlockSum, TkKronOp, TkMlnParams, TkRoundParams, TkSgmresInfo, TkSgmresParams,
+                   TkTucker, check)
 
 __all__ = ["Tucker", "KronOp", "SolveParams", "apply_op", "sketch", "rhosvd", "norm", "solve", "backward",
-           "TuckerSGMRESLoss", "storage_floats", "kernel_timer", "kernel_timer_read", "solve_workspace_bytes"]
+           "TuckerSGMRESLoss", "storage_floats", "kernel_timer", "kernel_timer_read", "solve_workspace_bytes",
+           "MlnParams", "mln_sketch", "mln_recover", "mln_solve", "mln_solve_workspace_bytes"]
 
 
 def _stream():
@@ -391,3 +396,92 @@ def kernel_timer_read(kind: str):
 def storage_floats(n: Sequence[int], ranks: Sequence[int]) -> int:
     """Floats stored by a Tucker tensor: sum_k n_k r_k + prod_k r_k."""
     return int(sum(a * b for a, b in zip(n, ranks)) + np.prod(ranks))
+
+
+# ---------------------------------------------------------------- multilinear Nystrom
+@dataclasses.dataclass
+class MlnParams:
+    r: int = 32
+    p: int = 32
+    tol: float = 1e-8
+    eta: float = 0.4
+    maxiter: int = 60
+    k_trunc: int = 2
+    breakdown_tol: float = -1.0
+    save_memory: bool = False
+    r_sol: int = 0
+    p_sol: int = 0
+
+    def struct(self) -> TkMlnParams:
+        p = TkMlnParams()
+        p.r, p.p, p.tol, p.eta, p.maxiter, p.k_trunc = self.r, self.p, self.tol, self.eta, self.maxiter, self.k_trunc
+        p.breakdown_tol, p.save_memory, p.r_sol, p.p_sol = self.breakdown_tol, int(self.save_memory), self.r_sol, \
+            self.p_sol
+        return p
+
+
+def mln_sketch(blocks, Psi: Sequence[torch.Tensor], r: int):
+    """Multilinear Nystrom sketch of a block sum; returns ``(core, F, diag)``
+    with core ``(r + p,) * d``, ``F[k]`` of shape ``(r, n_k)`` and the
+    superdiagonal ``diag`` of the core (length ``r + p``)."""
+    lib = _abi.load()
+    bs, keep = _blocks_struct(blocks)
+    x0 = blocks[0][1]
+    dev = x0.core.device
+    rt = int(Psi[0].shape[0])
+    p = rt - int(r)
+    core = torch.zeros((rt,) * x0.d, dtype=torch.float64, device=dev)
+    F = [torch.zeros((r, nk), dtype=torch.float64, device=dev) for nk in x0.n]
+    diag = torch.zeros(rt, dtype=torch.float64, device=dev)
+    nb = C.c_size_t()
+    check(lib.tucker_mln_sketch_workspace(C.byref(bs), int(r), p, C.byref(nb)))
+    ws = _workspace(nb.value, dev)
+    check(lib.tucker_mln_sketch(C.byref(bs), _ptr_array(Psi), int(r), p, C.c_void_p(core.data_ptr()), _ptr_array(F),
+                                C.c_void_p(diag.data_ptr()), C.c_void_p(ws.data_ptr()), nb.value, _stream()))
+    return core, F, diag
+
+
+def mln_recover(core: torch.Tensor, F: Sequence[torch.Tensor], Psi: Sequence[torch.Tensor], r: int) -> Tucker:
+    """Multilinear Nystrom recovery of a sketched tensor (rank capacity r)."""
+    lib = _abi.load()
+    d = core.dim()
+    rt = int(Psi[0].shape[0])
+    n = tuple(int(P.shape[1]) for P in Psi)
+    out = Tucker.empty(n, (r,) * d, core.device)
+    os_ = out.struct()
+    nn = (C.c_int64 * TK_MAX_D)(*(list(n) + [1] * (TK_MAX_D - d)))
+    nb = C.c_size_t()
+    check(lib.tucker_mln_recover_workspace(d, nn, int(r), rt - int(r), C.byref(nb)))
+    ws = _workspace(nb.value, core.device)
+    check(lib.tucker_mln_recover(C.c_void_p(core.data_ptr()), _ptr_array(F), _ptr_array(Psi), int(r), rt - int(r),
+                                 C.byref(os_), C.c_void_p(ws.data_ptr()), nb.value, _stream()))
+    out.ranks = tuple(int(os_.r[k]) for k in range(d))
+    return out
+
+
+def mln_solve_workspace_bytes(op: KronOp, b: Tucker, prm: MlnParams) -> int:
+    lib = _abi.load()
+    ops, k1 = op.struct(b.n)
+    bst = b.struct()
+    ps = prm.struct()
+    nb = C.c_size_t()
+    check(lib.tsgmres_mln_solve_workspace(C.byref(ops), C.byref(bst), C.byref(ps), C.byref(nb)))
+    return int(nb.value)
+
+
+def mln_solve(op: KronOp, b: Tucker, Psi: Sequence[torch.Tensor], prm: MlnParams, workspace=None):
+    """MLN-Tucker sGMRES; returns ``(x, info)``."""
+    lib = _abi.load()
+    ops, k1 = op.struct(b.n)
+    bst = b.struct()
+    ps = prm.struct()
+    nb = C.c_size_t()
+    check(lib.tsgmres_mln_solve_workspace(C.byref(ops), C.byref(bst), C.byref(ps), C.byref(nb)))
+    ws = workspace if workspace is not None and workspace.numel() >= nb.value else _workspace(nb.value, b.core.device)
+    x = Tucker.empty(b.n, (prm.r,) * b.d, b.core.device)
+    xs = x.struct()
+    info, keep = _info(prm.maxiter + 8)
+    check(lib.tsgmres_mln_solve(C.byref(ops), C.byref(bst), C.byref(ps), _ptr_array(Psi), C.byref(xs), C.byref(info),
+                                C.c_void_p(ws.data_ptr()), nb.value, _stream()))
+    x.ranks = tuple(int(xs.r[k]) for k in range(b.d))
+    return x, _info_dict(info, keep, b.d)

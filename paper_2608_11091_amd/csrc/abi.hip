@@ -524,6 +524,133 @@ int do_backward(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xb
   return si.status;
 }
 
+// ---------------------------------------------------------------- multilinear Nystrom
+void check_mln_rank(int r, int p) {
+  TK_CHECK(r >= 1 && r <= 64, kErrUnsupported, "MLN target rank r must be in [1, 64]");
+  TK_CHECK(p >= 0 && r + p <= 256, kErrUnsupported, "MLN: need p >= 0 and r + p <= 256");
+}
+
+std::array<const double*, kMaxD> psi_of(const double* const* Psi, int d) {
+  TK_CHECK(Psi != nullptr, kErrInvalidArg, "Psi is NULL");
+  std::array<const double*, kMaxD> a{};
+  for (int k = 0; k < d; ++k) a[k] = Psi[k];
+  return a;
+}
+
+int do_mln_sketch(const tk_block_sum* x, const double* const* Psi, int r, int p, double* core, double* const* F,
+                  double* diag, Arena& ar, hipStream_t st) {
+  check_mln_rank(r, p);
+  Blob blob;
+  Planner pl(ar, blob);
+  Seq q;
+  Imported im = import_blocks(q, ar, x, 1, 0);
+  const int d = im.sh.d;
+  const auto ps = psi_of(Psi, d);
+  TK_CHECK(F != nullptr, kErrInvalidArg, "factor sketch outputs missing");
+  MlnSk out;
+  out.core = core;
+  for (int k = 0; k < d; ++k) out.F[k] = F[k];
+  plan_mln_sketch(q, pl, im.sh, im.blocks, ps, r, r + p, out, diag);
+  finish_blob(ar, blob, st);
+  if (ar.measuring()) return 0;
+  TK_CHECK(core != nullptr, kErrInvalidArg, "core output is NULL");
+  for (int k = 0; k < d; ++k) {
+    TK_CHECK(ps[k] != nullptr, kErrInvalidArg, "Psi factor is NULL");
+    TK_CHECK(F[k] != nullptr, kErrInvalidArg, "factor sketch output is NULL");
+  }
+  q.run(st);
+  TK_HIP(hipStreamSynchronize(st));
+  return 0;
+}
+
+int do_mln_recover(const double* core, const double* const* F, const double* const* Psi, int r, int p, int d,
+                   const int64_t* n, tk_tucker* out, Arena& ar, hipStream_t st) {
+  check_mln_rank(r, p);
+  check_dims(d, n);
+  TK_CHECK(F != nullptr, kErrInvalidArg, "factor sketches missing");
+  const auto ps = psi_of(Psi, d);
+  Shape sh = shape_of(d, n, r, r, p);
+  Blob blob;
+  Planner pl(ar, blob);
+  Seq q;
+  MlnSk sk;
+  sk.core = const_cast<double*>(core);
+  for (int k = 0; k < d; ++k) sk.F[k] = const_cast<double*>(F[k]);
+  TT<double> o = alloc_tt<double>(ar, sh);
+  plan_mln_recovery(q, pl, sh, sk, ps, r, r + p, o);
+  finish_blob(ar, blob, st);
+  if (ar.measuring()) return 0;
+  TK_CHECK(core != nullptr && out != nullptr, kErrInvalidArg, "core or output is NULL");
+  for (int k = 0; k < d; ++k) {
+    TK_CHECK(ps[k] != nullptr && F[k] != nullptr, kErrInvalidArg, "Psi factor or factor sketch is NULL");
+    TK_CHECK(out->rcap[k] >= r, kErrCapacity, "output rank capacity below r");
+  }
+  q.run(st);
+  export_tt(sh, o, out, st);
+  return 0;
+}
+
+void check_mln_params(const tk_mln_params* prm) {
+  TK_CHECK(prm != nullptr, kErrInvalidArg, "parameters are NULL");
+  check_mln_rank(prm->r, prm->p);
+  TK_CHECK(prm->tol > 0 && prm->eta > 0 && prm->eta <= 1, kErrInvalidArg, "tol > 0 and 0 < eta <= 1 required");
+  TK_CHECK(prm->maxiter >= 1 && prm->maxiter <= 64, kErrUnsupported, "maxiter must be in [1, 64]");
+  TK_CHECK(prm->k_trunc >= 1, kErrInvalidArg, "k_trunc must be >= 1");
+  if (prm->save_memory)
+    TK_CHECK(prm->r_sol >= 1 && prm->r_sol <= prm->r && prm->p_sol >= 0 && prm->r_sol + prm->p_sol <= prm->r + prm->p,
+             kErrInvalidArg, "save_memory needs 1 <= r_sol <= r and r_sol + p_sol <= r + p");
+}
+
+int do_mln_solve(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* prm, const double* const* Psi,
+                 tk_tucker* x, tk_sgmres_info* info, Arena& ar, hipStream_t st) {
+  TK_CHECK(b != nullptr, kErrInvalidArg, "b is NULL");
+  check_dims(b->d, b->n);
+  check_op(op, b->d, b->n);
+  check_tucker(b, "b", b->d, b->n);
+  check_mln_params(prm);
+  const int d = b->d;
+  for (int k = 0; k < d; ++k) TK_CHECK(b->r[k] <= prm->r, kErrCapacity, "rank of b above the target rank r");
+  const auto ps = psi_of(Psi, d);
+  Shape sh = shape_of(d, b->n, prm->r, prm->r, prm->p);
+  Seq imp;
+  TT<double> bi = alloc_tt<double>(ar, sh);
+  emit_import<double>(imp, sh, *b, bi);
+  MlnCfg cfg;
+  cfg.r = prm->r;
+  cfg.p = prm->p;
+  cfg.tol = prm->tol;
+  cfg.eta = prm->eta;
+  cfg.maxiter = prm->maxiter;
+  cfg.k_trunc = prm->k_trunc;
+  cfg.bd_tol = prm->breakdown_tol > 0 ? prm->breakdown_tol : 1e-14;
+  cfg.save_memory = prm->save_memory != 0;
+  cfg.r_sol = prm->r_sol;
+  cfg.p_sol = prm->p_sol;
+  auto solver = make_mln_solver(ar, sh, op_dev(op), bi, cfg, ps, st);
+  if (ar.measuring()) return 0;
+  TK_CHECK(x != nullptr, kErrInvalidArg, "x is NULL");
+  for (int k = 0; k < d; ++k) TK_CHECK(ps[k] != nullptr, kErrInvalidArg, "Psi factor is NULL");
+  imp.run(st);
+  TT<double> xo;
+  MlnInfo mi;
+  mln_solver_run(*solver, xo, mi, st);
+  export_tt(sh, xo, x, st);
+  if (info) {
+    SolveInfo si;
+    si.status = mi.status;
+    si.iters = mi.iters;
+    si.cycles = 1;
+    si.true_relres = mi.true_relres;
+    si.seconds = mi.seconds;
+    si.hist_sketched = mi.hist;
+    si.hist_ranks = mi.ranks;
+    si.hist_true = {mi.true_relres};
+    si.hist_time = {mi.seconds};
+    fill_info(si, info, d);
+  }
+  return mi.status;
+}
+
 }  // namespace
 }  // namespace tk
 
@@ -646,6 +773,66 @@ int tucker_norm_workspace(const tk_block_sum* x, size_t* bytes) {
     const int r = do_norm(x, nullptr, ar, nullptr);
     if (bytes) *bytes = ar.used();
     return r;
+  });
+}
+
+int tucker_mln_sketch(const tk_block_sum* x, const double* const* Psi, int32_t r, int32_t p, double* core,
+                      double* const* F, double* diag, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
+    Arena ar(ws, ws_bytes);
+    return do_mln_sketch(x, Psi, r, p, core, F, diag, ar, as_stream(stream));
+  });
+}
+int tucker_mln_sketch_workspace(const tk_block_sum* x, int32_t r, int32_t p, size_t* bytes) {
+  return guarded([&] {
+    Arena ar(nullptr, 0);
+    // stand-in output addresses: planning only records them (a null core
+    // would select a different contraction form)
+    double* fake = reinterpret_cast<double*>(uintptr_t(0x1000));
+    const double* dummy[TK_MAX_D] = {fake, fake, fake, fake};
+    double* F[TK_MAX_D] = {fake, fake, fake, fake};
+    const int rv = do_mln_sketch(x, dummy, r, p, fake, F, nullptr, ar, nullptr);
+    if (bytes) *bytes = ar.used();
+    return rv;
+  });
+}
+
+int tucker_mln_recover(const double* core, const double* const* F, const double* const* Psi, int32_t r, int32_t p,
+                       tk_tucker* out, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
+    TK_CHECK(out != nullptr, kErrInvalidArg, "output is NULL");
+    Arena ar(ws, ws_bytes);
+    return do_mln_recover(core, F, Psi, r, p, out->d, out->n, out, ar, as_stream(stream));
+  });
+}
+int tucker_mln_recover_workspace(int32_t d, const int64_t* n, int32_t r, int32_t p, size_t* bytes) {
+  return guarded([&] {
+    TK_CHECK(n != nullptr, kErrInvalidArg, "mode sizes are NULL");
+    Arena ar(nullptr, 0);
+    const double* dummy[TK_MAX_D] = {nullptr, nullptr, nullptr, nullptr};
+    const int rv = do_mln_recover(nullptr, dummy, dummy, r, p, d, n, nullptr, ar, nullptr);
+    if (bytes) *bytes = ar.used();
+    return rv;
+  });
+}
+
+int tsgmres_mln_solve(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* prm, const double* const* Psi,
+                      tk_tucker* x, tk_sgmres_info* info, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
+    Arena ar(ws, ws_bytes);
+    return do_mln_solve(op, b, prm, Psi, x, info, ar, as_stream(stream));
+  });
+}
+int tsgmres_mln_solve_workspace(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* prm, size_t* bytes) {
+  return guarded([&] {
+    Arena ar(nullptr, 0);
+    const double* dummy[TK_MAX_D] = {nullptr, nullptr, nullptr, nullptr};
+    const int rv = do_mln_solve(op, b, prm, dummy, nullptr, nullptr, ar, nullptr);
+    if (bytes) *bytes = ar.used();
+    return rv;
   });
 }
 

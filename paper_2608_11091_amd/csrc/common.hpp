@@ -69,17 +69,27 @@ class Arena {
   T* alloc(size_t count) {
     size_t off = (used_ + 255) & ~size_t(255);
     used_ = off + count * sizeof(T);
+    peak_ = used_ > peak_ ? used_ : peak_;
     if (base_ == nullptr) return reinterpret_cast<T*>(uintptr_t(0x1000) + off);  // measuring only
     if (used_ > cap_) throw Error{kErrWorkspace, "workspace too small: need at least " + std::to_string(used_) + " bytes"};
     return reinterpret_cast<T*>(base_ + off);
   }
-  size_t used() const { return used_; }
+  // Bytes the workspace must hold (the high-water mark).
+  size_t used() const { return peak_; }
   bool measuring() const { return base_ == nullptr; }
+  // Scratch scopes: buffers allocated after mark() are handed out again after
+  // rewind(); valid only for plans whose steps never run concurrently.  An
+  // allocation that must outlive every scope (read by steps of several
+  // scopes) is made after seal(), which moves past the high-water mark.
+  size_t mark() const { return used_; }
+  void rewind(size_t m) { used_ = m; }
+  void seal() { used_ = peak_; }
 
  private:
   char* base_;
   size_t cap_;
   size_t used_ = 0;
+  size_t peak_ = 0;
 };
 
 // ---------------------------------------------------------------- device helpers

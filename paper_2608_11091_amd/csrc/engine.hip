@@ -254,6 +254,199 @@ std::function<void(hipStream_t)> fork_steps(Seq& q, size_t from) {
 
 }  // namespace
 
+// Khatri-Rao range sketch of a block sum (Sec. 3.1; also the factor sketches
+// of the multilinear Nystrom method): for every mode k,
+//   Y_k = sum_b coef_b U_bk MTTKRP(G_b; {U_bj^T L_j[:, :w]}_{j != k}, k)   (n_k x w),
+// i.e. the mode-k unfolding of the sum times the Khatri-Rao product of the
+// other modes' L_j[:, :w] (L_j column-major n_j x >= w).
+template <typename T>
+void plan_krp_range(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>& in, const double* coef,
+                    const std::array<const T*, kMaxD>& L, int w, const std::array<T*, kMaxD>& Y,
+                    const int* nb_active) {
+  const int d = sh.d, rc = sh.rc, nb = in.size();
+  Arena& ar = pl.ar;
+  Blob* bl = &pl.blob;
+  const size_t P = size_t(ipow(rc, d - 1));
+  auto nbA = [nb, nb_active]() { return nb_active ? std::min(nb, *nb_active) : nb; };
+  T* Mb = ar.alloc<T>(size_t(nb) * d * rc * w);
+  auto Mp = [&](int b, int j) { return Mb + (size_t(b) * d + j) * rc * w; };
+  for (auto& modes : modes_by_n<T>(sh)) {  // M_bj = U_bj^T L_j (rc x w)
+    const int n = sh.n[modes[0]];
+    GemmDesc<T> g;
+    g.ta = true;
+    g.tb = false;
+    g.M = rc;
+    g.N = w;
+    g.K = n;
+    g.lda = n;
+    g.ldb = n;
+    g.ldc = rc;
+    g.nb = nb_active;
+    const int nm = int(modes.size());
+    g.ngroups_of = [nm](int a) { return a * nm; };
+    for (int b = 0; b < nb; ++b)
+      for (int j : modes) g.group1(Mp(b, j), in.U[b][j], L[j]);
+    emit_gemm(q, pl, std::move(g));
+  }
+  T* Zl = ar.alloc<T>(size_t(nb) * P * w);
+  T* Zf = ar.alloc<T>(size_t(nb) * P * w);
+  {
+    GemmDesc<T> g;  // Zlast_b = G_b x_d M_bd^T : (P x w)
+    g.ta = true;
+    g.tb = false;
+    g.M = int(P);
+    g.N = w;
+    g.K = rc;
+    g.lda = rc;
+    g.ldb = rc;
+    g.ldc = int(P);
+    g.nb = nb_active;
+    g.ngroups_of = [](int a) { return a; };
+    for (int b = 0; b < nb; ++b) g.group1(Zl + size_t(b) * P * w, in.core[b], Mp(b, d - 1));
+    emit_gemm(q, pl, std::move(g));
+    GemmDesc<T> h;  // Zfirst_b = G_b x_1 M_b1^T : (P x w)
+    h.ta = false;
+    h.tb = false;
+    h.M = int(P);
+    h.N = w;
+    h.K = rc;
+    h.lda = int(P);
+    h.ldb = rc;
+    h.ldc = int(P);
+    h.nb = nb_active;
+    h.ngroups_of = [](int a) { return a; };
+    for (int b = 0; b < nb; ++b) h.group1(Zf + size_t(b) * P * w, in.core[b], Mp(b, 0));
+    emit_gemm(q, pl, std::move(h));
+  }
+  T* Tb = ar.alloc<T>(size_t(nb) * d * rc * w);
+  auto Tp = [&](int b, int k) { return Tb + (size_t(b) * d + k) * rc * w; };
+  {
+    std::vector<KrpTask<T>> tasks;
+    for (int b = 0; b < nb; ++b)
+      for (int k = 0; k < d; ++k) {
+        KrpTask<T> t{};
+        t.out = Tp(b, k);
+        t.scale = 1.0;
+        t.ldo = rc;
+        if (k < d - 1) {
+          t.Z = Zl + size_t(b) * P * w;
+          t.f = k;
+          for (int j = 0; j < d - 1; ++j) {
+            t.Mj[j] = Mp(b, j);
+            t.ldm[j] = rc;
+          }
+        } else {
+          t.Z = Zf + size_t(b) * P * w;
+          t.f = d - 2;
+          for (int j = 0; j < d - 1; ++j) {
+            t.Mj[j] = Mp(b, j + 1);
+            t.ldm[j] = rc;
+          }
+        }
+        tasks.push_back(t);
+      }
+    const size_t off = pl.blob.add(tasks);
+    std::vector<int> z(d - 1, rc);
+    q.steps.push_back([=](hipStream_t st) {
+      krp_reduce<T>(bl->at<KrpTask<T>>(off), nbA() * d, d - 1, z.data(), int(P), w, st);
+    });
+  }
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    GemmDesc<T> g;
+    g.ta = false;
+    g.tb = false;
+    g.M = n;
+    g.N = w;
+    g.K = rc;
+    g.lda = n;
+    g.ldb = rc;
+    g.ldc = n;
+    g.nb = nb_active;
+    g.terms_are_blocks = nb_active != nullptr;
+    for (int k : modes) {
+      std::vector<GemmTerm<T>> ts;
+      for (int b = 0; b < nb; ++b) ts.push_back(term<T>(in.U[b][k], Tp(b, k), coef + b));
+      g.group(Y[k], ts);
+    }
+    emit_gemm(q, pl, std::move(g));
+  }
+}
+
+// Core projection of a block sum onto per-mode matrices P_k (n_k x >= w,
+// column-major): C = sum_b coef_b G_b x_1 (P_1^T U_b1) ... x_d (P_d^T U_bd),
+// a w^d row-major core (the RoundSum core of Sec. 3.1 with P_k = the range
+// basis; the sketched core of the multilinear Nystrom method with P_k = Psi_k).
+template <typename T>
+void plan_core_projection(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>& in, const double* coef,
+                          const std::array<const T*, kMaxD>& Pm, int w, T* C, const int* nb_active) {
+  const int d = sh.d, rc = sh.rc, nb = in.size();
+  TK_CHECK(d >= 2, kErrUnsupported, "d = 1");
+  Arena& ar = pl.ar;
+  T* Wb = ar.alloc<T>(size_t(nb) * d * w * rc);
+  auto Wp = [&](int b, int k) { return Wb + (size_t(b) * d + k) * w * rc; };
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    GemmDesc<T> g;
+    g.ta = true;
+    g.tb = false;
+    g.M = w;
+    g.N = rc;
+    g.K = n;
+    g.lda = n;
+    g.ldb = n;
+    g.ldc = w;
+    g.nb = nb_active;
+    const int nm = int(modes.size());
+    g.ngroups_of = [nm](int a) { return a * nm; };
+    for (int b = 0; b < nb; ++b)
+      for (int k : modes) g.group1(Wp(b, k), Pm[k], in.U[b][k]);
+    emit_gemm(q, pl, std::move(g));
+  }
+  // after the TTM of mode k (k = d-1 .. 1) the block tensor has dims
+  // (rc^k, w^(d-k)); size the two ping-pong buffers for the largest
+  size_t tmplen = 0;
+  for (int k = 1; k < d; ++k) tmplen = std::max(tmplen, size_t(ipow(rc, k)) * size_t(ipow(w, d - k)));
+  T* X0 = ar.alloc<T>(size_t(nb) * tmplen);
+  T* X1 = ar.alloc<T>(size_t(nb) * tmplen);
+  int dims[kMaxD];
+  for (int j = 0; j < d; ++j) dims[j] = rc;
+  std::vector<const T*> Xs, Ws;
+  std::vector<T*> Ys;
+  std::vector<const double*> cs;
+  // mode d-1 from the block cores
+  for (int b = 0; b < nb; ++b) {
+    Xs.push_back(in.core[b]);
+    Ws.push_back(Wp(b, d - 1));
+    Ys.push_back(X0 + size_t(b) * tmplen);
+    cs.push_back(coef + b);
+  }
+  emit_ttm<T>(q, pl, d, dims, d - 1, w, Xs, Ws, w, false, Ys, nullptr, nullptr, 1.0, nb_active);
+  dims[d - 1] = w;
+  T* cur = X0;
+  T* nxt = X1;
+  for (int k = d - 2; k >= 1; --k) {
+    Xs.clear();
+    Ws.clear();
+    Ys.clear();
+    for (int b = 0; b < nb; ++b) {
+      Xs.push_back(cur + size_t(b) * tmplen);
+      Ws.push_back(Wp(b, k));
+      Ys.push_back(nxt + size_t(b) * tmplen);
+    }
+    emit_ttm<T>(q, pl, d, dims, k, w, Xs, Ws, w, false, Ys, nullptr, nullptr, 1.0, nb_active);
+    dims[k] = w;
+    std::swap(cur, nxt);
+  }
+  Xs.clear();
+  Ws.clear();
+  for (int b = 0; b < nb; ++b) {
+    Xs.push_back(cur + size_t(b) * tmplen);
+    Ws.push_back(Wp(b, 0));
+  }
+  emit_ttm<T>(q, pl, d, dims, 0, w, Xs, Ws, w, false, {}, C, &cs, 1.0, nb_active);
+}
+
 // ====================================================================== RoundSum
 template <typename T>
 RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>& in, const RoundCfg& cfg,
@@ -418,90 +611,7 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
   else
     emit_width();
 
-  // --- 2. Khatri-Rao range sketch Y_k = sum_b c_b U_bk MTTKRP(G_b; M_b, k)
-  T* Mb = ar.alloc<T>(size_t(nb) * d * rc * sc);
-  auto Mp = [&](int b, int j) { return Mb + (size_t(b) * d + j) * rc * sc; };
-  for (auto& modes : modes_by_n<T>(sh)) {
-    const int n = sh.n[modes[0]];
-    GemmDesc<T> g;
-    g.ta = true;
-    g.tb = false;
-    g.M = rc;
-    g.N = sc;
-    g.K = n;
-    g.lda = n;
-    g.ldb = n;
-    g.ldc = rc;
-    g.nb = nb_active;
-    const int nm = int(modes.size());
-    g.ngroups_of = [nm](int a) { return a * nm; };
-    for (int b = 0; b < nb; ++b)
-      for (int j : modes) g.group1(Mp(b, j), in.U[b][j], omega[j]);
-    emit_gemm(q, pl, std::move(g));
-  }
-  T* Zl = ar.alloc<T>(size_t(nb) * P * sc);
-  T* Zf = ar.alloc<T>(size_t(nb) * P * sc);
-  {
-    GemmDesc<T> g;  // Zlast_b = G_b x_d M_bd^T : (P x sc)
-    g.ta = true;
-    g.tb = false;
-    g.M = int(P);
-    g.N = sc;
-    g.K = rc;
-    g.lda = rc;
-    g.ldb = rc;
-    g.ldc = int(P);
-    g.nb = nb_active;
-    g.ngroups_of = [](int a) { return a; };
-    for (int b = 0; b < nb; ++b) g.group1(Zl + size_t(b) * P * sc, in.core[b], Mp(b, d - 1));
-    emit_gemm(q, pl, std::move(g));
-    GemmDesc<T> h;  // Zfirst_b = G_b x_1 M_b1^T : (P x sc)
-    h.ta = false;
-    h.tb = false;
-    h.M = int(P);
-    h.N = sc;
-    h.K = rc;
-    h.lda = int(P);
-    h.ldb = rc;
-    h.ldc = int(P);
-    h.nb = nb_active;
-    h.ngroups_of = [](int a) { return a; };
-    for (int b = 0; b < nb; ++b) h.group1(Zf + size_t(b) * P * sc, in.core[b], Mp(b, 0));
-    emit_gemm(q, pl, std::move(h));
-  }
-  T* Tb = ar.alloc<T>(size_t(nb) * d * rc * sc);
-  auto Tp = [&](int b, int k) { return Tb + (size_t(b) * d + k) * rc * sc; };
-  {
-    std::vector<KrpTask<T>> tasks;
-    for (int b = 0; b < nb; ++b)
-      for (int k = 0; k < d; ++k) {
-        KrpTask<T> t{};
-        t.out = Tp(b, k);
-        t.scale = 1.0;
-        t.ldo = rc;
-        if (k < d - 1) {
-          t.Z = Zl + size_t(b) * P * sc;
-          t.f = k;
-          for (int j = 0; j < d - 1; ++j) {
-            t.Mj[j] = Mp(b, j);
-            t.ldm[j] = rc;
-          }
-        } else {
-          t.Z = Zf + size_t(b) * P * sc;
-          t.f = d - 2;
-          for (int j = 0; j < d - 1; ++j) {
-            t.Mj[j] = Mp(b, j + 1);
-            t.ldm[j] = rc;
-          }
-        }
-        tasks.push_back(t);
-      }
-    const size_t off = blob.add(tasks);
-    std::vector<int> z(d - 1, rc);
-    q.steps.push_back([=](hipStream_t st) {
-      krp_reduce<T>(bl->at<KrpTask<T>>(off), nbA() * d, d - 1, z.data(), int(P), sc, st);
-    });
-  }
+  // --- 2. Khatri-Rao range sketch Y_k = sum_b c_b U_bk MTTKRP(G_b; U_bj^T Omega_j, k)
   std::array<T*, kMaxD> Y{}, Uh{};
   std::array<double*, kMaxD> Y64{}, Q64{};
   for (int k = 0; k < d; ++k) {
@@ -515,26 +625,7 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       Uh[k] = ar.alloc<T>(size_t(sh.n[k]) * sc);
     }
   }
-  for (auto& modes : modes_by_n<T>(sh)) {
-    const int n = sh.n[modes[0]];
-    GemmDesc<T> g;
-    g.ta = false;
-    g.tb = false;
-    g.M = n;
-    g.N = sc;
-    g.K = rc;
-    g.lda = n;
-    g.ldb = rc;
-    g.ldc = n;
-    g.nb = nb_active;
-    g.terms_are_blocks = nb_active != nullptr;
-    for (int k : modes) {
-      std::vector<GemmTerm<T>> ts;
-      for (int b = 0; b < nb; ++b) ts.push_back(term<T>(in.U[b][k], Tp(b, k), coef + b));
-      g.group(Y[k], ts);
-    }
-    emit_gemm(q, pl, std::move(g));
-  }
+  plan_krp_range<T>(q, pl, sh, in, coef, omega, sc, Y, nb_active);
   // --- 3. orthonormal basis of every range sketch Y_k (FP64): Householder QR
   // when the configuration asks for it, otherwise shifted Cholesky-QR in three
   // passes (Y -> Q -> Y -> Q ping-pong).  Pass 1 is
@@ -623,73 +714,12 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     }
   }
   // --- 4. core projection C^ = sum_b c_b G_b x_k (U^_k^T U_bk)
-  T* Wb = ar.alloc<T>(size_t(nb) * d * sc * rc);
-  auto Wp = [&](int b, int k) { return Wb + (size_t(b) * d + k) * sc * rc; };
-  for (auto& modes : modes_by_n<T>(sh)) {
-    const int n = sh.n[modes[0]];
-    GemmDesc<T> g;
-    g.ta = true;
-    g.tb = false;
-    g.M = sc;
-    g.N = rc;
-    g.K = n;
-    g.lda = n;
-    g.ldb = n;
-    g.ldc = sc;
-    g.nb = nb_active;
-    const int nm = int(modes.size());
-    g.ngroups_of = [nm](int a) { return a * nm; };
-    for (int b = 0; b < nb; ++b)
-      for (int k : modes) g.group1(Wp(b, k), Uh[k], in.U[b][k]);
-    emit_gemm(q, pl, std::move(g));
-  }
-  // after the TTM of mode k (k = d-1 .. 1) the block tensor has dims
-  // (rc^k, sc^(d-k)); size the two ping-pong buffers for the largest
-  size_t tmplen = 0;
-  for (int k = 1; k < d; ++k) tmplen = std::max(tmplen, size_t(ipow(rc, k)) * size_t(ipow(sc, d - k)));
-  T* X0 = ar.alloc<T>(size_t(nb) * tmplen);
-  T* X1 = ar.alloc<T>(size_t(nb) * tmplen);
   T* Cb[2] = {ar.alloc<T>(sclen), ar.alloc<T>(sclen)};
   T* Bt = ar.alloc<T>(sclen);
   {
-    int dims[kMaxD];
-    for (int j = 0; j < d; ++j) dims[j] = rc;
-    std::vector<const T*> Xs, Ws;
-    std::vector<T*> Ys;
-    std::vector<const double*> cs;
-    T* cur = nullptr;
-    // mode d-1 from the block cores
-    for (int b = 0; b < nb; ++b) {
-      Xs.push_back(in.core[b]);
-      Ws.push_back(Wp(b, d - 1));
-      Ys.push_back(X0 + size_t(b) * tmplen);
-      cs.push_back(coef + b);
-    }
-    if (d == 1) TK_CHECK(false, kErrUnsupported, "d = 1");
-    emit_ttm<T>(q, pl, d, dims, d - 1, sc, Xs, Ws, sc, false, Ys, nullptr, nullptr, 1.0, nb_active);
-    dims[d - 1] = sc;
-    cur = X0;
-    T* nxt = X1;
-    for (int k = d - 2; k >= 1; --k) {
-      Xs.clear();
-      Ws.clear();
-      Ys.clear();
-      for (int b = 0; b < nb; ++b) {
-        Xs.push_back(cur + size_t(b) * tmplen);
-        Ws.push_back(Wp(b, k));
-        Ys.push_back(nxt + size_t(b) * tmplen);
-      }
-      emit_ttm<T>(q, pl, d, dims, k, sc, Xs, Ws, sc, false, Ys, nullptr, nullptr, 1.0, nb_active);
-      dims[k] = sc;
-      std::swap(cur, nxt);
-    }
-    Xs.clear();
-    Ws.clear();
-    for (int b = 0; b < nb; ++b) {
-      Xs.push_back(cur + size_t(b) * tmplen);
-      Ws.push_back(Wp(b, 0));
-    }
-    emit_ttm<T>(q, pl, d, dims, 0, sc, Xs, Ws, sc, false, {}, Cb[0], &cs, 1.0, nb_active);
+    std::array<const T*, kMaxD> Uc{};
+    for (int k = 0; k < d; ++k) Uc[k] = Uh[k];
+    plan_core_projection<T>(q, pl, sh, in, coef, Uc, sc, Cb[0], nb_active);
   }
   // --- 5. ST-HOSVD of C^, modes 1..d in order.  Per mode the truncation is
   //        decided by a Jacobi eigen-solve of the Gram of the ROTATED unfolding
@@ -1218,6 +1248,24 @@ void plan_gemm(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int K, const
   emit_gemm(q, pl, std::move(g));
 }
 
+template <typename T>
+void plan_gemm_batched(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int K, const std::vector<const T*>& A,
+                       int lda, const std::vector<const T*>& B, int ldb, const std::vector<T*>& C, int ldc,
+                       double alpha) {
+  TK_CHECK(A.size() == B.size() && A.size() == C.size(), kErrInvalidArg, "batched GEMM: table sizes differ");
+  GemmDesc<T> g;
+  g.ta = ta;
+  g.tb = tb;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  for (size_t i = 0; i < C.size(); ++i) g.group1(C[i], A[i], B[i], nullptr, nullptr, nullptr, alpha);
+  emit_gemm(q, pl, std::move(g));
+}
+
 #define TK_INST(T)                                                                                             \
   template void plan_ttm<T>(Seq&, Planner&, int, const int*, int, int, const T*, const T*, int, bool, T*);     \
   template void plan_unfold_gram<T>(Seq&, Planner&, int, const int*, int, const T*, const T*, T*, int, double); \
@@ -1230,7 +1278,14 @@ void plan_gemm(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int K, const
   template void plan_sketch<T>(Seq&, Planner&, const Shape&, const Blocks<T>&, const std::array<const T*, kMaxD>&, \
                                int, double*);                                                                  \
   template void plan_inner<T>(Seq&, Planner&, const Shape&, const std::vector<TT<T>>&, const Blocks<T>&,      \
-                              double*, double, std::vector<T*>*);
+                              double*, double, std::vector<T*>*);                                              \
+  template void plan_gemm_batched<T>(Seq&, Planner&, bool, bool, int, int, int, const std::vector<const T*>&, \
+                                     int, const std::vector<const T*>&, int, const std::vector<T*>&, int, double); \
+  template void plan_krp_range<T>(Seq&, Planner&, const Shape&, const Blocks<T>&, const double*,              \
+                                  const std::array<const T*, kMaxD>&, int, const std::array<T*, kMaxD>&,     \
+                                  const int*);                                                                 \
+  template void plan_core_projection<T>(Seq&, Planner&, const Shape&, const Blocks<T>&, const double*,        \
+                                        const std::array<const T*, kMaxD>&, int, T*, const int*);
 TK_INST(double)
 TK_INST(float)
 #undef TK_INST

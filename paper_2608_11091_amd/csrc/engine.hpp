@@ -160,8 +160,72 @@ template <typename T>
 void plan_gemm(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int K, const T* A, int lda, const T* B, int ldb,
                T* C, int ldc, double alpha, double beta);
 
+// C_i = alpha op(A_i) op(B_i) for equally shaped problems, one launch.
+template <typename T>
+void plan_gemm_batched(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int K, const std::vector<const T*>& A,
+                       int lda, const std::vector<const T*>& B, int ldb, const std::vector<T*>& C, int ldc,
+                       double alpha);
+
+// Khatri-Rao range sketch of a block sum with per-block device coefficients
+// coef[b]: Y_k = sum_b coef_b U_bk MTTKRP(G_b; {U_bj^T L_j[:, :w]}_{j != k}, k)
+// (n_k x w; L_j column-major n_j x >= w).  The range sketch of RoundSum
+// (Sec. 3.1) and the factor sketches of the multilinear Nystrom method.
+template <typename T>
+void plan_krp_range(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>& in, const double* coef,
+                    const std::array<const T*, kMaxD>& L, int w, const std::array<T*, kMaxD>& Y,
+                    const int* nb_active);
+// Core projection C = sum_b coef_b G_b x_1 (P_1^T U_b1) ... x_d (P_d^T U_bd)
+// (w^d row-major; P_k column-major n_k x >= w).
+template <typename T>
+void plan_core_projection(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>& in, const double* coef,
+                          const std::array<const T*, kMaxD>& Pm, int w, T* C, const int* nb_active);
+
 // Exact squared Frobenius norm of a block sum (QR of concatenated factors).
 void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>& in, double* out_norm2);
+
+// ------------------------------------------------------------------ multilinear Nystrom
+// Sketched form of a Tucker tensor X (Sec. 3.3): the projected core
+// G_Psi = X x_1 Psi_1^T ... x_d Psi_d^T (rt^d, row-major) and the factor
+// sketches F_k = X_(k) (Khatri-Rao product of the other modes' Psi_j[:, :r])
+// (n_k x r, column-major).  Psi_k: n_k x rt column-major, rt = r + p.
+struct MlnSk {
+  double* core = nullptr;
+  double* F[kMaxD] = {nullptr, nullptr, nullptr, nullptr};
+};
+MlnSk alloc_mln(Arena& ar, const Shape& sh, int r, int rt);
+// Sketch of a block sum (every block sketched, then summed with its
+// coefficient).  diag (optional, device rt): the superdiagonal of G_Psi, which
+// is the Khatri-Rao sketch (Psi_1 (.) ... (.) Psi_d)^T vec(X).
+void plan_mln_sketch(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>& in,
+                     const std::array<const double*, kMaxD>& Psi, int r, int rt, const MlnSk& out, double* diag);
+// Recovery X~ = G_Psi x_k (F_k (Psi_k^T F_k)^+) into `out` (capacity sh.rc >= r;
+// ranks = numerical ranks of Psi_k^T F_k, at least 1).
+void plan_mln_recovery(Seq& q, Planner& pl, const Shape& sh, const MlnSk& sk,
+                       const std::array<const double*, kMaxD>& Psi, int r, int rt, const TT<double>& out);
+
+struct MlnCfg {
+  int r = 32, p = 32;
+  double tol = 1e-8, eta = 0.4;
+  int maxiter = 60, k_trunc = 2;
+  double bd_tol = 1e-14;
+  bool save_memory = false;
+  int r_sol = 0, p_sol = 0;
+};
+struct MlnInfo {
+  int status = 1, iters = 0;
+  double true_relres = 1.0, seconds = 0.0;
+  std::vector<double> hist;  // relative sketched residual per iteration
+  std::vector<int> ranks;    // d per iteration: ranks of the new basis tensor
+};
+class MlnSolver;
+struct MlnSolverDel {
+  void operator()(MlnSolver* s) const;
+};
+using MlnSolverPtr = std::unique_ptr<MlnSolver, MlnSolverDel>;
+// MLN-Tucker sGMRES on L(X) = b, planned once (b's ranks <= cfg.r).
+MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const TT<double>& b,
+                             const MlnCfg& cfg, const std::array<const double*, kMaxD>& Psi, hipStream_t st);
+void mln_solver_run(MlnSolver& s, TT<double>& x_out, MlnInfo& info, hipStream_t st);
 
 // ------------------------------------------------------------------ solver
 struct SolveCfg {

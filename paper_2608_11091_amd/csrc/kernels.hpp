@@ -82,10 +82,13 @@ void qr_batched(const QrTask* tasks_d, int ntasks, int n, int cap, const int* m_
 // R[j][c]: coefficient of input column c on basis column j (cap x cap).
 struct QrPivTask {
   const double* Y;    // n x cap, ld n
-  const double* ref;  // n x cap, ld n: reference columns for the cut
+  const double* ref;  // n x cap, ld n: reference columns for the cut; null =
+                      // the largest column of Y for every column (global cut)
   double* Q;          // n x cap, ld n
-  double* R;          // cap x cap
+  double* R;          // cap x cap, or null
   const int* m;       // active columns (device), or null = cap
+  double* Rt = nullptr;     // optional: R transposed (cap x cap, Rt[c][j] = R[j][c])
+  int* rank_out = nullptr;  // optional: number of basis columns kept
 };
 void qr_piv_batched(const QrPivTask* tasks_d, int ntasks, int n, int cap, double drop_tol, hipStream_t st);
 
@@ -164,6 +167,19 @@ void mat_axpy(const T* X, int ldx, T* Y, int ldy, int rows, int cols, hipStream_
 // out[l] = sum_b base[b * stride + l] (fixed order), as double.
 template <typename T>
 void sum_vectors(const T* base, size_t stride, int nb, int len, double* out, hipStream_t st);
+// Linear combinations of flat arrays, one task t < ntasks per output:
+//   y[t][e] = (accumulate ? y[t][e] : 0) + sum_{j < min(nx, limit)} s[j] (*c[j]) x[t * nx + j][e]
+// for e < len[t] (c[j] null = 1).  All tables are device arrays; nx <=
+// kLincombMax; the outputs of one launch must not overlap any of its inputs.
+constexpr int kLincombMax = 128;
+template <typename T>
+void lincomb(T* const* y, const T* const* x, const double* const* c, const double* s, const size_t* len,
+             int ntasks, int nx, size_t maxlen, int accumulate, int limit, hipStream_t st);
+// out[i] = src[i * stride] for i < n, as double.
+template <typename T>
+void strided_gather(const T* src, size_t stride, int n, double* out, hipStream_t st);
+// dst[i] = max(src[i], lo) for i < n.
+void ints_at_least(const int* src, int* dst, int n, int lo, hipStream_t st);
 // Copy n ints.
 void copy_ints(const int* src, int* dst, int n, hipStream_t st);
 // dst[i] = sqrt(src[i]) for i < n.

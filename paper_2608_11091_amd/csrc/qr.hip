@@ -182,10 +182,19 @@ __global__ __launch_bounds__(QR_NT) void qr_piv_kernel(const QrPivTask* __restri
   for (int c = 0; c < QR_MC; ++c) a[c] = (row < n && c < m) ? tk_.Y[row + (size_t)c * n] : 0.0;
   column_sums(
       [&](int c) {
-        const double v = (row < n && c < m) ? tk_.ref[row + (size_t)c * n] : 0.0;
+        const double v = (row < n && c < m) ? (tk_.ref ? tk_.ref[row + (size_t)c * n] : a[c]) : 0.0;
         return v * v;
       },
       red, fref2);
+  if (tk_.ref == nullptr) {
+    // global cut: every column is measured against the largest input column
+    if (row == 0) {
+      double mx = 0.0;
+      for (int c = 0; c < m; ++c) mx = fmax(mx, fref2[c]);
+      for (int c = 0; c < m; ++c) fref2[c] = mx;
+    }
+    __syncthreads();
+  }
 
   unsigned long long unch = m >= 64 ? ~0ull : ((1ull << m) - 1ull);
   int nlive = 0;
@@ -267,6 +276,14 @@ __global__ __launch_bounds__(QR_NT) void qr_piv_kernel(const QrPivTask* __restri
     for (int c = 0; c < QR_MC; ++c)
       if (c < cap) tk_.R[row + (size_t)c * cap] = (row < nlive && c < m && ((ok >> c) & 1ull)) ? a[c] : 0.0;
   }
+  if (tk_.Rt != nullptr && row < cap) {
+    unsigned long long ok = unch;
+    for (int jj = row; jj < nlive; ++jj) ok |= 1ull << piv_s[jj];
+#pragma unroll
+    for (int c = 0; c < QR_MC; ++c)
+      if (c < cap) tk_.Rt[c + (size_t)row * cap] = (row < nlive && c < m && ((ok >> c) & 1ull)) ? a[c] : 0.0;
+  }
+  if (tk_.rank_out != nullptr && row == 0) *tk_.rank_out = nlive;
 
   // ---------------- Q, backward accumulation in place (reflector j stored in column piv[j])
   unsigned long long later = 0ull;

@@ -1,5 +1,6 @@
 // Small bookkeeping kernels: coefficient gathering, zero-sum fix-up,
 // accumulation, vector sums and the per-iteration status record.
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -64,6 +65,39 @@ __global__ void zero_cols_from_kernel(T* A, int ld, int rows, int cols, const in
   if (e >= len) return;
   const int c = int(e / rows), r = int(e % rows);
   if (c >= from) A[r + size_t(c) * ld] = T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void lincomb_kernel(T* const* y, const T* const* x, const double* const* c,
+                                                      const double* s, const size_t* len, int ldx, int nx,
+                                                      int accumulate) {
+  __shared__ double cf[kLincombMax];
+  __shared__ const T* xp[kLincombMax];
+  const int t = blockIdx.y;
+  for (int j = threadIdx.x; j < nx; j += blockDim.x) {
+    cf[j] = s[j] * (c[j] ? *c[j] : 1.0);
+    xp[j] = x[size_t(t) * ldx + j];
+  }
+  __syncthreads();
+  T* yt = y[t];
+  const size_t n = len[t];
+  const size_t step = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += step) {
+    double acc = accumulate ? double(yt[e]) : 0.0;
+    for (int j = 0; j < nx; ++j) acc += cf[j] * double(xp[j][e]);
+    yt[e] = T(acc);
+  }
+}
+
+template <typename T>
+__global__ void strided_gather_kernel(const T* src, size_t stride, int n, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = double(src[size_t(i) * stride]);
+}
+
+__global__ void ints_at_least_kernel(const int* src, int* dst, int n, int lo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = max(src[i], lo);
 }
 
 __global__ void copy_ints_kernel(const int* src, int* dst, int n) {
@@ -159,6 +193,32 @@ hipStream_t side_stream() {
   return s;
 }
 
+template <typename T>
+void lincomb(T* const* y, const T* const* x, const double* const* c, const double* s, const size_t* len,
+             int ntasks, int nx, size_t maxlen, int accumulate, int limit, hipStream_t st) {
+  TK_CHECK(nx <= kLincombMax, kErrUnsupported, "linear combination of more than 128 arrays");
+  const int na = std::max(0, std::min(nx, limit));
+  if (ntasks <= 0 || maxlen == 0) return;
+  const size_t want = (maxlen + 1023) / 1024;  // about 4 elements per thread
+  const int blocks = int(want < 1024 ? want : 1024);
+  hipLaunchKernelGGL((lincomb_kernel<T>), dim3(blocks, ntasks), dim3(256), 0, st, y, x, c, s, len, nx, na,
+                     accumulate);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void strided_gather(const T* src, size_t stride, int n, double* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((strided_gather_kernel<T>), dim3(ceil_div(n, 256)), dim3(256), 0, st, src, stride, n, out);
+  TK_LAUNCH_CHECK();
+}
+
+void ints_at_least(const int* src, int* dst, int n, int lo, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(ints_at_least_kernel, dim3(1), dim3(64), 0, st, src, dst, n, lo);
+  TK_LAUNCH_CHECK();
+}
+
 void copy_ints(const int* src, int* dst, int n, hipStream_t st) {
   hipLaunchKernelGGL(copy_ints_kernel, dim3(1), dim3(64), 0, st, src, dst, n);
   TK_LAUNCH_CHECK();
@@ -241,5 +301,8 @@ template void mat_axpy<double>(const double*, int, double*, int, int, int, hipSt
 template void mat_axpy<float>(const float*, int, float*, int, int, int, hipStream_t);
 template void sum_vectors<double>(const double*, size_t, int, int, double*, hipStream_t);
 template void sum_vectors<float>(const float*, size_t, int, int, double*, hipStream_t);
+template void lincomb<double>(double* const*, const double* const*, const double* const*, const double*,
+                              const size_t*, int, int, size_t, int, int, hipStream_t);
+template void strided_gather<double>(const double*, size_t, int, double*, hipStream_t);
 
 }  // namespace tk

@@ -1,0 +1,183 @@
+"""GPU parity of the multilinear Nystrom path (Sec. 3.3: sketch, sum,
+recovery and the MLN-Tucker sGMRES solver) against the FP64 oracle, through
+the C ABI, on identical seeded inputs.  Tolerances:
+  * sketched cores, factor sketches and the superdiagonal sketch: relative
+    error <= 1e-12 of each array's norm (one contraction order apart);
+  * recovery: the recovered tensor against the oracle's, as tensors (exact
+    norm of the difference) <= 1e-10 relative; numerical ranks bit-exact
+    where the spectrum of Psi_k^T F_k has a gap across the 1e-12 cut;
+  * solver: per-iteration relative sketched residuals within 1e-8 relative
+    (or 1e-13 absolute), the same iteration count and status, the true
+    residual and the solution within 1e-8 relative.
+Sizes span several 64-wide GEMM tiles with ragged tails (n = 77, 70, 65)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mln as M
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def tk():
+    import paper_2608_11091_amd as tk
+    tk.load()
+    return tk
+
+
+def _rand_tucker(rng, n, r):
+    return O.Tucker(rng.standard_normal(tuple(r)), [rng.standard_normal((nk, rk)) for nk, rk in zip(n, r)])
+
+
+def _gpu(tk, X, rcap=None):
+    return tk.Tucker.from_numpy(X.core, X.U, rcap=rcap)
+
+
+def _cpu(tk, X):
+    core, U = X.to_numpy()
+    return O.Tucker(core, U)
+
+
+def _cm(Mx):
+    """numpy n x s (column-major semantics) -> torch (s, n) contiguous."""
+    return torch.from_numpy(np.ascontiguousarray(Mx.T)).cuda()
+
+
+def _dist(A, B):
+    return O.exact_norm([(1.0, A), (-1.0, B)]) / O.exact_norm([(1.0, B)])
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+SKETCH_CASES = [
+    ((77, 70, 65), [(5, 7, 6), (3, 2, 4), (6, 6, 6)], 20, 12),
+    ((21, 19, 22, 20), [(3, 4, 2, 5), (2, 2, 2, 2)], 6, 5),
+]
+
+
+@pytest.mark.parametrize("n,ranks,r,p", SKETCH_CASES)
+def test_mln_sketch_parity(tk, n, ranks, r, p):
+    rng = np.random.default_rng(11)
+    blocks = [(float(rng.uniform(-2, 2)), _rand_tucker(rng, n, rk)) for rk in ranks]
+    Psi = [rng.standard_normal((nk, r + p)) for nk in n]
+    print(f"mln sketch n={n} ranks={ranks} r={r} p={p}", flush=True)
+    ref, dref = M.mln_sketch(blocks, Psi, r)
+    core, F, diag = tk.mln_sketch([(c, _gpu(tk, X, (8,) * len(n))) for c, X in blocks], [_cm(P) for P in Psi], r)
+    assert _rel(core.cpu().numpy(), ref.core) <= 1e-12
+    for k in range(len(n)):
+        assert _rel(F[k].cpu().numpy().T, ref.F[k]) <= 1e-12, k
+    assert _rel(diag.cpu().numpy(), dref) <= 1e-12
+    # the superdiagonal is the Khatri-Rao sketch with S_k = Psi_k
+    assert _rel(diag.cpu().numpy(), O.sketch_krp(blocks, Psi)) <= 1e-12
+
+
+def test_mln_recover_full_rank_parity(tk):
+    # a sum whose unfoldings have rank above r: Psi_k^T F_k has full column rank
+    rng = np.random.default_rng(12)
+    n, r, p = (77, 70, 65), 20, 12
+    blocks = [(1.0, _rand_tucker(rng, n, (12, 12, 12))), (-0.7, _rand_tucker(rng, n, (12, 11, 10)))]
+    Psi = [rng.standard_normal((nk, r + p)) for nk in n]
+    sk, _ = M.mln_sketch(blocks, Psi, r)
+    ref = M.mln_recovery(sk, Psi)
+    got = tk.mln_recover(torch.from_numpy(sk.core).cuda(), [_cm(F) for F in sk.F], [_cm(P) for P in Psi], r)
+    print(f"mln recover full rank: ranks {got.ranks}", flush=True)
+    assert got.ranks == (r,) * 3
+    assert _dist(_cpu(tk, got), ref) <= 1e-10
+
+
+@pytest.mark.parametrize("ranks", [(2, 2, 2), (1, 3, 2)])
+def test_mln_recover_rank_deficient_is_exact(tk, ranks):
+    # unfolding ranks below r: Psi_k^T F_k is rank deficient, the cut drops the
+    # rounding-level directions and the recovery reproduces the sum
+    rng = np.random.default_rng(13)
+    n, r, p = (40, 33, 50), 8, 6
+    blocks = [(1.0, _rand_tucker(rng, n, ranks)), (0.5, _rand_tucker(rng, n, ranks))]
+    Psi = [rng.standard_normal((nk, r + p)) for nk in n]
+    sk, _ = M.mln_sketch(blocks, Psi, r)
+    ref = M.mln_recovery(sk, Psi)
+    got = tk.mln_recover(torch.from_numpy(sk.core).cuda(), [_cm(F) for F in sk.F], [_cm(P) for P in Psi], r)
+    print(f"mln recover deficient {ranks}: ranks {got.ranks}", flush=True)
+    # numerical ranks of Psi_k^T F_k: per block min(r_k, prod_{j != k} r_j), summed
+    expect = tuple(2 * min(ranks[k], int(np.prod([ranks[j] for j in range(3) if j != k]))) for k in range(3))
+    sv = [np.linalg.svd(P.T @ F, compute_uv=False) for P, F in zip(Psi, sk.F)]
+    assert expect == tuple(int(np.sum(s > 1e-12 * s[0])) for s in sv)
+    assert got.ranks == expect
+    X = O.Tucker(*_sum_as_tucker(blocks))
+    assert _dist(_cpu(tk, got), X) <= 1e-10
+    assert _dist(_cpu(tk, got), ref) <= 1e-10
+
+
+def _sum_as_tucker(blocks):
+    """Block sum as one Tucker tensor (block-diagonal core, concatenated factors)."""
+    d = blocks[0][1].d
+    rs = [sum(X.U[k].shape[1] for _, X in blocks) for k in range(d)]
+    core = np.zeros(rs)
+    off = [0] * d
+    for c, X in blocks:
+        sl = tuple(slice(o, o + X.core.shape[k]) for k, o in enumerate(off))
+        core[sl] = c * X.core
+        off = [o + X.core.shape[k] for k, o in enumerate(off)]
+    U = [np.concatenate([X.U[k] for _, X in blocks], axis=1) for k in range(d)]
+    return core, U
+
+
+def _convdiff(n, d=3):
+    from workloads import centered_difference_1d, laplacian_1d
+    L, D = laplacian_1d(n), centered_difference_1d(n)
+    terms = [(1e-2, [L if j == k else None for j in range(d)]) for k in range(d)]
+    terms += [(c, [D if j == k else None for j in range(d)]) for k, c in zip(range(d), (1.0, 0.5, 0.25))]
+    return terms
+
+
+def _compare_solves(tk, terms, B, Psi, prm_o, prm_g):
+    X, info = M.mln_sgmres(terms, B, Psi, prm_o)
+    xg, ig = tk.mln_solve(tk.KronOp.from_terms(terms), _gpu(tk, B, (prm_g.r,) * B.d), [_cm(P) for P in Psi], prm_g)
+    print(f"  oracle: status {info['status']} iters {info['iters']} true {info['true_relres']:.3e}", flush=True)
+    print(f"  gpu:    status {ig['status']} iters {ig['iters']} true {ig['true_relres']:.3e} ranks {xg.ranks}",
+          flush=True)
+    assert ig["status"] == info["status"]
+    assert ig["iters"] == len(info["hist"])
+    h_o, h_g = np.array(info["hist"]), np.array(ig["hist"])
+    assert len(h_g) == len(h_o)
+    dev = np.abs(h_g - h_o)
+    assert np.all(dev <= 1e-8 * np.abs(h_o) + 1e-13), dev.max()
+    assert abs(ig["true_relres"] - info["true_relres"]) <= 1e-8 * info["true_relres"] + 1e-13
+    assert _dist(_cpu(tk, xg), X) <= 1e-8
+    return info, ig
+
+
+@pytest.mark.parametrize("save", [False, True])
+def test_mln_solve_parity_convdiff(tk, save):
+    rng = np.random.default_rng(14)
+    n, r, p = 40, 10, 14
+    terms = _convdiff(n)
+    B = _rand_tucker(rng, (n,) * 3, (3, 3, 3))
+    from workloads import draw_mln_sketches
+    Psi = draw_mln_sketches((n,) * 3, r, p)
+    kw = dict(r=r, p=p, tol=1e-6, eta=0.4, maxiter=25, k_trunc=2)
+    if save:
+        kw.update(save_memory=True, r_sol=6, p_sol=6)
+    print(f"mln solve convdiff n={n} r={r} p={p} save={save}", flush=True)
+    _compare_solves(tk, terms, B, Psi, M.MLNParams(**kw), tk.MlnParams(**kw))
+
+
+def test_mln_solve_parity_poisson_breakdown(tk):
+    # full target rank on a tiny Poisson problem: the recovery is exact and the
+    # run ends by convergence or a lucky breakdown exactly as in the oracle
+    from workloads import laplacian_1d
+    n = 6
+    L = laplacian_1d(n)
+    terms = [(1.0, [L if j == k else None for j in range(3)]) for k in range(3)]
+    B = O.Tucker(np.ones((1, 1, 1)), [np.ones((n, 1))] * 3)
+    rng = np.random.default_rng(5)
+    r, p = n, 40
+    Psi = [rng.standard_normal((n, r + p)) for _ in range(3)]
+    kw = dict(r=r, p=p, tol=1e-9, maxiter=40, k_trunc=40)
+    print("mln solve poisson n=6", flush=True)
+    info, ig = _compare_solves(tk, terms, B, Psi, M.MLNParams(**kw), tk.MlnParams(**kw))
+    assert ig["true_relres"] <= 1e-8

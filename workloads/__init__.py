@@ -122,6 +122,13 @@ def draw_sketches(n: Sequence[int], s: int, cap: int, p: int, seed: int = 0):
     return S, Om
 
 
+def draw_mln_sketches(n: Sequence[int], r: int, p: int, seed: int = 7):
+    """Gaussian N(0,1) multilinear Nystrom sketches Psi_1..Psi_d
+    (n_k x (r + p)) from one seeded stream."""
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((nk, r + p)) for nk in n]
+
+
 def _gaussian_tucker(rng, n, ranks):
     core = rng.standard_normal(tuple(ranks))
     U = [rng.standard_normal((nk, rk)) for nk, rk in zip(n, ranks)]
