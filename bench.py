@@ -34,7 +34,7 @@ KERNEL_NAME = {
     "qr": "chol_kernel: Cholesky of the range-sketch Gram (Cholesky-QR3)",
     "krp": "krp_kernel: Khatri-Rao / MTTKRP core reductions",
     "ls": "ls_add_kernel: sketched least-squares column update",
-    "eigvals": "tridiag_bisect_kernel: eigenvalues for the effective-rank rule",
+    "eigvals": "tridiag_reg_kernel: eigenvalues for the effective-rank rule",
 }
 # FP32 form: eigensolvers and GEMMs inside cycles run in FP32 (vector ALU / MFMA)
 BOUND = {"gemm": ("mfma", PEAK["fp32"]), "jacobi": ("alu", 157.3), "qr": ("alu", 78.6), "krp": ("alu", 157.3),
@@ -103,6 +103,78 @@ def cpu_baseline(w, iters: int):
                        f"same workload, {dt:.1f} s")
 
 
+def mln_bench(tk, torch, w, op, b, args):
+    """MLN-Tucker sGMRES (one run, no restarts) on the same workload: timed
+    solves, the dominant kernel class with its roofline, the memory-efficient
+    variant, and the oracle on a bounded sample."""
+    import dataclasses
+
+    from workloads import draw_mln_sketches
+    r, p = args.mln_r, args.mln_p
+    Psi_np = draw_mln_sketches(w.n, r, p)
+    Psi = [_cm(torch, P) for P in Psi_np]
+    prm = tk.MlnParams(r=r, p=p, tol=args.tol, eta=w.eta, maxiter=w.maxiter, k_trunc=w.k_trunc)
+    prm_save = dataclasses.replace(prm, save_memory=True, r_sol=max(1, r // 2), p_sol=p // 2)
+    ws_full = tk.mln_solve_workspace_bytes(op, b, prm)
+    ws_save = tk.mln_solve_workspace_bytes(op, b, prm_save)
+    ws = torch.empty(max(ws_full, ws_save), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        tk.mln_solve(op, b, Psi, prm, workspace=ws)
+    torch.cuda.synchronize()
+    for k in CLASSES:
+        tk.kernel_timer(k, True)
+    tk.mln_solve(op, b, Psi, prm, workspace=ws)
+    torch.cuda.synchronize()
+    classes = {}
+    for k in CLASSES:
+        n_, ms_, _, _ = tk.kernel_timer_read(k)
+        tk.kernel_timer(k, False)
+        classes[k] = dict(launches=n_, total_ms=ms_, avg_us=(ms_ * 1e3 / n_) if n_ else 0.0)
+    dom = max(classes, key=lambda k: classes[k]["total_ms"])
+    tk.kernel_timer(dom, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [tk.mln_solve(op, b, Psi, prm, workspace=ws)[1] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, kms, kflops, kbytes = tk.kernel_timer_read(dom)
+    tk.kernel_timer(dom, False)
+    t1 = time.perf_counter()
+    isave = tk.mln_solve(op, b, Psi, prm_save, workspace=ws)[1]
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t1
+    # the MLN path runs in FP64 throughout: FP64 matrix-core / vector peaks
+    bound, peak = {"gemm": ("mfma", PEAK["fp64"])}.get(dom, (BOUND[dom][0], 78.6))
+    name = {"qr": "qr_piv_kernel / qr_kernel: pivoted and Householder QRs of the recovery and exact norms"}.get(
+        dom, KERNEL_NAME[dom])
+    achieved = (kflops / (kms * 1e-3)) / 1e12 if kms > 0 else 0.0
+    inf = infos[-1]
+    out = dict(method="MLN-Tucker sGMRES (Sec. 3.3)", r=r, p=p, iters_per_s=sum(i["iters"] for i in infos) / dt,
+               ms_per_iter=dt / max(1, sum(i["iters"] for i in infos)) * 1e3, seconds_per_solve=dt / args.steps,
+               iters=inf["iters"], status=inf["status_name"], true_relres=inf["true_relres"],
+               hist_first_last=[inf["hist"][0], inf["hist"][-1]] if inf["hist"] else [],
+               workspace_bytes=ws_full,
+               save_memory=dict(r_sol=prm_save.r_sol, p_sol=prm_save.p_sol, workspace_bytes=ws_save,
+                                seconds_per_solve=dts, iters=isave["iters"], true_relres=isave["true_relres"]),
+               roofline={"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                         "frac": achieved / peak, "kernel": name, "launches": launches,
+                         "avg_launch_us": kms * 1e3 / max(launches, 1)},
+               kernel_classes=classes)
+    if not args.no_cpu_baseline:
+        import oracle as O
+        from oracle import mln as M
+        B = O.Tucker(w.b_core, w.b_factors)
+        it = args.mln_cpu_iters
+        t2 = time.perf_counter()
+        _, oi = M.mln_sgmres(w.terms, B, Psi_np, M.MLNParams(r=r, p=p, tol=1e-30, eta=w.eta, maxiter=it,
+                                                            k_trunc=w.k_trunc))
+        dto = time.perf_counter() - t2
+        out["cpu_baseline"] = dict(value=oi["iters"] / dto, unit="sGMRES iterations/s", kind="oracle",
+                                   sample=f"first {oi['iters']} MLN iterations of the same workload plus the final "
+                                          f"recovery and exact residual, {dto:.1f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +188,10 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-mln", action="store_true", help="skip the MLN-Tucker sGMRES measurement")
+    ap.add_argument("--mln-r", type=int, default=48)
+    ap.add_argument("--mln-p", type=int, default=48)
+    ap.add_argument("--mln-cpu-iters", type=int, default=20)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, launch a plain elementwise copy of this many MiB three times "
                          "(a kernel of known traffic for scaling hardware byte counters)")
@@ -245,6 +321,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
+    if not args.no_mln:
+        out["mln"] = mln_bench(tk, torch, w, op, b, args)
     if args.copy_calibration_mib > 0:
         nb = args.copy_calibration_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")

@@ -246,7 +246,9 @@ int tsgmres_mln_solve_workspace(const tk_kron_op* op, const tk_tucker* b, const 
  * the summed kernel time in milliseconds and (each optional, may be NULL) the
  * summed algorithmic flops and HBM bytes of those launches.  Flops: 2*M*N*K per
  * GEMM product, 9*N^3 per eigendecomposition with vectors, (4/3)*N^3 per
- * eigenvalues-only solve (N = launch order), 0 for the other classes.  Bytes
+ * eigenvalues-only solve (N = launch order), 2*(2*n*m^2 - (2/3)*m^3) per
+ * Householder QR of an n x m matrix (m = the launch's column capacity,
+ * counted with its thin Q), 0 for the other classes.  Bytes
  * (eigensolvers only, 0 for the other classes): per matrix, the N*N input read
  * once plus the N eigenvalues written, plus the N*N eigenvectors written when
  * they are computed, in the launch's element size. */

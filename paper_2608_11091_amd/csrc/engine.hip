@@ -1127,8 +1127,13 @@ void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>
       // rank-revealing QR of the remainder: columns left with <= 64 u of their
       // norm in the factor lie (numerically) inside the earlier blocks' span
       // and are cut; what is cut is below the rounding of the core sum itself
+      // the basis of a mode's last block is needed only when it is re-orthogonalised
+      // (blocks after the first) or projected out of later blocks
       std::vector<QrPivTask> qt;
-      for (int k : act) qt.push_back(QrPivTask{Xt[k], fac[k][i], Qi(k), Rt[k], facr[k][i]});
+      for (int k : act) {
+        const bool need_q = i > 0 || int(fac[k].size()) > 1;
+        qt.push_back(QrPivTask{Xt[k], fac[k][i], need_q ? Qi(k) : nullptr, Rt[k], facr[k][i]});
+      }
       const size_t off = pl.blob.add(qt);
       q.steps.push_back([=](hipStream_t st) { qr_piv_batched(bl->at<QrPivTask>(off), na, n, rc, kCutTol, st); });
       if (i == 0) {

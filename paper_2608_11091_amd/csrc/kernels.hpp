@@ -70,7 +70,7 @@ void mat_recap(const T* src, int ld_src, int rows_src, int cols_src, T* dst, int
 // upper triangle of the m x m factor, zero elsewhere).  n <= 512, cap <= 64.
 struct QrTask {
   const double* Y;
-  double* Q;
+  double* Q;          // or null: R only
   double* R;
   const int* m;  // optional per-task active column count (overrides m_dev)
 };
@@ -84,7 +84,7 @@ struct QrPivTask {
   const double* Y;    // n x cap, ld n
   const double* ref;  // n x cap, ld n: reference columns for the cut; null =
                       // the largest column of Y for every column (global cut)
-  double* Q;          // n x cap, ld n
+  double* Q;          // n x cap, ld n, or null: R only
   double* R;          // cap x cap, or null
   const int* m;       // active columns (device), or null = cap
   double* Rt = nullptr;     // optional: R transposed (cap x cap, Rt[c][j] = R[j][c])

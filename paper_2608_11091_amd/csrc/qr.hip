@@ -1,324 +1,258 @@
-// Householder QR of tall-skinny FP64 matrices, one workgroup per matrix.
-//
-// Thread t owns row t of the n x m matrix (n <= 512, m <= 64) in registers.
-// Step j forms the reflector of column j (a block reduction of the column
-// tail), then the row vector w = v^T A[:, j+1:] is reduced with a wave-level
-// reduce-scatter (each lane ends with one column's wave partial, 63
-// shuffles per wave) followed by an 8-way LDS sum in fixed order.  Q is then
-// formed in place by backward accumulation of the reflectors.  Everything
-// is deterministic: no atomics, fixed reduction trees.
+// Small dense factorisations of the hot path, one workgroup per matrix:
+// Householder QR (plain and column-pivoted with a rank cut) of tall-skinny
+// FP64 matrices, the Cholesky factor of a small Gram, and the row-wise
+// triangular solve that turns a Gram's Cholesky factor into a basis.
+// Everything is deterministic: no atomics, fixed reduction orders.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace tk {
 
 namespace {
 
-constexpr int QR_NT = 512;
-constexpr int QR_MC = 64;
-constexpr int QR_NW = QR_NT / kWave;
+// ---------------------------------------------------------------- Householder QR
+// Column-distributed layout: lane c of every wave owns column c (c < 64) and
+// wave w holds rows [32w, 32w + 32) of it in registers, so a block of
+// ceil(n / 32) waves covers n <= 512 rows.  Sums over rows are in-thread
+// over the 32 rows plus one pass over the waves' partials in LDS (fixed
+// order).  Every wave derives the pivot of a step from the same LDS partials,
+// and the pivot column's lane of each wave hands the reflector of that
+// wave's rows to the other lanes through a per-wave LDS slot (in-order LDS
+// within a wave, no block barrier), so a factorisation step needs two
+// barriers and a Q step one.
+constexpr int QC_RS = 32;
+constexpr int QC_MAXW = 16;
+constexpr int QC_NT = QC_MAXW * kWave;
 
-// Sums p[c] over the workgroup for every c < 64 (p computed by `term(c)`),
-// result in wv[c].  Uses red[QR_NW][64].
-template <typename F>
-__device__ __forceinline__ void column_sums(F term, double (*red)[QR_MC], double* wv) {
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  double p[32];
-  {
-    const bool up = lane & 32;
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
-      const double lo = term(i), hi = term(i + 32);
-      const double send = up ? lo : hi, keep = up ? hi : lo;
-      p[i] = keep + __shfl_xor(send, 32, 64);
-    }
-  }
-#pragma unroll
-  for (int h = 16; h >= 1; h >>= 1) {
-    const bool up = lane & h;
-#pragma unroll
-    for (int i = 0; i < h; ++i) {
-      const double lo = p[i], hi = p[i + h];
-      const double send = up ? lo : hi, keep = up ? hi : lo;
-      p[i] = keep + __shfl_xor(send, h, 64);
-    }
-  }
-  red[w][lane] = p[0];  // wave partial of column `lane`
-  __syncthreads();
-  if (threadIdx.x < QR_MC) {
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < QR_NW; ++q) s += red[q][threadIdx.x];
-    wv[threadIdx.x] = s;
-  }
-  __syncthreads();
+struct QrJob {
+  const double* Y;
+  const double* ref;
+  double* Q;
+  double* R;
+  double* Rt;
+  int* rank_out;
+  int m;
+};
+__device__ __forceinline__ QrJob job_of(const QrTask& t, int cap, const int* m_dev) {
+  QrJob j{t.Y, nullptr, t.Q, t.R, nullptr, nullptr, 0};
+  j.m = t.m ? *t.m : (m_dev ? *m_dev : cap);
+  return j;
+}
+__device__ __forceinline__ QrJob job_of(const QrPivTask& t, int cap, const int*) {
+  QrJob j{t.Y, t.ref, t.Q, t.R, t.Rt, t.rank_out, 0};
+  j.m = t.m ? *t.m : cap;
+  return j;
 }
 
-__global__ __launch_bounds__(QR_NT) void qr_kernel(const QrTask* __restrict__ tasks, int n, int cap,
-                                                   const int* __restrict__ m_dev) {
-  __shared__ double red[QR_NW][QR_MC];
-  __shared__ double wv[QR_MC];
-  __shared__ double tau_s[QR_MC];
-  __shared__ double r2[2][QR_NW];
-  const QrTask tk_ = tasks[blockIdx.x];
-  const int row = threadIdx.x;
-  const int lane = row & 63, wid = row >> 6;
-  int m = tk_.m ? *tk_.m : (m_dev ? *m_dev : cap);
-  m = min(m, cap);
-  m = min(m, n);
-
-  double a[QR_MC];
-#pragma unroll
-  for (int c = 0; c < QR_MC; ++c) a[c] = (row < n && c < m) ? tk_.Y[row + (size_t)c * n] : 0.0;
-
-  // ---------------- factorisation
-  for (int j = 0; j < m; ++j) {
-    double xj = 0.0;
-#pragma unroll
-    for (int c = 0; c < QR_MC; ++c) xj = (c == j) ? a[c] : xj;
-    // alpha = A[j][j], xnorm^2 = sum_{i>j} A[i][j]^2, one two-value block reduction
-    double va = (row == j) ? xj : 0.0;
-    double vn = (row > j) ? xj * xj : 0.0;
-    va = wave_sum(va);
-    vn = wave_sum(vn);
-    if (lane == 0) {
-      r2[0][wid] = va;
-      r2[1][wid] = vn;
-    }
-    __syncthreads();
-    double alpha = 0.0, xnorm2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < QR_NW; ++q) {
-      alpha += r2[0][q];
-      xnorm2 += r2[1][q];
-    }
-    double beta, tau, scal;
-    if (xnorm2 == 0.0) {
-      beta = alpha;
-      tau = 0.0;
-      scal = 0.0;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      tau = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
-    }
-    const double vr = (row == j) ? 1.0 : (row > j ? xj * scal : 0.0);
-    if (tau != 0.0) {
-      column_sums([&](int c) { return c > j ? vr * a[c] : 0.0; }, red, wv);
-      const double tv = tau * vr;
-#pragma unroll
-      for (int c = 0; c < QR_MC; ++c)
-        if (c > j) a[c] -= tv * wv[c];
-    } else {
-      __syncthreads();  // keep r2 reads ahead of the next step's writes
-    }
-    const double nj = (row == j) ? beta : (row > j ? vr : xj);
-#pragma unroll
-    for (int c = 0; c < QR_MC; ++c) a[c] = (c == j) ? nj : a[c];
-    if (row == 0) tau_s[j] = tau;
-  }
-  __syncthreads();
-
-  // ---------------- R (upper triangle of the leading m x m block)
-  if (tk_.R != nullptr && row < cap) {
-#pragma unroll
-    for (int c = 0; c < QR_MC; ++c)
-      if (c < cap) tk_.R[row + (size_t)c * cap] = (row < m && c < m && c >= row) ? a[c] : 0.0;
-  }
-
-  // ---------------- Q, backward accumulation in place (LAPACK org2r order)
-  for (int j = m - 1; j >= 0; --j) {
-    const double tau = tau_s[j];
-    double xj = 0.0;
-#pragma unroll
-    for (int c = 0; c < QR_MC; ++c) xj = (c == j) ? a[c] : xj;
-    const double vr = (row == j) ? 1.0 : (row > j ? xj : 0.0);
-    if (j < m - 1 && tau != 0.0) {
-      column_sums([&](int c) { return (c > j && c < m) ? vr * a[c] : 0.0; }, red, wv);
-      const double tv = tau * vr;
-#pragma unroll
-      for (int c = 0; c < QR_MC; ++c)
-        if (c > j && c < m) a[c] -= tv * wv[c];
-    }
-    const double nj = (row == j) ? 1.0 - tau : (row > j ? -tau * xj : 0.0);
-#pragma unroll
-    for (int c = 0; c < QR_MC; ++c) a[c] = (c == j) ? nj : a[c];
-  }
-  if (row < n) {
-#pragma unroll
-    for (int c = 0; c < QR_MC; ++c)
-      if (c < cap) tk_.Q[row + (size_t)c * n] = (c < m) ? a[c] : 0.0;
-  }
+// Sum of part[q][c] over the nw waves in fixed order (every wave gets the
+// same result).
+__device__ __forceinline__ double wave_partials_sum(const double (*part)[kWave], int nw, int c) {
+  double s = 0.0;
+#pragma unroll 2
+  for (int q = 0; q < nw; ++q) s += part[q][c];
+  return s;
 }
 
-// Column-pivoted Householder QR with a rank cut, for the per-factor blocks of
-// the exact norm.  Each step picks the unchosen column with the largest
-// remaining norm relative to its reference norm (the factor column before
-// projection); once that ratio is <= drop_tol every remaining column is
-// numerically inside the span already built, and the factorisation stops.
-// Outputs Q (live columns in pivot order, zeros after) and R with
-// R[j][c] = coefficient of input column c on basis column j, so that
-// Y = Q R up to the dropped remainders.  Column bookkeeping uses 64-bit masks
-// (uniform across the block), so all register indices stay static.
-__global__ __launch_bounds__(QR_NT) void qr_piv_kernel(const QrPivTask* __restrict__ tasks, int n, int cap,
-                                                       double drop_tol) {
-  __shared__ double red[QR_NW][QR_MC];
-  __shared__ double wv[QR_MC];
-  __shared__ double fref2[QR_MC];
-  __shared__ double tau_s[QR_MC];
-  __shared__ double r2[2][QR_NW];
-  __shared__ int piv_s[QR_MC];
-  __shared__ int inv_s[QR_MC];
-  __shared__ int ctl;
-  const QrPivTask tk_ = tasks[blockIdx.x];
-  const int row = threadIdx.x;
-  const int lane = row & 63, wid = row >> 6;
-  int m = tk_.m ? *tk_.m : cap;
-  m = min(m, cap);
+// Eight independent accumulation chains combined by a fixed tree.
+__device__ __forceinline__ double tree8(const double* s) {
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+// PIV = false: plain Householder QR of the leading m columns (m from the task,
+// else m_dev, else cap).  PIV = true: column pivoting by the largest remaining
+// norm relative to the column's reference norm (or to the largest input
+// column when the task has no reference) and a stop once that ratio is at or
+// below drop_tol; R[j][c] is then the coefficient of input column c on basis
+// column j.
+template <bool PIV, typename Task>
+__global__ __launch_bounds__(QC_NT) void qr_cols_kernel(const Task* __restrict__ tasks, int n, int cap,
+                                                        double drop_tol, const int* __restrict__ m_dev) {
+  __shared__ double pn1[QC_MAXW][kWave];  // per-wave sums of squares over rows >= j
+  __shared__ double rowj[kWave];          // row j of every column
+  __shared__ double pw[2][QC_MAXW][kWave];  // per-wave partials of v^T A
+  __shared__ double fref2[kWave];
+  __shared__ double tau_s[kWave];
+  __shared__ int piv_s[kWave];
+  __shared__ int step_of[kWave];
+  __shared__ double vsh[QC_MAXW][QC_RS];  // reflector on each wave's rows
+  const QrJob jb = job_of(tasks[blockIdx.x], cap, m_dev);
+  const int tid = threadIdx.x;
+  const int c = tid & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform: row tests stay scalar
+  const int nw = blockDim.x / kWave;
+  const int r0 = w * QC_RS;
+  const int m = max(0, min(jb.m, cap));
   const int kmax = min(m, n);
 
-  double a[QR_MC];
+  // unconditional loads at clamped indices (always inside the n x cap input),
+  // masked afterwards: no per-row branches whose conditions stay live
+  const int cl = min(c, cap - 1);
+  const bool colin = c < m;
+  const double* refp = jb.ref ? jb.ref : jb.Y;  // reference columns (the input itself for the global cut)
+  double a[QC_RS];
+  double sref = 0.0;  // this thread's share of the squared reference norm
 #pragma unroll
-  for (int c = 0; c < QR_MC; ++c) a[c] = (row < n && c < m) ? tk_.Y[row + (size_t)c * n] : 0.0;
-  column_sums(
-      [&](int c) {
-        const double v = (row < n && c < m) ? (tk_.ref ? tk_.ref[row + (size_t)c * n] : a[c]) : 0.0;
-        return v * v;
-      },
-      red, fref2);
-  if (tk_.ref == nullptr) {
-    // global cut: every column is measured against the largest input column
-    if (row == 0) {
-      double mx = 0.0;
-      for (int c = 0; c < m; ++c) mx = fmax(mx, fref2[c]);
-      for (int c = 0; c < m; ++c) fref2[c] = mx;
+  for (int i = 0; i < QC_RS; ++i) {
+    const int r = r0 + i;
+    const size_t at = (size_t)min(r, n - 1) + (size_t)cl * n;
+    const bool in = colin && r < n;
+    const double y = jb.Y[at];
+    a[i] = in ? y : 0.0;
+    if (PIV) {
+      const double v = in ? refp[at] : 0.0;
+      sref += v * v;
+    }
+  }
+  // the pivot column's lane stores v on this wave's rows; the other lanes of
+  // the wave read it back after a wave-scope fence
+  auto publish = [&](bool own, int t0, double scale, double diag) {
+    if (own) {
+#pragma unroll
+      for (int i = 0; i < QC_RS; ++i) vsh[w][i] = (i < t0) ? 0.0 : (i == t0 ? diag : a[i] * scale);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  // column sums of squares over rows >= j, and row j of every column (from
+  // the wave that holds it)
+  auto norm_partials = [&](int j) {
+    const int t0 = j - r0;
+    double s1[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < QC_RS; ++i) s1[i & 7] += (i >= t0) ? a[i] * a[i] : 0.0;
+    pn1[w][c] = tree8(s1);
+    if (t0 >= 0 && t0 < QC_RS) {
+      double x = 0.0;
+#pragma unroll
+      for (int i = 0; i < QC_RS; ++i) x = (i == t0) ? a[i] : x;
+      rowj[c] = x;
+    }
+  };
+  if (PIV) pw[0][w][c] = sref;
+  if (tid < kWave) step_of[tid] = -1;
+  norm_partials(0);
+  __syncthreads();
+  if (PIV) {
+    if (w == 0) {
+      double t = wave_partials_sum(pw[0], nw, c);
+      if (jb.ref == nullptr) {
+        // global cut: every column is measured against the largest input column
+        t = wave_max(t);
+      }
+      fref2[c] = t;
     }
     __syncthreads();
   }
 
-  unsigned long long unch = m >= 64 ? ~0ull : ((1ull << m) - 1ull);
+  // ---------------- factorisation
+  bool alive = colin;  // this lane's column is still unchosen
   int nlive = 0;
   for (int j = 0; j < kmax; ++j) {
-    // squared norms (rows >= j) of the unchosen columns
-    column_sums([&](int c) { return (((unch >> c) & 1ull) && row >= j) ? a[c] * a[c] : 0.0; }, red, wv);
-    if (row == 0) {
-      int best = -1;
-      double br = 0.0;
-      for (int c = 0; c < m; ++c) {
-        if (!((unch >> c) & 1ull) || !(fref2[c] > 0.0)) continue;
-        const double rel = wv[c] / fref2[c];
-        if (rel > br) {
-          br = rel;
-          best = c;
-        }
-      }
-      ctl = (best >= 0 && br > drop_tol * drop_tol) ? best : -1;
+    const double n1 = wave_partials_sum(pn1, nw, c);
+    int p = j;
+    if (PIV) {
+      double rel = (alive && fref2[c] > 0.0) ? n1 / fref2[c] : -1.0;
+      if (!(rel >= 0.0)) rel = -1.0;  // NaN as well: every lane takes the same decision
+      // the largest ratio (DPP reduction), then the lowest lane holding it
+      const double best = wave_max(rel);
+      const unsigned long long hit = __ballot(rel == best);
+      const int idx = __ffsll((long long)hit) - 1;
+      p = __builtin_amdgcn_readfirstlane(best > drop_tol * drop_tol ? idx : -1);
     }
-    __syncthreads();
-    const int p = ctl;
     if (p < 0) break;
-    unch &= ~(1ull << p);
-    double xj = 0.0;
-#pragma unroll
-    for (int c = 0; c < QR_MC; ++c) xj = (c == p) ? a[c] : xj;
-    double va = (row == j) ? xj : 0.0;
-    double vn = (row > j) ? xj * xj : 0.0;
-    va = wave_sum(va);
-    vn = wave_sum(vn);
-    if (lane == 0) {
-      r2[0][wid] = va;
-      r2[1][wid] = vn;
-    }
-    __syncthreads();
-    double alpha = 0.0, xnorm2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < QR_NW; ++q) {
-      alpha += r2[0][q];
-      xnorm2 += r2[1][q];
-    }
+    // reflector of column p on rows >= j: beta = -sign(alpha) ||x||; the
+    // column's norm over rows >= j is all that is needed besides alpha
+    const double alpha = rowj[p];
+    const double xx = rdlane(n1, p);
     double beta, tau, scal;
-    if (xnorm2 == 0.0) {
+    if (xx == alpha * alpha) {  // nothing below the diagonal (to rounding): no reflection
       beta = alpha;
       tau = 0.0;
       scal = 0.0;
     } else {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      beta = -copysign(sqrt(xx), alpha);
       tau = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    const double vr = (row == j) ? 1.0 : (row > j ? xj * scal : 0.0);
-    if (tau != 0.0) {
-      column_sums([&](int c) { return ((unch >> c) & 1ull) ? vr * a[c] : 0.0; }, red, wv);
-      const double tv = tau * vr;
-#pragma unroll
-      for (int c = 0; c < QR_MC; ++c)
-        if ((unch >> c) & 1ull) a[c] -= tv * wv[c];
-    } else {
-      __syncthreads();  // keep r2 reads ahead of the next step's writes
-    }
-    const double nj = (row == j) ? beta : (row > j ? vr : xj);
-#pragma unroll
-    for (int c = 0; c < QR_MC; ++c) a[c] = (c == p) ? nj : a[c];
-    if (row == 0) {
+    if (tid == 0) {
       tau_s[j] = tau;
       piv_s[j] = p;
     }
+    alive = alive && c != p;
+    const int t0 = j - r0;
+    const bool upd = tau != 0.0 && alive;
+    publish(c == p, t0, scal, 1.0);
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < QC_RS; ++i) s[i & 7] += vsh[w][i] * a[i];
+    pw[0][w][c] = upd ? tree8(s) : 0.0;
+    __syncthreads();
+    const double wc = wave_partials_sum(pw[0], nw, c);
+    const double tw = upd ? tau * wc : 0.0;
+#pragma unroll
+    for (int i = 0; i < QC_RS; ++i) {
+      const double v = vsh[w][i];
+      const double own = (i < t0) ? a[i] : (i == t0 ? beta : v);  // column p: beta, then the reflector
+      a[i] = (c == p) ? own : a[i] - tw * v;
+    }
     nlive = j + 1;
+    norm_partials(j + 1);
+    __syncthreads();
   }
+  if (tid < nlive) step_of[piv_s[tid]] = tid;
   __syncthreads();
 
-  // ---------------- R: row j holds the coefficients on basis column j of every
-  // input column chosen at step >= j or never chosen
-  if (tk_.R != nullptr && row < cap) {
-    unsigned long long ok = unch;
-    for (int jj = row; jj < nlive; ++jj) ok |= 1ull << piv_s[jj];
+  // ---------------- R (and its transpose): row jj of every column
+  if (jb.R != nullptr || jb.Rt != nullptr) {
 #pragma unroll
-    for (int c = 0; c < QR_MC; ++c)
-      if (c < cap) tk_.R[row + (size_t)c * cap] = (row < nlive && c < m && ((ok >> c) & 1ull)) ? a[c] : 0.0;
+    for (int i = 0; i < QC_RS; ++i) {
+      const int row = r0 + i;
+      if (row < cap && c < cap) {
+        const int sc = step_of[c];
+        const bool ok = PIV ? (row < nlive && c < m && (sc < 0 || sc >= row)) : (row < nlive && c < m && c >= row);
+        const double val = ok ? a[i] : 0.0;
+        if (jb.R) jb.R[row + (size_t)c * cap] = val;
+        if (jb.Rt) jb.Rt[c + (size_t)row * cap] = val;
+      }
+    }
   }
-  if (tk_.Rt != nullptr && row < cap) {
-    unsigned long long ok = unch;
-    for (int jj = row; jj < nlive; ++jj) ok |= 1ull << piv_s[jj];
-#pragma unroll
-    for (int c = 0; c < QR_MC; ++c)
-      if (c < cap) tk_.Rt[c + (size_t)row * cap] = (row < nlive && c < m && ((ok >> c) & 1ull)) ? a[c] : 0.0;
-  }
-  if (tk_.rank_out != nullptr && row == 0) *tk_.rank_out = nlive;
+  if (jb.rank_out != nullptr && tid == 0) *jb.rank_out = nlive;
 
-  // ---------------- Q, backward accumulation in place (reflector j stored in column piv[j])
-  unsigned long long later = 0ull;
+  // ---------------- Q by backward accumulation; basis column j sits in column piv[j]
+  if (jb.Q == nullptr) return;  // R only (uniform over the block)
+  bool later = false;  // this lane's column already holds a finished basis column
   for (int j = nlive - 1; j >= 0; --j) {
     const int p = piv_s[j];
     const double tau = tau_s[j];
-    double xj = 0.0;
+    const int t0 = j - r0;
+    const int b = j & 1;
+    const bool upd = later && tau != 0.0;
+    publish(c == p, t0, 1.0, 1.0);
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int c = 0; c < QR_MC; ++c) xj = (c == p) ? a[c] : xj;
-    const double vr = (row == j) ? 1.0 : (row > j ? xj : 0.0);
-    if (later != 0ull && tau != 0.0) {
-      column_sums([&](int c) { return ((later >> c) & 1ull) ? vr * a[c] : 0.0; }, red, wv);
-      const double tv = tau * vr;
+    for (int i = 0; i < QC_RS; ++i) s[i & 7] += vsh[w][i] * a[i];
+    pw[b][w][c] = upd ? tree8(s) : 0.0;
+    __syncthreads();
+    const double wc = wave_partials_sum(pw[b], nw, c);
+    const double tw = upd ? tau * wc : 0.0;
 #pragma unroll
-      for (int c = 0; c < QR_MC; ++c)
-        if ((later >> c) & 1ull) a[c] -= tv * wv[c];
+    for (int i = 0; i < QC_RS; ++i) {
+      const double v = vsh[w][i];
+      const double own = (i < t0) ? 0.0 : (i == t0 ? 1.0 - tau : -tau * v);
+      a[i] = (c == p) ? own : a[i] - tw * v;
     }
-    const double nj = (row == j) ? 1.0 - tau : (row > j ? -tau * xj : 0.0);
-#pragma unroll
-    for (int c = 0; c < QR_MC; ++c) a[c] = (c == p) ? nj : a[c];
-    later |= 1ull << p;
+    later = later || c == p;
   }
-  // basis column j sits in register column piv[j]: write it through the
-  // inverse permutation, then zero the columns beyond the rank
-  if (row < QR_MC) inv_s[row] = -1;
-  __syncthreads();
-  if (row < nlive) inv_s[piv_s[row]] = row;
-  __syncthreads();
-  if (row < n) {
+  const int jj = step_of[c];
 #pragma unroll
-    for (int c = 0; c < QR_MC; ++c) {
-      const int j = inv_s[c];
-      if (j >= 0) tk_.Q[row + (size_t)j * n] = a[c];
+  for (int i = 0; i < QC_RS; ++i) {
+    const int row = r0 + i;
+    if (row < n) {
+      if (jj >= 0) jb.Q[row + (size_t)jj * n] = a[i];
+      if (c >= nlive && c < cap) jb.Q[row + (size_t)c * n] = 0.0;
     }
-    for (int j = nlive; j < cap; ++j) tk_.Q[row + (size_t)j * n] = 0.0;
   }
 }
 
@@ -432,21 +366,33 @@ void trsm_rows(const TrsmTask* tasks_d, int ntasks, int n, int cap, const int* m
   TK_LAUNCH_CHECK();
 }
 
+// Algorithmic flops of a launch at full column count m = min(cap, n): the
+// Householder factorisation 2 n m^2 - (2/3) m^3, and as much again for the
+// explicit thin Q.
+static double qr_flops(int ntasks, int n, int cap, bool with_q) {
+  const double m = std::min(cap, n), nn = n;
+  const double f = 2.0 * nn * m * m - 2.0 / 3.0 * m * m * m;
+  return ntasks * f * (with_q ? 2.0 : 1.0);
+}
+
 void qr_batched(const QrTask* tasks_d, int ntasks, int n, int cap, const int* m_dev, hipStream_t st) {
   if (ntasks <= 0) return;
-  TK_CHECK(n <= QR_NT, kErrUnsupported, "Householder QR: more than 512 rows");
-  TK_CHECK(cap <= QR_MC, kErrUnsupported, "Householder QR: more than 64 columns");
-  timer_begin(kKcQr, st);
-  hipLaunchKernelGGL(qr_kernel, dim3(ntasks), dim3(QR_NT), 0, st, tasks_d, n, cap, m_dev);
+  TK_CHECK(n >= 1 && n <= QC_MAXW * QC_RS, kErrUnsupported, "Householder QR: more than 512 rows");
+  TK_CHECK(cap <= kWave, kErrUnsupported, "Householder QR: more than 64 columns");
+  timer_begin(kKcQr, st, qr_flops(ntasks, n, cap, true));
+  hipLaunchKernelGGL((qr_cols_kernel<false, QrTask>), dim3(ntasks), dim3(kWave * ceil_div(n, QC_RS)), 0, st,
+                     tasks_d, n, cap, 0.0, m_dev);
   TK_LAUNCH_CHECK();
   timer_end(kKcQr, st);
 }
 
 void qr_piv_batched(const QrPivTask* tasks_d, int ntasks, int n, int cap, double drop_tol, hipStream_t st) {
   if (ntasks <= 0) return;
-  TK_CHECK(n <= QR_NT && cap <= QR_MC, kErrUnsupported, "pivoted QR: more than 512 rows or 64 columns");
-  timer_begin(kKcQr, st);
-  hipLaunchKernelGGL(qr_piv_kernel, dim3(ntasks), dim3(QR_NT), 0, st, tasks_d, n, cap, drop_tol);
+  TK_CHECK(n >= 1 && n <= QC_MAXW * QC_RS && cap <= kWave, kErrUnsupported,
+           "pivoted QR: more than 512 rows or 64 columns");
+  timer_begin(kKcQr, st, qr_flops(ntasks, n, cap, true));
+  hipLaunchKernelGGL((qr_cols_kernel<true, QrPivTask>), dim3(ntasks), dim3(kWave * ceil_div(n, QC_RS)), 0, st,
+                     tasks_d, n, cap, drop_tol, nullptr);
   TK_LAUNCH_CHECK();
   timer_end(kKcQr, st);
 }
