@@ -58,11 +58,11 @@ NOTE = {
 # for a plain copy of known size), valid only for the kernel sources it was
 # measured on: reported as null once any of them changes.
 TRAFFIC = {
-    "jacobi": dict(bytes_per_launch=47981.0,
+    "jacobi": dict(bytes_per_launch=48153.0,
                    sources={"paper_2608_11091_amd/csrc/eig.hip":
-                            "2102867efc5668069c67d4a71075f6b8e051799e9437b6ff75d394056cdab9c5",
+                            "ed3dda42d480fa733f8f2c2b4fd0c8cfcaa07a08b9e2074312b6510f2b47fe84",
                             "paper_2608_11091_amd/csrc/common.hpp":
-                            "8d6d9d994a251521ce45a3795fcac58bda48148c1b1ac227f5fcc0afc2e6fa9b"},
+                            "4c69bc4b5fa7702b065187f8a03356bf28eea6a4eb39b7ef47949b76efcf3b1c"},
                    profile="profiles/jacobi_vec_traffic_deblur3d_n512.md"),
 }
 
@@ -145,7 +145,7 @@ def mln_bench(tk, torch, w, op, b, args):
     dts = time.perf_counter() - t1
     # the MLN path runs in FP64 throughout: FP64 matrix-core / vector peaks
     bound, peak = {"gemm": ("mfma", PEAK["fp64"])}.get(dom, (BOUND[dom][0], 78.6))
-    name = {"qr": "qr_piv_kernel / qr_kernel: pivoted and Householder QRs of the recovery and exact norms"}.get(
+    name = {"qr": "qr_cols_kernel: pivoted and plain Householder QRs of the recovery and exact norms"}.get(
         dom, KERNEL_NAME[dom])
     achieved = (kflops / (kms * 1e-3)) / 1e12 if kms > 0 else 0.0
     inf = infos[-1]
@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--mln-r", type=int, default=48)
     ap.add_argument("--mln-p", type=int, default=48)
     ap.add_argument("--mln-cpu-iters", type=int, default=20)
+    ap.add_argument("--mln-only", action="store_true",
+                    help="measure only MLN-Tucker sGMRES (for profiling); prints {\"mln\": ...}")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, launch a plain elementwise copy of this many MiB three times "
                          "(a kernel of known traffic for scaling hardware byte counters)")
@@ -210,6 +212,9 @@ def main():
     w = make_config(args.config, n=args.n, cap=args.cap, tol=args.tol)
     op = tk.KronOp.from_terms(w.terms)
     b = tk.Tucker.from_numpy(w.b_core, w.b_factors)
+    if args.mln_only:
+        print(json.dumps({"mln": mln_bench(tk, torch, w, op, b, args)}))
+        return
     S = [_cm(torch, s) for s in w.S]
     Om = [_cm(torch, o) for o in w.Omega]
     mk = lambda form: tk.SolveParams(form=form, tol=args.tol, eta=w.eta, maxiter=w.maxiter,
