@@ -23,6 +23,12 @@ Parity status (see the pins in ``tests/test_oracle_*.py``):
     Khatri-Rao identity, Nystrom exactness below the target rank, the
     memory-efficient truncation identity, reduction to vector sketched GMRES
     when the recovery is exact, a tiny Poisson solve).
+  * exponential-sum preconditioner and flexible cycle (``oracle.precond``):
+    pinned (closed-form DST-I eigenpairs of the 1D Laplacian, the
+    exponential sum's relative error against 1/x over the spectrum, the
+    spectral application against the dense sum of matrix exponentials and
+    against the dense inverse, and the flexible cycle against the dense
+    solution).
   * effective-rank heuristic's choice of sketch size beyond the exactness
     test: parity unpinned (a heuristic; only its invariance and monotone
     behaviour are tested).
@@ -33,12 +39,12 @@ from .tucker import (Tucker, to_dense, ttm, multi_ttm, unfold, apply_op, transpo
 from .roundsum import RoundParams, roundsum, effective_sketch_size, st_hosvd
 from .sgmres import SGMRESParams, sgmres_cycle, solve, sketched_lstsq
 from .adjoint import adjoint_gradients, loss_and_cotangent
-from . import mln
+from . import mln, precond
 
 __all__ = [
     "Tucker", "to_dense", "ttm", "multi_ttm", "unfold", "apply_op", "transpose_terms",
     "dense_operator", "sketch_krp", "sketch_kron", "inner", "exact_norm", "block_dense",
     "scale", "RoundParams", "roundsum", "effective_sketch_size", "st_hosvd",
     "SGMRESParams", "sgmres_cycle", "solve", "sketched_lstsq", "adjoint_gradients",
-    "loss_and_cotangent", "mln",
+    "loss_and_cotangent", "mln", "precond",
 ]

@@ -86,8 +86,13 @@ class _Replay:
 
 
 def sgmres_cycle(terms, B: Tucker, S, Omega, prm: SGMRESParams, tol: Optional[float] = None,
-                 transpose: bool = False, log: Optional[list] = None, replay=None):
-    """One cycle of Alg. 2 on ``L(X) = B``; returns (X, info)."""
+                 transpose: bool = False, log: Optional[list] = None, replay=None, precond=None):
+    """One cycle of Alg. 2 on ``L(X) = B``; returns (X, info).
+
+    ``precond`` (optional) makes the cycle flexible (Sec. 3.4): it maps
+    (V_k, round_fn) to the preconditioned tensor Z_k = T(M(V_k)), where
+    round_fn is the cycle's RoundSum; the operator is applied to Z_k and the
+    solution is RoundSum(sum_i y_i Z_i)."""
     tol = prm.tol if tol is None else tol
     eps = prm.eps_trunc if prm.eps_trunc is not None else max(1e-2 * tol, prm.eps_min)
     rp = RoundParams(eps=eps, cap=prm.cap, p=prm.p)
@@ -101,8 +106,13 @@ def sgmres_cycle(terms, B: Tucker, S, Omega, prm: SGMRESParams, tol: Optional[fl
     status = NOT_CONVERGED
     y = np.zeros(0)
     k = 0
+    Z: List[Tucker] = []
     for k in range(1, prm.maxiter + 1):
-        LV = apply_op(terms, V[-1], transpose=transpose)
+        Zk = V[-1]
+        if precond is not None:
+            Zk = precond(V[-1], lambda blocks: roundsum(blocks, Omega, rep.next(rp))[0])
+            Z.append(Zk)
+        LV = apply_op(terms, Zk, transpose=transpose)
         W, i1 = roundsum(LV, Omega, rep.next(rp))
         cols.append(sketch_krp([(1.0, W)], S))
         window = V[max(0, k - prm.k_trunc):k]
@@ -124,7 +134,8 @@ def sgmres_cycle(terms, B: Tucker, S, Omega, prm: SGMRESParams, tol: Optional[fl
         if rel < prm.eta * tol:
             status = OK
             break
-    X, i3 = roundsum([(float(y[i]), V[i]) for i in range(len(y))], Omega, rep.next(rp))
+    basis = Z if precond is not None else V
+    X, i3 = roundsum([(float(y[i]), basis[i]) for i in range(len(y))], Omega, rep.next(rp))
     if log is not None:
         log.append(dict(final=True, s=i3["s"], r=i3["ranks"]))
     return X, dict(status=status, iters=k, hist=hist, beta=beta, beta_s=beta_s)
@@ -136,7 +147,7 @@ def _residual_blocks(terms, B: Tucker, X: Tucker, transpose=False):
 
 
 def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False,
-          x0: Optional[Tucker] = None, log: Optional[list] = None):
+          x0: Optional[Tucker] = None, log: Optional[list] = None, precond=None):
     """Restarted Tucker sGMRES with FP64 iterative refinement."""
     t0 = time.perf_counter()
     eps_out = prm.eps_outer if prm.eps_outer is not None else 1e-2 * prm.tol
@@ -161,7 +172,7 @@ def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False
         cycles += 1
         tol_in = min(0.5, max(prm.tol * bnorm / rnorm, prm.tol_inner_floor))
         d, info = sgmres_cycle(terms, r, S, Omega, prm, tol=tol_in, transpose=transpose,
-                               log=log, replay=rep)
+                               log=log, replay=rep, precond=precond)
         iters += info["iters"]
         if x is None:
             x = d
