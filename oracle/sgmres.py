@@ -110,7 +110,10 @@ def sgmres_cycle(terms, B: Tucker, S, Omega, prm: SGMRESParams, tol: Optional[fl
     for k in range(1, prm.maxiter + 1):
         Zk = V[-1]
         if precond is not None:
-            Zk = precond(V[-1], lambda blocks: roundsum(blocks, Omega, rep.next(rp))[0])
+            # the 2q + 1 terms of the preconditioner are rounded at the full sketch
+            # width cap + p (their concatenated factors exceed the effective-rank rule)
+            rpz = dataclasses.replace(rp, force_s=prm.cap + prm.p)
+            Zk = precond(V[-1], lambda blocks: roundsum(blocks, Omega, rep.next(rpz))[0])
             Z.append(Zk)
         LV = apply_op(terms, Zk, transpose=transpose)
         W, i1 = roundsum(LV, Omega, rep.next(rp))
