@@ -175,6 +175,45 @@ def mln_bench(tk, torch, w, op, b, args):
     return out
 
 
+def precond_bench(tk, torch, args):
+    """Preconditioned flexible RHOSVD-Tucker sGMRES (Sec. 3.4) on the Laplacian
+    experiment's problem at n = 512: 3D Poisson, right-hand side
+    ones/||ones|| x e_1 x e_1, k_trunc = 1, p = 5, exponential sum with 2q + 1
+    terms; both forms, time to 1e-8 and iterations/s."""
+    import numpy as np
+
+    from workloads import draw_sketches, laplacian_1d
+    n, cap, p, q, maxiter = args.precond_n, args.precond_cap, 5, args.precond_q, 40
+    L = laplacian_1d(n)
+    terms = [(1.0, [L if j == k else None for j in range(3)]) for k in range(3)]
+    e1 = np.zeros((n, 1))
+    e1[0] = 1.0
+    op = tk.KronOp.from_terms(terms)
+    b = tk.Tucker.from_numpy(np.ones((1, 1, 1)), [np.ones((n, 1)) / np.sqrt(n), e1, e1], rcap=(cap,) * 3)
+    S, Om = draw_sketches([n] * 3, 2 * maxiter, cap, p, seed=0)
+    S = [_cm(torch, a) for a in S]
+    Om = [_cm(torch, a) for a in Om]
+    pre = tk.laplacian_precond((n,) * 3)
+    out = dict(workload=f"poisson3d_n{n}, rhs ones/||ones|| x e1 x e1 (Laplacian experiment at n = {n})",
+               q=q, terms=2 * q + 1, rank_cap=cap, oversample=p, k_trunc=1, sketch_size=2 * maxiter, maxiter=maxiter)
+    for form, name in ((1, "fp32_form"), (0, "fp64_form")):
+        prm = tk.SolveParams(form=form, tol=args.tol, eta=0.4, maxiter=maxiter, k_trunc=1, rank_cap=cap, oversample=p,
+                             max_restarts=8, precond_q=q, precond=pre)
+        ws = torch.empty(tk.solve_workspace_bytes(op, b, 2 * maxiter, prm), dtype=torch.uint8, device="cuda")
+        tk.solve(op, b, S, Om, prm, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [tk.solve(op, b, S, Om, prm, workspace=ws)[1] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        inf = infos[-1]
+        out[name] = dict(iters=inf["iters"], cycles=inf["cycles"], status=inf["status_name"],
+                         true_relres=inf["true_relres"], true_hist=inf["true_hist"],
+                         seconds_per_solve=dt / args.steps,
+                         iters_per_s=sum(i["iters"] for i in infos) / dt, workspace_bytes=ws.numel())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +231,10 @@ def main():
     ap.add_argument("--mln-r", type=int, default=48)
     ap.add_argument("--mln-p", type=int, default=48)
     ap.add_argument("--mln-cpu-iters", type=int, default=20)
+    ap.add_argument("--no-precond", action="store_true", help="skip the preconditioned Laplacian measurement")
+    ap.add_argument("--precond-n", type=int, default=512)
+    ap.add_argument("--precond-cap", type=int, default=32)
+    ap.add_argument("--precond-q", type=int, default=49)
     ap.add_argument("--mln-only", action="store_true",
                     help="measure only MLN-Tucker sGMRES (for profiling); prints {\"mln\": ...}")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -328,6 +371,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
     if not args.no_mln:
         out["mln"] = mln_bench(tk, torch, w, op, b, args)
+    if not args.no_precond:
+        out["precond"] = precond_bench(tk, torch, args)
     if args.copy_calibration_mib > 0:
         nb = args.copy_calibration_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")

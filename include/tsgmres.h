@@ -118,6 +118,16 @@ typedef struct {
   double eps_min;           /* <= 0: 1e-13 (FP64) / 1e-6 (FP32) */
   double tol_inner_floor;   /* <= 0: 1e-13 (FP64) / 1e-5 (FP32) */
   const tk_tucker* x0;      /* optional initial guess (NULL = zero) */
+  /* Optional separable spectral preconditioner (Sec. 3.4), which makes every
+   * cycle flexible: Z_k = RoundSum(M(V_k)) at the full sketch width, L is
+   * applied to Z_k and the cycle's solution is RoundSum(sum_i y_i Z_i), with
+   *   M = sum_{h=-q..q} c_h (x)_k V_k exp(-t_h Lambda_k) V_k^T,
+   *   t_h = exp(h eta), c_h = eta t_h, eta = pi / sqrt(q)
+   * (for V_k, Lambda_k the eigenpairs of a 1D Laplacian, an exponential-sum
+   * approximation of the inverse of the d-dimensional Laplacian). */
+  int32_t precond_q;                   /* 0: none; >= 1: 2q + 1 terms */
+  const double* const* precond_V;      /* host array of d device pointers: orthogonal V_k, n_k x n_k column-major */
+  const double* const* precond_lambda; /* host array of d device pointers: eigenvalues lambda_k, length n_k */
 } tk_sgmres_params;
 
 /* Solver report (host memory owned by the caller). */

@@ -50,10 +50,16 @@ def expsum(q: int) -> Tuple[np.ndarray, np.ndarray]:
 
 
 def expsum_blocks(X: Tucker, eig: Sequence[Tuple[np.ndarray, np.ndarray]], q: int):
-    """The 2q + 1 terms of M(X) in the spectral basis: [(c_h, G x_k (exp(-t_h Lambda_k) V_k^T U_k))]."""
+    """The 2q + 1 terms of M(X) in the spectral basis,
+    c_h G x_k (exp(-t_h Lambda_k) V_k^T U_k), each written with row scalings
+    exp(-t_h (lambda - lambda_min,k)) (largest entry 1) and the coefficient
+    c_h exp(-t_h sum_k lambda_min,k): the same tensor, with block coefficients
+    that bound the blocks' size (RoundSum weighs blocks by |coef| ||core||)."""
     t, c = expsum(q)
     Ut = [V.T @ U for (V, _), U in zip(eig, X.U)]
-    return [(float(ch), Tucker(X.core, [np.exp(-th * lam)[:, None] * u for (_, lam), u in zip(eig, Ut)]))
+    lmin = [float(np.min(lam)) for _, lam in eig]
+    return [(float(ch * np.exp(-th * sum(lmin))),
+             Tucker(X.core, [np.exp(-th * (lam - lm))[:, None] * u for (_, lam), lm, u in zip(eig, lmin, Ut)]))
             for th, ch in zip(t, c)]
 
 

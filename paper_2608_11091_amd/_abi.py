@@ -50,7 +50,8 @@ class TkSgmresParams(C.Structure):
     _fields_ = [("form", C.c_int32), ("tol", C.c_double), ("eta", C.c_double), ("maxiter", C.c_int32),
                 ("max_restarts", C.c_int32), ("k_trunc", C.c_int32), ("rank_cap", C.c_int32),
                 ("oversample", C.c_int32), ("s", C.c_int64), ("eps_trunc", C.c_double), ("eps_min", C.c_double),
-                ("tol_inner_floor", C.c_double), ("x0", C.POINTER(TkTucker))]
+                ("tol_inner_floor", C.c_double), ("x0", C.POINTER(TkTucker)), ("precond_q", C.c_int32),
+                ("precond_V", C.POINTER(C.c_void_p)), ("precond_lambda", C.POINTER(C.c_void_p))]
 
 
 class TkMlnParams(C.Structure):

@@ -29,7 +29,8 @@ from ._abi import (TK_MAX_D, TkBlockSum, TkKronOp, TkMlnParams, TkRoundParams, T
 
 __all__ = ["Tucker", "KronOp", "SolveParams", "apply_op", "sketch", "rhosvd", "norm", "solve", "backward",
            "TuckerSGMRESLoss", "storage_floats", "kernel_timer", "kernel_timer_read", "solve_workspace_bytes",
-           "MlnParams", "mln_sketch", "mln_recover", "mln_solve", "mln_solve_workspace_bytes"]
+           "MlnParams", "mln_sketch", "mln_recover", "mln_solve", "mln_solve_workspace_bytes",
+           "laplacian_precond"]
 
 
 def _stream():
@@ -246,17 +247,45 @@ class SolveParams:
     eps_trunc: float = -1.0
     eps_min: float = -1.0
     tol_inner_floor: float = -1.0
+    # exponential-sum preconditioner (Sec. 3.4): q and the per-mode eigenpairs
+    # (lists of device tensors: V_k as (n_k, n_k) holding the column-major
+    # matrix, lambda_k of length n_k), e.g. from ``laplacian_precond``
+    precond_q: int = 0
+    precond: Optional[Tuple[list, list]] = None
 
     def struct(self, s: int, x0: Optional[Tucker] = None):
         p = TkSgmresParams()
         p.form, p.tol, p.eta, p.maxiter, p.max_restarts = self.form, self.tol, self.eta, self.maxiter, self.max_restarts
         p.k_trunc, p.rank_cap, p.oversample, p.s = self.k_trunc, self.rank_cap, self.oversample, s
         p.eps_trunc, p.eps_min, p.tol_inner_floor = self.eps_trunc, self.eps_min, self.tol_inner_floor
-        keep = None
+        keep = []
         if x0 is not None:
-            keep = x0.struct()
-            p.x0 = C.pointer(keep)
+            xs = x0.struct()
+            keep.append(xs)
+            p.x0 = C.pointer(xs)
+        p.precond_q = int(self.precond_q)
+        if self.precond_q > 0:
+            if self.precond is None:
+                raise ValueError("precond_q > 0 needs the eigenpairs in `precond`")
+            Vs, lams = self.precond
+            va, la = _ptr_array(Vs), _ptr_array(lams)
+            keep += [va, la]
+            p.precond_V = va
+            p.precond_lambda = la
         return p, keep
+
+
+def laplacian_precond(n: Sequence[int], device="cuda"):
+    """Eigenpairs of the 1D Laplacian (n+1)^2 tridiag(-1, 2, -1) per mode (the
+    DST-I basis, closed form) as device tensors, for ``SolveParams.precond``."""
+    Vs, lams = [], []
+    for nk in n:
+        i = np.arange(1, nk + 1)
+        V = np.sqrt(2.0 / (nk + 1)) * np.sin(np.outer(i, i) * np.pi / (nk + 1))
+        lam = 4.0 * (nk + 1) ** 2 * np.sin(i * np.pi / (2 * (nk + 1))) ** 2
+        Vs.append(torch.from_numpy(np.ascontiguousarray(V.T)).to(device))
+        lams.append(torch.from_numpy(lam).to(device))
+    return Vs, lams
 
 
 def _info(hist_cap: int):

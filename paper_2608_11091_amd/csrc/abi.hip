@@ -355,6 +355,20 @@ void check_params(const tk_sgmres_params* prm) {
   TK_CHECK(prm->rank_cap >= 1 && prm->oversample >= 0 && prm->rank_cap + prm->oversample <= 64, kErrUnsupported,
            "rank_cap + oversample must be in [1, 64]");
   TK_CHECK(prm->s >= prm->maxiter && prm->s <= 256, kErrUnsupported, "sketch size must be in [maxiter, 256]");
+  TK_CHECK(prm->precond_q >= 0 && prm->precond_q <= 400, kErrInvalidArg, "precond_q must be in [0, 400]");
+  TK_CHECK(prm->precond_q == 0 || (prm->precond_V != nullptr && prm->precond_lambda != nullptr), kErrInvalidArg,
+           "preconditioner eigenpairs missing");
+}
+
+PrecondT<double> precond_of(const tk_sgmres_params* prm, int d) {
+  PrecondT<double> pc;
+  pc.q = prm->precond_q;
+  if (pc.q > 0)
+    for (int k = 0; k < d; ++k) {
+      pc.V[k] = prm->precond_V[k];
+      pc.lam[k] = prm->precond_lambda[k];
+    }
+  return pc;
 }
 
 OpDev<double> op_dev(const tk_kron_op* op) {
@@ -416,7 +430,8 @@ int do_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* p
     Sk[k] = S[k];
     Ok[k] = omega[k];
   }
-  auto solver = make_solver(ar, sh, op_dev(op), bi, solve_cfg(prm), Sk, Ok, prm->x0 ? &x0i : nullptr, st);
+  auto solver = make_solver(ar, sh, op_dev(op), bi, solve_cfg(prm), Sk, Ok, prm->x0 ? &x0i : nullptr, st,
+                            precond_of(prm, d));
   if (ar.measuring()) return 0;
   TK_CHECK(x != nullptr, kErrInvalidArg, "x is NULL");
   imp.run(st);
@@ -473,7 +488,7 @@ int do_backward(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xb
   SolveCfg scfg = solve_cfg(prm);
   scfg.transpose = true;
   OpDev<double> od = op_dev(op);
-  auto solver = make_solver(ar, sh, od, xbr, scfg, Sk, Ok, nullptr, st);
+  auto solver = make_solver(ar, sh, od, xbr, scfg, Sk, Ok, nullptr, st, precond_of(prm, d));
   // gradient contractions, planned for both solution slots of the solver
   double* dal = ar.alloc<double>(op->nterms);
   Seq grad[2];

@@ -4,6 +4,7 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 
 namespace tk {
@@ -1271,6 +1272,81 @@ void plan_gemm_batched(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int 
   emit_gemm(q, pl, std::move(g));
 }
 
+// ====================================================================== preconditioner
+template <typename T>
+void plan_precond(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, const TT<T>& x, const TT<T>& z,
+                  const RoundCfg& rcfg, const std::array<const T*, kMaxD>& omega) {
+  const int d = sh.d, rc = sh.rc, qn = pc.q, nh = 2 * qn + 1;
+  TK_CHECK(qn >= 1, kErrInvalidArg, "preconditioner: q must be >= 1");
+  Arena& ar = pl.ar;
+  Blob* bl = &pl.blob;
+  // spectral factors V_k^T U_k, one GEMM launch per group of equal mode size
+  std::array<T*, kMaxD> Ut{};
+  for (int k = 0; k < d; ++k) Ut[k] = ar.alloc<T>(size_t(sh.n[k]) * rc);
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    std::vector<const T*> a, b;
+    std::vector<T*> c;
+    for (int k : modes) {
+      a.push_back(pc.V[k]);
+      b.push_back(x.U[k]);
+      c.push_back(Ut[k]);
+    }
+    plan_gemm_batched<T>(q, pl, true, false, n, rc, n, a, n, b, n, c, n, 1.0);
+  }
+  // the 2q + 1 terms: row scalings exp(-t_h (lambda - lambda_min)) of every
+  // spectral factor (largest entry 1) and device coefficients
+  // eta t_h exp(-t_h sum_k lambda_min,k), so that a block's coefficient bounds
+  // its size (RoundSum weighs blocks by |coefficient| ||core||)
+  const double eta = 3.14159265358979323846 / std::sqrt(double(qn));
+  double* lmin = ar.alloc<double>(kMaxD);
+  double* coef = ar.alloc<double>(nh);
+  {
+    std::array<const T*, kMaxD> lam = pc.lam;
+    std::array<int, kMaxD> nn{};
+    for (int k = 0; k < d; ++k) nn[k] = sh.n[k];
+    q.steps.push_back([=](hipStream_t st) { expsum_shift<T>(lam.data(), nn.data(), d, qn, eta, lmin, coef, st); });
+  }
+  std::vector<std::array<const T*, kMaxD>> fac(nh);
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    std::vector<ExpScaleTask<T>> tasks;
+    for (int h = 0; h < nh; ++h) {
+      const double t = std::exp((h - qn) * eta);
+      for (int k : modes) {
+        T* o = ar.alloc<T>(size_t(n) * rc);
+        tasks.push_back(ExpScaleTask<T>{Ut[k], pc.lam[k], lmin + k, o, t});
+        fac[h][k] = o;
+      }
+    }
+    const size_t off = pl.blob.add(tasks);
+    const int nt = int(tasks.size());
+    q.steps.push_back([=](hipStream_t st) { exp_scale_rows<T>(bl->at<ExpScaleTask<T>>(off), nt, n, rc, st); });
+  }
+  Blocks<T> terms;
+  for (int h = 0; h < nh; ++h) terms.add(x.core, fac[h], x.rank, coef + h, 1.0);
+  // rounding in the spectral basis at the full sketch width; the core goes
+  // straight into z, the factors into temporaries that are mapped back
+  RoundCfg cfg = rcfg;
+  cfg.force_s = sh.sc();
+  TT<T> zt;
+  zt.core = z.core;
+  zt.rank = z.rank;
+  for (int k = 0; k < d; ++k) zt.U[k] = ar.alloc<T>(size_t(sh.n[k]) * rc);
+  plan_roundsum<T>(q, pl, sh, terms, cfg, omega, zt, nullptr);
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    std::vector<const T*> a, b;
+    std::vector<T*> c;
+    for (int k : modes) {
+      a.push_back(pc.V[k]);
+      b.push_back(zt.U[k]);
+      c.push_back(z.U[k]);
+    }
+    plan_gemm_batched<T>(q, pl, false, false, n, rc, n, a, n, b, n, c, n, 1.0);
+  }
+}
+
 #define TK_INST(T)                                                                                             \
   template void plan_ttm<T>(Seq&, Planner&, int, const int*, int, int, const T*, const T*, int, bool, T*);     \
   template void plan_unfold_gram<T>(Seq&, Planner&, int, const int*, int, const T*, const T*, T*, int, double); \
@@ -1290,7 +1366,9 @@ void plan_gemm_batched(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int 
                                   const std::array<const T*, kMaxD>&, int, const std::array<T*, kMaxD>&,     \
                                   const int*);                                                                 \
   template void plan_core_projection<T>(Seq&, Planner&, const Shape&, const Blocks<T>&, const double*,        \
-                                        const std::array<const T*, kMaxD>&, int, T*, const int*);
+                                        const std::array<const T*, kMaxD>&, int, T*, const int*);         \
+  template void plan_precond<T>(Seq&, Planner&, const Shape&, const PrecondT<T>&, const TT<T>&, const TT<T>&,  \
+                                const RoundCfg&, const std::array<const T*, kMaxD>&);
 TK_INST(double)
 TK_INST(float)
 #undef TK_INST

@@ -227,6 +227,22 @@ MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op
                              const MlnCfg& cfg, const std::array<const double*, kMaxD>& Psi, hipStream_t st);
 void mln_solver_run(MlnSolver& s, TT<double>& x_out, MlnInfo& info, hipStream_t st);
 
+// Separable spectral preconditioner (Sec. 3.4): per mode an orthogonal V_k
+// (n_k x n_k, column-major) and eigenvalues lambda_k of the 1D operator;
+// M = sum_{h=-q..q} c_h (x)_k V_k exp(-t_h Lambda_k) V_k^T with t_h = exp(h eta),
+// c_h = eta t_h, eta = pi / sqrt(q).  q = 0: no preconditioner.
+template <typename T>
+struct PrecondT {
+  int q = 0;
+  std::array<const T*, kMaxD> V{};
+  std::array<const T*, kMaxD> lam{};
+};
+// z = RoundSum of the 2q + 1 terms of M(x) in the spectral basis (full sketch
+// width), factors mapped back by V_k.
+template <typename T>
+void plan_precond(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, const TT<T>& x, const TT<T>& z,
+                  const RoundCfg& rcfg, const std::array<const T*, kMaxD>& omega);
+
 // ------------------------------------------------------------------ solver
 struct SolveCfg {
   int form = 0;  // 0 FP64, 1 FP32
@@ -253,7 +269,7 @@ using SolverPtr = std::unique_ptr<Solver, SolverDel>;
 SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const TT<double>& b,
                                     const SolveCfg& cfg, const std::array<const double*, kMaxD>& S,
                                     const std::array<const double*, kMaxD>& omega, const TT<double>* x0,
-                                    hipStream_t st);
+                                    hipStream_t st, const PrecondT<double>& precond = PrecondT<double>{});
 void solver_run(Solver& s, TT<double>& x_out, SolveInfo& info, hipStream_t st);
 TT<double> solver_solution(Solver& s);
 TT<double> solver_slot(Solver& s, int i);  // the two buffers the solution alternates between

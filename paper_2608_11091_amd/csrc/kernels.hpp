@@ -175,6 +175,24 @@ constexpr int kLincombMax = 128;
 template <typename T>
 void lincomb(T* const* y, const T* const* x, const double* const* c, const double* s, const size_t* len,
              int ntasks, int nx, size_t maxlen, int accumulate, int limit, hipStream_t st);
+// Row scaling by exponentials, one task per output: out[i + j*n] =
+// exp(-t * (lam[i] - *shift)) * in[i + j*n] for i < n, j < cols (column-major, ld n).
+template <typename T>
+struct ExpScaleTask {
+  const T* in;
+  const T* lam;
+  const double* shift;
+  T* out;
+  double t;
+};
+template <typename T>
+void exp_scale_rows(const ExpScaleTask<T>* tasks_d, int ntasks, int n, int cols, hipStream_t st);
+// Coefficients of the shifted exponential-sum terms: lmin[k] = min_i lam_k[i]
+// (lam_k of length n[k], k < d) and coef[h] = eta t_h exp(-t_h sum_k lmin[k]),
+// t_h = exp((h - q) eta), h < 2q + 1.
+template <typename T>
+void expsum_shift(const T* const* lam, const int* n, int d, int q, double eta, double* lmin, double* coef,
+                  hipStream_t st);
 // out[i] = src[i * stride] for i < n, as double.
 template <typename T>
 void strided_gather(const T* src, size_t stride, int n, double* out, hipStream_t st);

@@ -90,6 +90,38 @@ __global__ __launch_bounds__(256) void lincomb_kernel(T* const* y, const T* cons
 }
 
 template <typename T>
+__global__ void exp_scale_rows_kernel(const ExpScaleTask<T>* tasks, int n, int cols) {
+  const ExpScaleTask<T> tk_ = tasks[blockIdx.y];
+  const size_t len = size_t(n) * cols;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = int(e % n);
+    tk_.out[e] = T(exp(-tk_.t * (double(tk_.lam[i]) - *tk_.shift))) * tk_.in[e];
+  }
+}
+
+template <typename T>
+__global__ void expsum_shift_kernel(const T* l0, const T* l1, const T* l2, const T* l3, int n0, int n1, int n2,
+                                    int n3, int d, int q, double eta, double* lmin, double* coef) {
+  __shared__ double m[kMaxD];
+  const T* ls[kMaxD] = {l0, l1, l2, l3};
+  const int ns[kMaxD] = {n0, n1, n2, n3};
+  if (threadIdx.x < d) {
+    const int k = threadIdx.x;
+    double v = double(ls[k][0]);
+    for (int i = 1; i < ns[k]; ++i) v = fmin(v, double(ls[k][i]));
+    m[k] = v;
+    lmin[k] = v;
+  }
+  __syncthreads();
+  double sum = 0.0;
+  for (int k = 0; k < d; ++k) sum += m[k];
+  for (int h = threadIdx.x; h < 2 * q + 1; h += blockDim.x) {
+    const double t = exp((h - q) * eta);
+    coef[h] = eta * t * exp(-t * sum);
+  }
+}
+
+template <typename T>
 __global__ void strided_gather_kernel(const T* src, size_t stride, int n, double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = double(src[size_t(i) * stride]);
@@ -207,6 +239,27 @@ void lincomb(T* const* y, const T* const* x, const double* const* c, const doubl
 }
 
 template <typename T>
+void exp_scale_rows(const ExpScaleTask<T>* tasks_d, int ntasks, int n, int cols, hipStream_t st) {
+  if (ntasks <= 0 || n <= 0 || cols <= 0) return;
+  const size_t len = size_t(n) * cols;
+  const size_t want = (len + 255) / 256;
+  const int blocks = int(want < 256 ? want : 256);
+  hipLaunchKernelGGL((exp_scale_rows_kernel<T>), dim3(blocks, ntasks), dim3(256), 0, st, tasks_d, n, cols);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void expsum_shift(const T* const* lam, const int* n, int d, int q, double eta, double* lmin, double* coef,
+                  hipStream_t st) {
+  TK_CHECK(d >= 1 && d <= kMaxD, kErrInvalidArg, "expsum_shift: order");
+  const T* l[kMaxD] = {lam[0], d > 1 ? lam[1] : lam[0], d > 2 ? lam[2] : lam[0], d > 3 ? lam[3] : lam[0]};
+  int nn[kMaxD] = {n[0], d > 1 ? n[1] : 1, d > 2 ? n[2] : 1, d > 3 ? n[3] : 1};
+  hipLaunchKernelGGL((expsum_shift_kernel<T>), dim3(1), dim3(256), 0, st, l[0], l[1], l[2], l[3], nn[0], nn[1],
+                     nn[2], nn[3], d, q, eta, lmin, coef);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
 void strided_gather(const T* src, size_t stride, int n, double* out, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL((strided_gather_kernel<T>), dim3(ceil_div(n, 256)), dim3(256), 0, st, src, stride, n, out);
@@ -304,5 +357,9 @@ template void sum_vectors<float>(const float*, size_t, int, int, double*, hipStr
 template void lincomb<double>(double* const*, const double* const*, const double* const*, const double*,
                               const size_t*, int, int, size_t, int, int, hipStream_t);
 template void strided_gather<double>(const double*, size_t, int, double*, hipStream_t);
+template void exp_scale_rows<double>(const ExpScaleTask<double>*, int, int, int, hipStream_t);
+template void exp_scale_rows<float>(const ExpScaleTask<float>*, int, int, int, hipStream_t);
+template void expsum_shift<double>(const double* const*, const int*, int, int, double, double*, double*, hipStream_t);
+template void expsum_shift<float>(const float* const*, const int*, int, int, double, double*, double*, hipStream_t);
 
 }  // namespace tk

@@ -53,6 +53,8 @@ struct Cycle {
   int maxiter = 60, kt = 2, s = 120;
   TT<T> rhs, W, dsol;
   std::vector<TT<T>> V;
+  std::vector<TT<T>> Z;  // preconditioned basis (flexible cycle), when pc.q > 0
+  PrecondT<T> pc;
   double* eps_pair = nullptr;  // device {eps, tau}
   double *beta2, *beta, *bs, *bsn2, *bsn, *Mcols, *h, *sumsq2, *omega;
   double *Hv, *tau, *R, *qtb, *y, *res, *nrmM2;
@@ -71,7 +73,9 @@ struct Cycle {
   }
 
   void plan(Planner& pl, const OpDev<T>& op, bool transpose, const std::array<const T*, kMaxD>& S,
-            const std::array<const T*, kMaxD>& omega_) {
+            const std::array<const T*, kMaxD>& omega_, const PrecondT<T>& pc_) {
+    pc = pc_;
+    const bool flexible = pc.q > 0;
     Arena& ar = pl.ar;
     Blob* bl = &pl.blob;
     const int d = sh.d;
@@ -79,6 +83,8 @@ struct Cycle {
     W = alloc_tt<T>(ar, sh);
     dsol = alloc_tt<T>(ar, sh);
     for (int k = 0; k <= maxiter; ++k) V.push_back(alloc_tt<T>(ar, sh));
+    if (flexible)
+      for (int k = 0; k < maxiter; ++k) Z.push_back(alloc_tt<T>(ar, sh));
     eps_pair = ar.alloc<double>(2);
     beta2 = ar.alloc<double>(1);
     beta = ar.alloc<double>(1);
@@ -133,10 +139,20 @@ struct Cycle {
       }
     }
 
-    // ---- iterations
+    // ---- iterations.  Each iteration plans its temporaries in a scratch
+    // scope: iterations run in sequence (the host waits for each one's status,
+    // and a RoundSum's side-stream work joins before the RoundSum ends), so
+    // they share that memory.
     for (int k = 0; k < maxiter; ++k) {
+      const size_t mk = ar.mark();
       Seq q;
-      Blocks<T> LV = plan_apply<T>(q, pl, sh, op, V[k], transpose);
+      TT<T> Zk = V[k];
+      if (flexible) {
+        // flexible cycle (Sec. 3.4): Z_k = T(M(V_k)), and the operator acts on Z_k
+        Zk = Z[k];
+        plan_precond<T>(q, pl, sh, pc, V[k], Zk, rcfg, omega_);
+      }
+      Blocks<T> LV = plan_apply<T>(q, pl, sh, op, Zk, transpose);
       plan_roundsum<T>(q, pl, sh, LV, rcfg, omega_, W, nullptr);
       Blocks<T> wb;
       wb.add(W, nullptr, 1.0);
@@ -170,12 +186,15 @@ struct Cycle {
         scale_copy<T>(vc, vc, cl, 1.0, nullptr, om, st);
       });
       iter.push_back(std::move(q));
+      ar.rewind(mk);
     }
 
-    // ---- final assembly X = RoundSum(sum_i y_i V_i)
+    // ---- final assembly X = RoundSum(sum_i y_i V_i) (sum_i y_i Z_i when flexible)
     Blocks<T> fb;
-    for (int i = 0; i < maxiter; ++i) fb.add(V[i], y + i, 1.0);
+    for (int i = 0; i < maxiter; ++i) fb.add(flexible ? Z[i] : V[i], y + i, 1.0);
     plan_roundsum<T>(fin, pl, sh, fb, rcfg, omega_, dsol, &nb_final);
+    // everything planned after the cycle lies past the iterations' scratch
+    ar.seal();
   }
 
   // Runs one cycle; returns (status, iterations).
@@ -238,7 +257,7 @@ void SolverDel::operator()(Solver* s) const { delete s; }
 SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const TT<double>& b,
                                     const SolveCfg& cfg, const std::array<const double*, kMaxD>& S,
                                     const std::array<const double*, kMaxD>& omega, const TT<double>* x0,
-                                    hipStream_t st) {
+                                    hipStream_t st, const PrecondT<double>& precond) {
   SolverPtr sv(new Solver());
   Solver& s = *sv;
   s.sh = sh;
@@ -305,7 +324,7 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
     c.maxiter = cfg.maxiter;
     c.kt = cfg.k_trunc;
     c.s = cfg.s;
-    c.plan(pl, op, cfg.transpose, S, omega);
+    c.plan(pl, op, cfg.transpose, S, omega, precond);
     s.r = c.rhs;     // the cycle reads its right-hand side in place
     s.d64 = c.dsol;  // and leaves its solution in place
   } else {
@@ -340,6 +359,14 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
       S32[k] = ds;
       O32[k] = dom;
     }
+    PrecondT<float> pc32;
+    pc32.q = precond.q;
+    if (precond.q > 0)
+      for (int k = 0; k < d; ++k) {
+        const size_t n = size_t(sh.n[k]);
+        pc32.V[k] = to32(precond.V[k], n * n);
+        pc32.lam[k] = to32(precond.lam[k], n);
+      }
     s.c32 = std::make_unique<Cycle<float>>();
     auto& c = *s.c32;
     c.sh = sh;
@@ -347,7 +374,7 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
     c.kt = cfg.k_trunc;
     c.s = cfg.s;
     c.bd_tol = 1e-6;
-    c.plan(pl, s.op32, cfg.transpose, S32, O32);
+    c.plan(pl, s.op32, cfg.transpose, S32, O32, pc32);
     s.r = alloc_tt<double>(ar, sh);
     s.d64 = alloc_tt<double>(ar, sh);
     emit_cast_tt<double, float>(s.s_to_cycle, sh, s.r, c.rhs);
