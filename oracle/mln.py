@@ -47,6 +47,7 @@ import numpy as np
 
 from .roundsum import _mttkrp
 from .sgmres import BREAKDOWN, NOT_CONVERGED, OK, sketched_lstsq
+from .tikhonov import projected_tikhonov
 from .tucker import Tucker, apply_op, exact_norm, inner, multi_ttm, scale
 
 RCOND = 1e-12
@@ -113,6 +114,7 @@ class MLNParams:
     save_memory: bool = False
     r_sol: int = 0
     p_sol: int = 0
+    tikhonov: bool = False      # projected Tikhonov with GCV on the sketched LS (Sec. 4.3)
 
 
 def mln_sgmres(terms, B: Tucker, Psi: Sequence[np.ndarray], prm: MLNParams, transpose: bool = False,
@@ -129,6 +131,7 @@ def mln_sgmres(terms, B: Tucker, Psi: Sequence[np.ndarray], prm: MLNParams, tran
     rt_sol = prm.r_sol + prm.p_sol
     cols: List[np.ndarray] = []
     hist: List[float] = []
+    lams: List[float] = []
     status = NOT_CONVERGED
     y = np.zeros(0)
     i = 0
@@ -145,6 +148,9 @@ def mln_sgmres(terms, B: Tucker, Psi: Sequence[np.ndarray], prm: MLNParams, tran
         omega = exact_norm([(1.0, W)])
         M = np.stack(cols, axis=1)
         y, res, rkk = sketched_lstsq(M, b_s)
+        if prm.tikhonov:
+            y, res, lam = projected_tikhonov(M, b_s)
+            lams.append(lam)
         rel = res / beta_s
         hist.append(rel)
         if log is not None:
@@ -171,4 +177,5 @@ def mln_sgmres(terms, B: Tucker, Psi: Sequence[np.ndarray], prm: MLNParams, tran
     X = mln_recovery(mln_sum(final_sk, [float(v) for v in y]), Psi_rec)
     Bn = exact_norm([(1.0, B)])
     true_res = exact_norm([(1.0, B)] + [(-c, T) for c, T in apply_op(terms, X, transpose=transpose)]) / Bn
-    return X, dict(status=status, iters=i, hist=hist, true_relres=true_res, beta=beta, beta_s=beta_s)
+    return X, dict(status=status, iters=i, hist=hist, true_relres=true_res, beta=beta, beta_s=beta_s,
+                   lam=lams)

@@ -40,6 +40,7 @@ import numpy as np
 from scipy.linalg import solve_triangular
 
 from .roundsum import RoundParams, roundsum
+from .tikhonov import projected_tikhonov
 from .tucker import Tucker, apply_op, exact_norm, inner, scale, sketch_krp
 
 OK, NOT_CONVERGED, BREAKDOWN, RANK_FLOOR = 0, 1, 2, 3
@@ -60,6 +61,7 @@ class SGMRESParams:
     eps_outer: Optional[float] = None      # x-update / residual RoundSums (default 1e-2 * tol)
     breakdown_tol: float = 1e-14
     replay: Optional[dict] = None          # rank replay: {"s": [...], "ranks": [...]} consumed in order
+    tikhonov: bool = False                 # projected Tikhonov with GCV on the sketched LS (Sec. 4.3)
 
 
 def sketched_lstsq(M: np.ndarray, b: np.ndarray):
@@ -107,6 +109,7 @@ def sgmres_cycle(terms, B: Tucker, S, Omega, prm: SGMRESParams, tol: Optional[fl
     y = np.zeros(0)
     k = 0
     Z: List[Tucker] = []
+    lams = []
     for k in range(1, prm.maxiter + 1):
         Zk = V[-1]
         if precond is not None:
@@ -125,11 +128,16 @@ def sgmres_cycle(terms, B: Tucker, S, Omega, prm: SGMRESParams, tol: Optional[fl
         wnorm = float(np.linalg.norm(W.core.ravel()))
         M = np.stack(cols, axis=1)
         y, res, rkk = sketched_lstsq(M, b_s)
+        if prm.tikhonov:
+            # the regularised y_k replaces the least-squares one; the breakdown
+            # test still reads the unregularised R factor
+            y, res, lam = projected_tikhonov(M, b_s)
+            lams.append(lam)
         rel = res / beta_s
         hist.append(rel)
         if log is not None:
             log.append(dict(k=k, s1=i1["s"], r1=i1["ranks"], s2=i2["s"], r2=i2["ranks"], h=h,
-                            omega=omega, res=rel))
+                            omega=omega, res=rel, lam=lams[-1] if lams else None))
         if omega <= prm.breakdown_tol * wnorm or rkk <= prm.breakdown_tol * np.linalg.norm(M):
             status = BREAKDOWN
             break
@@ -141,7 +149,7 @@ def sgmres_cycle(terms, B: Tucker, S, Omega, prm: SGMRESParams, tol: Optional[fl
     X, i3 = roundsum([(float(y[i]), basis[i]) for i in range(len(y))], Omega, rep.next(rp))
     if log is not None:
         log.append(dict(final=True, s=i3["s"], r=i3["ranks"]))
-    return X, dict(status=status, iters=k, hist=hist, beta=beta, beta_s=beta_s)
+    return X, dict(status=status, iters=k, hist=hist, beta=beta, beta_s=beta_s, lam=lams)
 
 
 def _residual_blocks(terms, B: Tucker, X: Tucker, transpose=False):
