@@ -128,6 +128,11 @@ typedef struct {
   int32_t precond_q;                   /* 0: none; >= 1: 2q + 1 terms */
   const double* const* precond_V;      /* host array of d device pointers: orthogonal V_k, n_k x n_k column-major */
   const double* const* precond_lambda; /* host array of d device pointers: eigenvalues lambda_k, length n_k */
+  /* Projected Tikhonov (Sec. 4.3): 1 replaces every iteration's y_k by
+   * argmin ||M_k y - b_s||^2 + lambda_k^2 ||y||^2 with lambda_k chosen by
+   * GCV (see tsgmres_projected_tikhonov); the sketched residual and its
+   * convergence test use that y_k.  0: plain sketched least squares. */
+  int32_t tikhonov;
 } tk_sgmres_params;
 
 /* Solver report (host memory owned by the caller). */
@@ -139,6 +144,7 @@ typedef struct {
   double* hist_true;           /* [hist_cap] true relative residual per cycle, or NULL */
   int32_t* hist_ranks;         /* [hist_cap * TK_MAX_D] ranks of each new basis tensor, or NULL */
   double* hist_cycle_seconds;  /* [hist_cap] elapsed seconds at the end of each cycle, or NULL */
+  double* hist_lambda;         /* [hist_cap] Tikhonov lambda_k per iteration (when regularised), or NULL */
 } tk_sgmres_info;
 
 /* Operator factors applied to a Tucker tensor (Eq. (2)): for every term j and
@@ -213,6 +219,7 @@ typedef struct {
                             r_sol factor columns; the solution is recovered from
                             the truncated sketches with Psi_k[:, :r_sol + p_sol] */
   int32_t r_sol, p_sol;  /* save_memory: 1 <= r_sol <= r, r_sol + p_sol <= r + p */
+  int32_t tikhonov;      /* 1: projected Tikhonov with GCV, as in tk_sgmres_params */
 } tk_mln_params;
 
 /* MLN sketch of a block sum x = sum_b coef_b X_b (the sketch of every block
@@ -245,6 +252,25 @@ int tucker_mln_recover_workspace(int32_t d, const int64_t* n, int32_t r, int32_t
 int tsgmres_mln_solve(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* prm, const double* const* Psi,
                       tk_tucker* x, tk_sgmres_info* info, void* ws, size_t ws_bytes, void* stream);
 int tsgmres_mln_solve_workspace(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* prm, size_t* bytes);
+
+/* Projected Tikhonov regularisation of a sketched least-squares problem
+ * (Sec. 4.3): y = argmin ||M y - b||^2 + lambda^2 ||y||^2 for the device
+ * matrix M (s x k, column-major, ld s) and device vector b (length s),
+ * 1 <= k <= 64, k <= s <= 256.  M is factorised by Householder QR,
+ * M = Q R, which reduces the problem to k + 1 data: c = (Q^T b)[:k] and
+ * rho = ||b - Q c||.  With the SVD R = U diag(sigma) W^T (one-sided Jacobi)
+ * and beta_hat = U^T c, y = W diag(sigma / (sigma^2 + lambda^2)) beta_hat.
+ * lambda_fixed >= 0 uses that lambda; < 0 chooses it by generalised cross
+ * validation on the projected problem,
+ *   G(lambda) = ||M y - b||^2 / (1 + sum_i lambda^2 / (sigma_i^2 + lambda^2))^2,
+ * minimised over 241 log-spaced points in [1e-12, 1] sigma_1 followed by 60
+ * golden-section steps in log10(lambda) between the grid minimum's
+ * neighbours (lambda = 0 for M = 0).  Writes y (device, k) and out (device,
+ * 2): out[0] = lambda, out[1] = ||M y - b|| / ||b||.  Synchronous on
+ * `stream`. */
+int tsgmres_projected_tikhonov(const double* M, const double* b, int32_t s, int32_t k, double lambda_fixed,
+                               double* y, double* out, void* ws, size_t ws_bytes, void* stream);
+int tsgmres_projected_tikhonov_workspace(int32_t s, int32_t k, size_t* bytes);
 
 /* Kernel-class timers for performance reporting (not thread-safe; for
  * benchmarks).  kind: 0 GEMM, 1 symmetric eigensolver with eigenvectors

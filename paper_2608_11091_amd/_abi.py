@@ -23,6 +23,7 @@ EXPORTS = [
     "tsgmres_backward", "tsgmres_backward_workspace", "tucker_norm", "tucker_norm_workspace",
     "tucker_mln_sketch", "tucker_mln_sketch_workspace", "tucker_mln_recover", "tucker_mln_recover_workspace",
     "tsgmres_mln_solve", "tsgmres_mln_solve_workspace",
+    "tsgmres_projected_tikhonov", "tsgmres_projected_tikhonov_workspace",
     "tk_kernel_timer", "tk_kernel_timer_read", "tk_last_error", "tk_version",
 ]
 
@@ -51,13 +52,15 @@ class TkSgmresParams(C.Structure):
                 ("max_restarts", C.c_int32), ("k_trunc", C.c_int32), ("rank_cap", C.c_int32),
                 ("oversample", C.c_int32), ("s", C.c_int64), ("eps_trunc", C.c_double), ("eps_min", C.c_double),
                 ("tol_inner_floor", C.c_double), ("x0", C.POINTER(TkTucker)), ("precond_q", C.c_int32),
-                ("precond_V", C.POINTER(C.c_void_p)), ("precond_lambda", C.POINTER(C.c_void_p))]
+                ("precond_V", C.POINTER(C.c_void_p)), ("precond_lambda", C.POINTER(C.c_void_p)),
+                ("tikhonov", C.c_int32)]
 
 
 class TkMlnParams(C.Structure):
     _fields_ = [("r", C.c_int32), ("p", C.c_int32), ("tol", C.c_double), ("eta", C.c_double),
                 ("maxiter", C.c_int32), ("k_trunc", C.c_int32), ("breakdown_tol", C.c_double),
-                ("save_memory", C.c_int32), ("r_sol", C.c_int32), ("p_sol", C.c_int32)]
+                ("save_memory", C.c_int32), ("r_sol", C.c_int32), ("p_sol", C.c_int32),
+                ("tikhonov", C.c_int32)]
 
 
 class TkSgmresInfo(C.Structure):
@@ -65,7 +68,7 @@ class TkSgmresInfo(C.Structure):
                 ("true_relres", C.c_double), ("seconds", C.c_double), ("hist_cap", C.c_int32),
                 ("hist_len", C.c_int32), ("hist_sketched", C.POINTER(C.c_double)),
                 ("hist_true", C.POINTER(C.c_double)), ("hist_ranks", C.POINTER(C.c_int32)),
-                ("hist_cycle_seconds", C.POINTER(C.c_double))]
+                ("hist_cycle_seconds", C.POINTER(C.c_double)), ("hist_lambda", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -102,6 +105,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.tsgmres_mln_solve.argtypes = [P(TkKronOp), P(TkTucker), P(TkMlnParams), P(VP), P(TkTucker),
                                       P(TkSgmresInfo), VP, SZ, VP]
     lib.tsgmres_mln_solve_workspace.argtypes = [P(TkKronOp), P(TkTucker), P(TkMlnParams), P(SZ)]
+    lib.tsgmres_projected_tikhonov.argtypes = [VP, VP, I32, I32, C.c_double, VP, VP, VP, SZ, VP]
+    lib.tsgmres_projected_tikhonov_workspace.argtypes = [I32, I32, P(SZ)]
     lib.tk_kernel_timer.argtypes = [C.c_int32, C.c_int32]
     lib.tk_kernel_timer_read.argtypes = [C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.tk_last_error.restype = C.c_char_p

@@ -252,12 +252,15 @@ class SolveParams:
     # matrix, lambda_k of length n_k), e.g. from ``laplacian_precond``
     precond_q: int = 0
     precond: Optional[Tuple[list, list]] = None
+    # projected Tikhonov with GCV on the sketched least squares (Sec. 4.3)
+    tikhonov: bool = False
 
     def struct(self, s: int, x0: Optional[Tucker] = None):
         p = TkSgmresParams()
         p.form, p.tol, p.eta, p.maxiter, p.max_restarts = self.form, self.tol, self.eta, self.maxiter, self.max_restarts
         p.k_trunc, p.rank_cap, p.oversample, p.s = self.k_trunc, self.rank_cap, self.oversample, s
         p.eps_trunc, p.eps_min, p.tol_inner_floor = self.eps_trunc, self.eps_min, self.tol_inner_floor
+        p.tikhonov = int(self.tikhonov)
         keep = []
         if x0 is not None:
             xs = x0.struct()
@@ -294,23 +297,26 @@ def _info(hist_cap: int):
     ht = (C.c_double * hist_cap)()
     hr = (C.c_int32 * (hist_cap * TK_MAX_D))()
     hc = (C.c_double * hist_cap)()
+    hl = (C.c_double * hist_cap)()
     info.hist_cap = hist_cap
     info.hist_sketched = hs
     info.hist_true = ht
     info.hist_ranks = hr
     info.hist_cycle_seconds = hc
-    return info, (hs, ht, hr, hc)
+    info.hist_lambda = hl
+    return info, (hs, ht, hr, hc, hl)
 
 
 def _info_dict(info, keep, d):
-    hs, ht, hr, hc = keep
+    hs, ht, hr, hc, hl = keep
     n = info.hist_len
     return dict(status=int(info.status), status_name=_abi.STATUS.get(int(info.status), "?"),
                 iters=int(info.iters_total), cycles=int(info.cycles), true_relres=float(info.true_relres),
                 seconds=float(info.seconds), hist=[hs[i] for i in range(n)],
                 true_hist=[ht[i] for i in range(int(info.cycles))],
                 cycle_seconds=[hc[i] for i in range(int(info.cycles))],
-                ranks=[tuple(hr[i * TK_MAX_D + k] for k in range(d)) for i in range(n)])
+                ranks=[tuple(hr[i * TK_MAX_D + k] for k in range(d)) for i in range(n)],
+                lam=[hl[i] for i in range(n)])
 
 
 def _hist_cap(prm: SolveParams) -> int:
@@ -440,12 +446,14 @@ class MlnParams:
     save_memory: bool = False
     r_sol: int = 0
     p_sol: int = 0
+    tikhonov: bool = False   # projected Tikhonov with GCV (Sec. 4.3)
 
     def struct(self) -> TkMlnParams:
         p = TkMlnParams()
         p.r, p.p, p.tol, p.eta, p.maxiter, p.k_trunc = self.r, self.p, self.tol, self.eta, self.maxiter, self.k_trunc
         p.breakdown_tol, p.save_memory, p.r_sol, p.p_sol = self.breakdown_tol, int(self.save_memory), self.r_sol, \
             self.p_sol
+        p.tikhonov = int(self.tikhonov)
         return p
 
 
@@ -514,3 +522,30 @@ def mln_solve(op: KronOp, b: Tucker, Psi: Sequence[torch.Tensor], prm: MlnParams
                                 C.c_void_p(ws.data_ptr()), nb.value, _stream()))
     x.ranks = tuple(int(xs.r[k]) for k in range(b.d))
     return x, _info_dict(info, keep, b.d)
+
+
+# ---------------------------------------------------------------- projected Tikhonov
+def projected_tikhonov(M: torch.Tensor, b: torch.Tensor, lam: Optional[float] = None):
+    """Regularised least squares argmin ||M y - b||^2 + lambda^2 ||y||^2 on
+    the device (Sec. 4.3): ``M`` is an (s, k) FP64 CUDA tensor, ``b`` length
+    s; ``lam`` None chooses lambda by GCV.  Returns (y, lambda, ||M y - b|| /
+    ||b||)."""
+    lib = _abi.load()
+    if M.dim() != 2 or M.dtype != torch.float64 or not M.is_cuda:
+        raise ValueError("M must be a 2D float64 CUDA tensor")
+    s, k = int(M.shape[0]), int(M.shape[1])
+    if b.shape != (s,) or b.dtype != torch.float64 or b.device != M.device:
+        raise ValueError("b must be a float64 vector of length s on M's device")
+    Mc = M.t().contiguous()            # column-major s x k
+    bc = b.contiguous()
+    nb = C.c_size_t()
+    check(lib.tsgmres_projected_tikhonov_workspace(s, k, C.byref(nb)))
+    ws = _workspace(nb.value, M.device)
+    y = torch.empty(k, dtype=torch.float64, device=M.device)
+    out = torch.empty(2, dtype=torch.float64, device=M.device)
+    check(lib.tsgmres_projected_tikhonov(C.c_void_p(Mc.data_ptr()), C.c_void_p(bc.data_ptr()), s, k,
+                                         -1.0 if lam is None else float(lam), C.c_void_p(y.data_ptr()),
+                                         C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()), nb.value,
+                                         _stream()))
+    o = out.cpu()
+    return y, float(o[0]), float(o[1])

@@ -342,6 +342,7 @@ SolveCfg solve_cfg(const tk_sgmres_params* prm) {
   c.eps_trunc = prm->eps_trunc;
   c.eps_min = prm->eps_min;
   c.tol_inner_floor = prm->tol_inner_floor;
+  c.tikhonov = prm->tikhonov != 0;
   return c;
 }
 
@@ -358,6 +359,7 @@ void check_params(const tk_sgmres_params* prm) {
   TK_CHECK(prm->precond_q >= 0 && prm->precond_q <= 400, kErrInvalidArg, "precond_q must be in [0, 400]");
   TK_CHECK(prm->precond_q == 0 || (prm->precond_V != nullptr && prm->precond_lambda != nullptr), kErrInvalidArg,
            "preconditioner eigenpairs missing");
+  TK_CHECK(prm->tikhonov == 0 || prm->tikhonov == 1, kErrInvalidArg, "tikhonov must be 0 or 1");
 }
 
 PrecondT<double> precond_of(const tk_sgmres_params* prm, int d) {
@@ -398,6 +400,9 @@ void fill_info(const SolveInfo& si, tk_sgmres_info* info, int d) {
   if (info->hist_cycle_seconds)
     for (int i = 0; i < std::min<int>(int(si.hist_time.size()), info->hist_cap); ++i)
       info->hist_cycle_seconds[i] = si.hist_time[i];
+  if (info->hist_lambda)
+    for (int i = 0; i < info->hist_cap; ++i)
+      info->hist_lambda[i] = i < int(si.hist_lambda.size()) ? si.hist_lambda[i] : 0.0;
 }
 
 int do_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* prm, const double* const* S,
@@ -451,6 +456,8 @@ int do_backward(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xb
   check_dims(x->d, x->n);
   check_op(op, x->d, x->n);
   check_tucker(x, "x", x->d, x->n);
+  TK_CHECK(prm == nullptr || prm->tikhonov == 0, kErrUnsupported,
+           "the adjoint gradients assume an unregularised solve (tikhonov must be 0)");
   check_params(prm);
   TK_CHECK(S != nullptr && omega != nullptr, kErrInvalidArg, "sketch matrices missing");
   const int d = x->d;
@@ -611,6 +618,7 @@ void check_mln_params(const tk_mln_params* prm) {
   TK_CHECK(prm->tol > 0 && prm->eta > 0 && prm->eta <= 1, kErrInvalidArg, "tol > 0 and 0 < eta <= 1 required");
   TK_CHECK(prm->maxiter >= 1 && prm->maxiter <= 64, kErrUnsupported, "maxiter must be in [1, 64]");
   TK_CHECK(prm->k_trunc >= 1, kErrInvalidArg, "k_trunc must be >= 1");
+  TK_CHECK(prm->tikhonov == 0 || prm->tikhonov == 1, kErrInvalidArg, "tikhonov must be 0 or 1");
   if (prm->save_memory)
     TK_CHECK(prm->r_sol >= 1 && prm->r_sol <= prm->r && prm->p_sol >= 0 && prm->r_sol + prm->p_sol <= prm->r + prm->p,
              kErrInvalidArg, "save_memory needs 1 <= r_sol <= r and r_sol + p_sol <= r + p");
@@ -641,6 +649,7 @@ int do_mln_solve(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* 
   cfg.save_memory = prm->save_memory != 0;
   cfg.r_sol = prm->r_sol;
   cfg.p_sol = prm->p_sol;
+  cfg.tikhonov = prm->tikhonov != 0;
   auto solver = make_mln_solver(ar, sh, op_dev(op), bi, cfg, ps, st);
   if (ar.measuring()) return 0;
   TK_CHECK(x != nullptr, kErrInvalidArg, "x is NULL");
@@ -661,9 +670,47 @@ int do_mln_solve(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* 
     si.hist_ranks = mi.ranks;
     si.hist_true = {mi.true_relres};
     si.hist_time = {mi.seconds};
+    si.hist_lambda = mi.lambda;
     fill_info(si, info, d);
   }
   return mi.status;
+}
+
+// ---------------------------------------------------------------- Tikhonov
+int do_tikhonov(const double* M, const double* b, int s, int k, double lam_fixed, double* y, double* out, Arena& ar,
+                hipStream_t st) {
+  TK_CHECK(k >= 1 && k <= 64, kErrUnsupported, "k must be in [1, 64]");
+  TK_CHECK(s >= k && s <= 256, kErrUnsupported, "s must be in [k, 256]");
+  TK_CHECK(std::isfinite(lam_fixed) || lam_fixed < 0, kErrInvalidArg, "lambda_fixed must be finite");
+  LsState ls{};
+  ls.Mcol = M;
+  ls.bs = b;
+  ls.Hv = ar.alloc<double>(size_t(s) * k);
+  ls.tau = ar.alloc<double>(k);
+  ls.R = ar.alloc<double>(size_t(k) * k);
+  ls.qtb = ar.alloc<double>(s);
+  ls.y = ar.alloc<double>(k);
+  ls.res = ar.alloc<double>(k);
+  ls.nrmM2 = ar.alloc<double>(1);
+  ls.flags = ar.alloc<int>(4);
+  ls.lam = ar.alloc<double>(k);
+  double* bn2 = ar.alloc<double>(1);
+  double* bn = ar.alloc<double>(1);
+  ls.bs_norm = bn;
+  const double** tab = ar.alloc<const double*>(1);
+  if (ar.measuring()) return 0;
+  TK_CHECK(M != nullptr && b != nullptr && y != nullptr && out != nullptr, kErrInvalidArg, "NULL argument");
+  TK_HIP(hipMemcpyAsync(tab, &b, sizeof(b), hipMemcpyHostToDevice, st));
+  dot_batched<double>(tab, tab, size_t(s), 1, 1.0, bn2, st);
+  vec_sqrt(bn2, bn, 1, st);
+  ls_init(ls, s, st);
+  for (int j = 0; j < k; ++j) ls_add_column(ls, s, k, j, 0.0, 0.0, st);
+  ls_tikhonov(ls, s, k, k - 1, 0.0, lam_fixed, st);
+  TK_HIP(hipMemcpyAsync(y, ls.y, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+  TK_HIP(hipMemcpyAsync(out, ls.lam + (k - 1), sizeof(double), hipMemcpyDeviceToDevice, st));
+  TK_HIP(hipMemcpyAsync(out + 1, ls.res + (k - 1), sizeof(double), hipMemcpyDeviceToDevice, st));
+  TK_HIP(hipStreamSynchronize(st));
+  return 0;
 }
 
 }  // namespace
@@ -846,6 +893,23 @@ int tsgmres_mln_solve_workspace(const tk_kron_op* op, const tk_tucker* b, const 
     Arena ar(nullptr, 0);
     const double* dummy[TK_MAX_D] = {nullptr, nullptr, nullptr, nullptr};
     const int rv = do_mln_solve(op, b, prm, dummy, nullptr, nullptr, ar, nullptr);
+    if (bytes) *bytes = ar.used();
+    return rv;
+  });
+}
+
+int tsgmres_projected_tikhonov(const double* M, const double* b, int32_t s, int32_t k, double lambda_fixed,
+                               double* y, double* out, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
+    Arena ar(ws, ws_bytes);
+    return do_tikhonov(M, b, s, k, lambda_fixed, y, out, ar, as_stream(stream));
+  });
+}
+int tsgmres_projected_tikhonov_workspace(int32_t s, int32_t k, size_t* bytes) {
+  return guarded([&] {
+    Arena ar(nullptr, 0);
+    const int rv = do_tikhonov(nullptr, nullptr, s, k, -1.0, nullptr, nullptr, ar, nullptr);
     if (bytes) *bytes = ar.used();
     return rv;
   });

@@ -210,12 +210,14 @@ struct MlnCfg {
   double bd_tol = 1e-14;
   bool save_memory = false;
   int r_sol = 0, p_sol = 0;
+  bool tikhonov = false;  // projected Tikhonov with GCV on the sketched least squares
 };
 struct MlnInfo {
   int status = 1, iters = 0;
   double true_relres = 1.0, seconds = 0.0;
   std::vector<double> hist;  // relative sketched residual per iteration
   std::vector<int> ranks;    // d per iteration: ranks of the new basis tensor
+  std::vector<double> lambda;  // regularisation parameter per iteration (when regularised)
 };
 class MlnSolver;
 struct MlnSolverDel {
@@ -251,6 +253,7 @@ struct SolveCfg {
   int s = 120;
   double eps_trunc = -1, eps_min = -1, tol_inner_floor = -1;
   bool transpose = false;
+  bool tikhonov = false;  // projected Tikhonov with GCV on the sketched least squares
 };
 
 struct SolveInfo {
@@ -258,6 +261,7 @@ struct SolveInfo {
   double true_relres = 1.0, seconds = 0.0;
   std::vector<double> hist_sketched, hist_true, hist_time;
   std::vector<int> hist_ranks;  // d per iteration
+  std::vector<double> hist_lambda;  // regularisation parameter per iteration (when regularised)
 };
 
 // Solver bound to fixed device inputs; plans everything at construction.

@@ -230,9 +230,14 @@ struct LsState {
   int* flags;          // [0] breakdown, [1] converged
   double beta_s_inv;   // not used when bs_norm is given
   const double* bs_norm; // device ||b_s||
+  double* lam = nullptr; // regularisation parameter per column (kmax), when regularised
 };
 void ls_add_column(const LsState& st_, int s, int kmax, int k, double conv_tol, double breakdown_tol,
                    hipStream_t st);
 void ls_init(const LsState& st_, int s, hipStream_t st);
+// Projected Tikhonov on the factorisation after column k (k + 1 columns):
+// y, res[k], lam[k] and the converged flag are replaced by the regularised
+// ones.  lam_fixed >= 0 uses that lambda, < 0 chooses it by GCV.
+void ls_tikhonov(const LsState& st_, int s, int kmax, int k, double conv_tol, double lam_fixed, hipStream_t st);
 
 }  // namespace tk

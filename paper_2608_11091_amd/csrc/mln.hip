@@ -253,11 +253,12 @@ class MlnSolver {
   std::vector<MlnSk> Strunc; // truncated copies of every stored sketch (save_memory)
   MlnSk Wsk, Fsk;
   double *bnorm2, *beta, *d0, *bs, *bsn2, *bsn, *Mcols, *h, *s2, *omega, *rnorm2;
-  double *Hv, *tau, *R, *qtb, *y, *res, *nrmM2;
+  double *Hv, *tau, *R, *qtb, *y, *res, *nrmM2, *lam;
   int* flags;
   IterStatus* st_dev;
   IterStatus* st_host = nullptr;
   double* host2 = nullptr;
+  double* lam_host = nullptr;
   Seq setup, fin;
   std::vector<Seq> iter;
   int nb_final = 0;
@@ -267,6 +268,7 @@ class MlnSolver {
   ~MlnSolver() {
     if (st_host) (void)hipHostFree(st_host);
     if (host2) (void)hipHostFree(host2);
+    if (lam_host) (void)hipHostFree(lam_host);
   }
   const MlnSk& full(int i) const { return Sfull[cfg.save_memory ? i % (kt + 2) : i]; }
 };
@@ -326,12 +328,14 @@ MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op
   s.y = ar.alloc<double>(mx);
   s.res = ar.alloc<double>(mx);
   s.nrmM2 = ar.alloc<double>(1);
+  s.lam = ar.alloc<double>(mx);
   s.flags = ar.alloc<int>(4);
   s.st_dev = ar.alloc<IterStatus>(1);
-  s.ls = LsState{s.Mcols, s.bs, s.Hv, s.tau, s.R, s.qtb, s.y, s.res, s.nrmM2, s.flags, 0.0, s.bsn};
+  s.ls = LsState{s.Mcols, s.bs, s.Hv, s.tau, s.R, s.qtb, s.y, s.res, s.nrmM2, s.flags, 0.0, s.bsn, s.lam};
   if (!ar.measuring()) {
     TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&s.st_host), sizeof(IterStatus), 0));
     TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&s.host2), 2 * sizeof(double), 0));
+    TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&s.lam_host), sizeof(double) * mx, 0));
   }
   const size_t cl = sh.core_len();
   auto store = [&](Seq& q, int i) {
@@ -417,8 +421,11 @@ MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op
       const double bdt = cfg.bd_tol;
       IterStatus* sd = s.st_dev;
       int* fl = s.flags;
+      const bool tik = cfg.tikhonov;
       q.steps.push_back([=](hipStream_t st) {
         ls_add_column(lsv, rt, mx, k, *ctol, bdt, st);
+        // regularised y_k and residual (Sec. 4.3)
+        if (tik) ls_tikhonov(lsv, rt, mx, k, *ctol, -1.0, st);
         iter_status(s2k, fl, resk, rk, d, bdt, om, sd, st);
         scale_copy<double>(vc, vc, cl, 1.0, nullptr, om, st);
       });
@@ -486,7 +493,9 @@ void mln_solver_run(MlnSolver& s, TT<double>& x_out, MlnInfo& info, hipStream_t 
   s.fin.run(st);
   TK_HIP(hipMemcpyAsync(s.host2, s.rnorm2, sizeof(double), hipMemcpyDeviceToHost, st));
   TK_HIP(hipMemcpyAsync(s.host2 + 1, s.bnorm2, sizeof(double), hipMemcpyDeviceToHost, st));
+  if (s.cfg.tikhonov) TK_HIP(hipMemcpyAsync(s.lam_host, s.lam, sizeof(double) * kend, hipMemcpyDeviceToHost, st));
   TK_HIP(hipStreamSynchronize(st));
+  if (s.cfg.tikhonov) info.lambda.assign(s.lam_host, s.lam_host + kend);
   const double rn = std::sqrt(std::max(s.host2[0], 0.0)), bn = std::sqrt(std::max(s.host2[1], 0.0));
   info.status = status;
   info.iters = kend;

@@ -51,16 +51,18 @@ template <typename T>
 struct Cycle {
   Shape sh;
   int maxiter = 60, kt = 2, s = 120;
+  bool tikhonov = false;
   TT<T> rhs, W, dsol;
   std::vector<TT<T>> V;
   std::vector<TT<T>> Z;  // preconditioned basis (flexible cycle), when pc.q > 0
   PrecondT<T> pc;
   double* eps_pair = nullptr;  // device {eps, tau}
   double *beta2, *beta, *bs, *bsn2, *bsn, *Mcols, *h, *sumsq2, *omega;
-  double *Hv, *tau, *R, *qtb, *y, *res, *nrmM2;
+  double *Hv, *tau, *R, *qtb, *y, *res, *nrmM2, *lam;
   int* flags;
   IterStatus* st_dev;
   IterStatus* st_host = nullptr;  // pinned
+  double* lam_host = nullptr;     // pinned, maxiter
   Seq setup, fin;
   std::vector<Seq> iter;
   int nb_final = 0;
@@ -70,6 +72,7 @@ struct Cycle {
 
   ~Cycle() {
     if (st_host) (void)hipHostFree(st_host);
+    if (lam_host) (void)hipHostFree(lam_host);
   }
 
   void plan(Planner& pl, const OpDev<T>& op, bool transpose, const std::array<const T*, kMaxD>& S,
@@ -102,10 +105,14 @@ struct Cycle {
     y = ar.alloc<double>(maxiter);
     res = ar.alloc<double>(maxiter);
     nrmM2 = ar.alloc<double>(1);
+    lam = ar.alloc<double>(maxiter);
     flags = ar.alloc<int>(4);
     st_dev = ar.alloc<IterStatus>(1);
-    ls = LsState{Mcols, bs, Hv, tau, R, qtb, y, res, nrmM2, flags, 0.0, bsn};
-    if (!ar.measuring()) TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&st_host), sizeof(IterStatus), 0));
+    ls = LsState{Mcols, bs, Hv, tau, R, qtb, y, res, nrmM2, flags, 0.0, bsn, lam};
+    if (!ar.measuring()) {
+      TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&st_host), sizeof(IterStatus), 0));
+      TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&lam_host), sizeof(double) * maxiter, 0));
+    }
 
     RoundCfg rcfg;
     rcfg.eps_dev = eps_pair;
@@ -179,9 +186,13 @@ struct Cycle {
       const double bdt = bd_tol;
       IterStatus* sd = st_dev;
       int* fl = flags;
+      const bool tik = tikhonov;
       q.steps.push_back([=](hipStream_t st) {
         dot_batched<T>(bl->at<const T*>(off), bl->at<const T*>(off), cl, 2, 1.0, s2, st);
         ls_add_column(lsv, ss, mx, k, *ctol, bdt, st);
+        // regularised y_k and residual (Sec. 4.3); the breakdown test keeps
+        // the unregularised R factor
+        if (tik) ls_tikhonov(lsv, ss, mx, k, *ctol, -1.0, st);
         iter_status(s2, fl, resk, rk, d, bdt, om, sd, st);
         scale_copy<T>(vc, vc, cl, 1.0, nullptr, om, st);
       });
@@ -226,6 +237,11 @@ struct Cycle {
     }
     nb_final = kend;
     fin.run(st);
+    if (tikhonov) {
+      TK_HIP(hipMemcpyAsync(lam_host, lam, sizeof(double) * kend, hipMemcpyDeviceToHost, st));
+      TK_HIP(hipStreamSynchronize(st));
+      info.hist_lambda.insert(info.hist_lambda.end(), lam_host, lam_host + kend);
+    }
     return {status, kend};
   }
 };
@@ -324,6 +340,7 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
     c.maxiter = cfg.maxiter;
     c.kt = cfg.k_trunc;
     c.s = cfg.s;
+    c.tikhonov = cfg.tikhonov;
     c.plan(pl, op, cfg.transpose, S, omega, precond);
     s.r = c.rhs;     // the cycle reads its right-hand side in place
     s.d64 = c.dsol;  // and leaves its solution in place
@@ -373,6 +390,7 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
     c.maxiter = cfg.maxiter;
     c.kt = cfg.k_trunc;
     c.s = cfg.s;
+    c.tikhonov = cfg.tikhonov;
     c.bd_tol = 1e-6;
     c.plan(pl, s.op32, cfg.transpose, S32, O32, pc32);
     s.r = alloc_tt<double>(ar, sh);

@@ -113,17 +113,11 @@ def test_zero_matrix_gives_zero_solution():
 
 
 def _noisy_blur_problem(n, seed, noise):
-    from workloads import gaussian_blur_toeplitz
-    rng = np.random.default_rng(seed)
-    K = gaussian_blur_toeplitz(n, sigma=1.5, halfwidth=6)
-    Xc = rng.standard_normal((2, 2, 2))
-    XU = [rng.standard_normal((n, 2)) for _ in range(3)]
-    Xt = O.Tucker(Xc, XU)
-    Y = O.to_dense(O.Tucker(Xc, [K @ u for u in XU]))
-    Y = Y + noise * np.linalg.norm(Y) / np.sqrt(Y.size) * rng.standard_normal(Y.shape)
+    from workloads import noisy_blur_problem
+    K, Y, (Xc, XU), rng = noisy_blur_problem(n, seed, noise)
     # full-rank Tucker form of the noisy data (identity factors): no compression
     B = O.Tucker(Y, [np.eye(n) for _ in range(3)])
-    return [(1.0, [K, K, K])], B, Xt, rng
+    return [(1.0, [K, K, K])], B, O.Tucker(Xc, XU), rng
 
 
 def test_gcv_regularises_a_noisy_blur_cycle():

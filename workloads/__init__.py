@@ -113,6 +113,23 @@ def gaussian_blur_toeplitz(n: int, sigma: float = 3.0, halfwidth: int = 12) -> n
     return K
 
 
+def noisy_blur_problem(n: int, seed: int = 5, noise: float = 0.05, sigma: float = 1.5, halfwidth: int = 6,
+                       rank: int = 2):
+    """Small ill-posed deblurring problem for the regularised solves: K the
+    Gaussian blur (``gaussian_blur_toeplitz``), X_true a rank-(rank,)*3 Tucker
+    image with N(0,1) core and factors, Y = X_true x_k K plus white noise of
+    relative level ``noise`` (dense, n^3).  Returns (K, Y, (core, factors) of
+    X_true, rng) with the rng positioned after the draws."""
+    rng = np.random.default_rng(seed)
+    K = gaussian_blur_toeplitz(n, sigma=sigma, halfwidth=halfwidth)
+    Xc = rng.standard_normal((rank,) * 3)
+    XU = [rng.standard_normal((n, rank)) for _ in range(3)]
+    KU = [K @ u for u in XU]
+    Y = np.einsum("abc,ia,jb,kc->ijk", Xc, KU[0], KU[1], KU[2])
+    Y = Y + noise * np.linalg.norm(Y) / np.sqrt(Y.size) * rng.standard_normal(Y.shape)
+    return K, Y, (Xc, XU), rng
+
+
 def draw_sketches(n: Sequence[int], s: int, cap: int, p: int, seed: int = 0):
     """Gaussian N(0,1) sketches from one seeded stream: S_1..S_d (n_k x s)
     then Omega_1..Omega_d (n_k x (cap+p))."""
