@@ -276,7 +276,7 @@ int tsgmres_projected_tikhonov_workspace(int32_t s, int32_t k, size_t* bytes);
  * benchmarks).  kind: 0 GEMM, 1 symmetric eigensolver with eigenvectors
  * (Jacobi), 2 QR (Cholesky-QR / Householder), 3 Khatri-Rao reduction,
  * 4 sketched least-squares update, 5 eigenvalues-only solver (tridiagonal
- * reduction + bisection).  Enabling (or disabling) clears the record; while
+ * reduction + bisection), 6 projected Tikhonov (Jacobi SVD + GCV).  Enabling (or disabling) clears the record; while
  * enabled, every launch of the class records a HIP event pair on its stream.
  * tk_kernel_timer_read synchronises those events and returns the launch count,
  * the summed kernel time in milliseconds and (each optional, may be NULL) the

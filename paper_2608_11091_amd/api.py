@@ -408,7 +408,7 @@ class TuckerSGMRESLoss(torch.autograd.Function):
         return g * torch.from_numpy(dalpha), None
 
 
-KERNEL_CLASSES = {"gemm": 0, "jacobi": 1, "qr": 2, "krp": 3, "ls": 4, "eigvals": 5}
+KERNEL_CLASSES = {"gemm": 0, "jacobi": 1, "qr": 2, "krp": 3, "ls": 4, "eigvals": 5, "tikhonov": 6}
 
 
 def kernel_timer(kind: str, enable: bool) -> None:

@@ -164,7 +164,9 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
 
 // Optional HIP-event timing of one kernel class (for live roofline numbers):
 // when enabled, launches of that class record an event pair on their stream.
-enum KernelClass : int { kKcGemm = 0, kKcJacobi = 1, kKcQr = 2, kKcKrp = 3, kKcLs = 4, kKcEigVals = 5, kKcCount = 6 };
+enum KernelClass : int {
+  kKcGemm = 0, kKcJacobi = 1, kKcQr = 2, kKcKrp = 3, kKcLs = 4, kKcEigVals = 5, kKcTikhonov = 6, kKcCount = 7
+};
 bool timer_on(int kind);
 void timer_begin(int kind, hipStream_t st, double flops = 0.0, double bytes = 0.0);
 void timer_end(int kind, hipStream_t st);

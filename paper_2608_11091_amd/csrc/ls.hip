@@ -317,10 +317,10 @@ __global__ __launch_bounds__(LS_NT) void ls_tikhonov_kernel(LsState S, int s, in
 
 void ls_tikhonov(const LsState& st_, int s, int kmax, int k, double conv_tol, double lam_fixed, hipStream_t st) {
   TK_CHECK(s <= LS_NT && kmax <= 64 && k < kmax, kErrUnsupported, "projected Tikhonov: sizes out of range");
-  timer_begin(kKcLs, st);
+  timer_begin(kKcTikhonov, st);
   hipLaunchKernelGGL(ls_tikhonov_kernel, dim3(1), dim3(LS_NT), 0, st, st_, s, kmax, k, conv_tol, lam_fixed);
   TK_LAUNCH_CHECK();
-  timer_end(kKcLs, st);
+  timer_end(kKcTikhonov, st);
 }
 
 void ls_init(const LsState& st_, int s, hipStream_t st) {

@@ -130,6 +130,53 @@ def noisy_blur_problem(n: int, seed: int = 5, noise: float = 0.05, sigma: float 
     return K, Y, (Xc, XU), rng
 
 
+def hollow_bars(n: int, nbars: int, rng):
+    """Tucker form of a phantom of ``nbars`` hollow axis-aligned bars (a
+    stand-in with the structure of the inverse-problem experiment's phantom):
+    each bar is an outer box minus an inner box, two rank-1 indicator tensors,
+    so the factors hold 2 * nbars indicator vectors per mode and the core is
+    superdiagonal with entries +1 (outer) and -1 (inner)."""
+    r = 2 * nbars
+    U = [np.zeros((n, r)) for _ in range(3)]
+    core = np.zeros((r,) * 3)
+    for b in range(nbars):
+        for k in range(3):
+            lo = int(rng.integers(n // 8, n // 2))
+            hi = int(rng.integers(lo + n // 4, min(n - n // 16, lo + 3 * n // 4)))
+            wall = max(2, (hi - lo) // 5)
+            U[k][lo:hi, 2 * b] = 1.0
+            U[k][lo + wall:hi - wall, 2 * b + 1] = 1.0
+        core[2 * b, 2 * b, 2 * b] = 1.0
+        core[2 * b + 1, 2 * b + 1, 2 * b + 1] = -1.0
+    return core, U
+
+
+def deblur_gcv_problem(n: int = 256, nbars: int = 3, rank_b: int = 32, noise: float = 0.05,
+                       sigma: float = 3.0, halfwidth: int = 12, seed: int = 3):
+    """Regularised deblurring workload (the setting of the inverse-problem
+    experiment: blur operator K (x) K (x) K, noisy data compressed to Tucker
+    format before the solve).  X_true: ``hollow_bars`` phantom; Y = X_true x_k K
+    plus white noise of relative level ``noise``; B = truncated HOSVD of Y to
+    rank (rank_b,)*3.  Returns (K, (B core, B factors), (X_true core,
+    factors)); cached on disk by its parameters."""
+    K = gaussian_blur_toeplitz(n, sigma=sigma, halfwidth=halfwidth)
+    key = f"deblur-gcv-v2-n{n}-b{nbars}-rb{rank_b}-e{noise}-s{sigma}-h{halfwidth}-seed{seed}"
+    path = _cache_path(key)
+    rng = np.random.default_rng(seed)
+    Xc, XU = hollow_bars(n, nbars, rng)
+    if os.path.exists(path):
+        z = np.load(path)
+        return K, (z["core"], [z["Q0"], z["Q1"], z["Q2"]]), (Xc, XU)
+    KU = [K @ U for U in XU]
+    Y = np.einsum("abc,ia,jb,kc->ijk", Xc, KU[0], KU[1], KU[2], optimize=True)
+    scale = noise * np.linalg.norm(Y) / np.sqrt(Y.size)
+    Y += scale * rng.standard_normal(Y.shape)
+    core, Q = _hosvd_truncate_dense(Y, [rank_b] * 3)
+    del Y
+    np.savez(path, core=core, Q0=Q[0], Q1=Q[1], Q2=Q[2])
+    return K, (core, Q), (Xc, XU)
+
+
 def draw_sketches(n: Sequence[int], s: int, cap: int, p: int, seed: int = 0):
     """Gaussian N(0,1) sketches from one seeded stream: S_1..S_d (n_k x s)
     then Omega_1..Omega_d (n_k x (cap+p))."""
