@@ -29,6 +29,10 @@ Parity status (see the pins in ``tests/test_oracle_*.py``):
     spectral application against the dense sum of matrix exponentials and
     against the dense inverse, and the flexible cycle against the dense
     solution).
+  * RHOSVD-Tucker GMRES, full Arnoldi (``oracle.gmres``): pinned (dense
+    textbook GMRES with exact RoundSums, the Arnoldi relation and
+    orthonormality of the basis, the Poisson closed form, lucky breakdown on
+    an eigentensor).
   * projected Tikhonov with GCV (``oracle.tikhonov``): pinned (the stacked
     least-squares solution, the influence-matrix definition of GCV, the
     closed-form minimiser for equal singular values, brute-force
@@ -44,12 +48,12 @@ from .tucker import (Tucker, to_dense, ttm, multi_ttm, unfold, apply_op, transpo
 from .roundsum import RoundParams, roundsum, effective_sketch_size, st_hosvd
 from .sgmres import SGMRESParams, sgmres_cycle, solve, sketched_lstsq
 from .adjoint import adjoint_gradients, loss_and_cotangent
-from . import mln, precond, tikhonov
+from . import gmres, mln, precond, tikhonov
 
 __all__ = [
     "Tucker", "to_dense", "ttm", "multi_ttm", "unfold", "apply_op", "transpose_terms",
     "dense_operator", "sketch_krp", "sketch_kron", "inner", "exact_norm", "block_dense",
     "scale", "RoundParams", "roundsum", "effective_sketch_size", "st_hosvd",
     "SGMRESParams", "sgmres_cycle", "solve", "sketched_lstsq", "adjoint_gradients",
-    "loss_and_cotangent", "mln", "precond", "tikhonov",
+    "loss_and_cotangent", "gmres", "mln", "precond", "tikhonov",
 ]

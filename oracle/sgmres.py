@@ -158,8 +158,10 @@ def _residual_blocks(terms, B: Tucker, X: Tucker, transpose=False):
 
 
 def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False,
-          x0: Optional[Tucker] = None, log: Optional[list] = None, precond=None):
-    """Restarted Tucker sGMRES with FP64 iterative refinement."""
+          x0: Optional[Tucker] = None, log: Optional[list] = None, precond=None, method: str = "sgmres"):
+    """Restarted Tucker sGMRES with FP64 iterative refinement.  ``method``
+    "gmres" runs full-Arnoldi cycles (Alg. 1, ``oracle.gmres``) inside the same
+    refinement loop; S is then unused."""
     t0 = time.perf_counter()
     eps_out = prm.eps_outer if prm.eps_outer is not None else 1e-2 * prm.tol
     rpo = RoundParams(eps=eps_out, cap=prm.cap, p=prm.p, force_s=prm.cap + prm.p)
@@ -182,8 +184,14 @@ def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False
             break
         cycles += 1
         tol_in = min(0.5, max(prm.tol * bnorm / rnorm, prm.tol_inner_floor))
-        d, info = sgmres_cycle(terms, r, S, Omega, prm, tol=tol_in, transpose=transpose,
-                               log=log, replay=rep, precond=precond)
+        if method == "gmres":
+            from .gmres import gmres_cycle
+            if precond is not None or prm.replay is not None:
+                raise ValueError("full-Arnoldi cycles take no preconditioner or rank replay")
+            d, info = gmres_cycle(terms, r, Omega, prm, tol=tol_in, transpose=transpose, log=log)
+        else:
+            d, info = sgmres_cycle(terms, r, S, Omega, prm, tol=tol_in, transpose=transpose,
+                                   log=log, replay=rep, precond=precond)
         iters += info["iters"]
         if x is None:
             x = d
