@@ -133,6 +133,13 @@ typedef struct {
    * GCV (see tsgmres_projected_tikhonov); the sketched residual and its
    * convergence test use that y_k.  0: plain sketched least squares. */
   int32_t tikhonov;
+  /* Cycle method: 0 = RHOSVD-Tucker sGMRES (Alg. 2: truncated Arnoldi
+   * window k_trunc, sketched least squares, stop at res_k < eta * tol);
+   * 1 = RHOSVD-Tucker GMRES (Alg. 1: full Arnoldi, every basis tensor in the
+   * orthogonalisation RoundSum, least squares on the Hessenberg matrix,
+   * stop at res_k < tol; S and s are not used and S may be NULL; no
+   * preconditioner).  Both run inside the same FP64 refinement loop. */
+  int32_t method;
 } tk_sgmres_params;
 
 /* Solver report (host memory owned by the caller). */

@@ -53,7 +53,7 @@ class TkSgmresParams(C.Structure):
                 ("oversample", C.c_int32), ("s", C.c_int64), ("eps_trunc", C.c_double), ("eps_min", C.c_double),
                 ("tol_inner_floor", C.c_double), ("x0", C.POINTER(TkTucker)), ("precond_q", C.c_int32),
                 ("precond_V", C.POINTER(C.c_void_p)), ("precond_lambda", C.POINTER(C.c_void_p)),
-                ("tikhonov", C.c_int32)]
+                ("tikhonov", C.c_int32), ("method", C.c_int32)]
 
 
 class TkMlnParams(C.Structure):

@@ -254,6 +254,9 @@ class SolveParams:
     precond: Optional[Tuple[list, list]] = None
     # projected Tikhonov with GCV on the sketched least squares (Sec. 4.3)
     tikhonov: bool = False
+    # 0: RHOSVD-Tucker sGMRES cycles (Alg. 2); 1: RHOSVD-Tucker GMRES, full
+    # Arnoldi (Alg. 1), which takes no sketch S (pass None)
+    method: int = 0
 
     def struct(self, s: int, x0: Optional[Tucker] = None):
         p = TkSgmresParams()
@@ -261,6 +264,7 @@ class SolveParams:
         p.k_trunc, p.rank_cap, p.oversample, p.s = self.k_trunc, self.rank_cap, self.oversample, s
         p.eps_trunc, p.eps_min, p.tol_inner_floor = self.eps_trunc, self.eps_min, self.tol_inner_floor
         p.tikhonov = int(self.tikhonov)
+        p.method = int(self.method)
         keep = []
         if x0 is not None:
             xs = x0.struct()
@@ -324,11 +328,12 @@ def _hist_cap(prm: SolveParams) -> int:
 
 
 def solve(op: KronOp, b: Tucker, S, omega, prm: SolveParams, x0: Optional[Tucker] = None, workspace=None):
-    """Restarted Tucker sGMRES; returns ``(x, info)``."""
+    """Restarted Tucker sGMRES (or full-Arnoldi GMRES with ``prm.method`` 1,
+    where ``S`` may be None); returns ``(x, info)``."""
     lib = _abi.load()
     ops, k1 = op.struct(b.n)
     bst = b.struct()
-    s = int(S[0].shape[0])
+    s = int(S[0].shape[0]) if S is not None else 0
     ps, k2 = prm.struct(s, x0)
     nb = C.c_size_t()
     check(lib.tsgmres_solve_workspace(C.byref(ops), C.byref(bst), C.byref(ps), C.byref(nb)))
@@ -336,7 +341,8 @@ def solve(op: KronOp, b: Tucker, S, omega, prm: SolveParams, x0: Optional[Tucker
     x = Tucker.empty(b.n, (prm.rank_cap,) * b.d, b.core.device)
     xs = x.struct()
     info, keep = _info(_hist_cap(prm))
-    check(lib.tsgmres_solve(C.byref(ops), C.byref(bst), C.byref(ps), _ptr_array(S), _ptr_array(omega), C.byref(xs),
+    check(lib.tsgmres_solve(C.byref(ops), C.byref(bst), C.byref(ps), _ptr_array(S) if S is not None else None,
+                            _ptr_array(omega), C.byref(xs),
                             C.byref(info), C.c_void_p(ws.data_ptr()), nb.value, _stream()))
     x.ranks = tuple(int(xs.r[k]) for k in range(b.d))
     return x, _info_dict(info, keep, b.d)

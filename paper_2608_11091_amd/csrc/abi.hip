@@ -343,6 +343,7 @@ SolveCfg solve_cfg(const tk_sgmres_params* prm) {
   c.eps_min = prm->eps_min;
   c.tol_inner_floor = prm->tol_inner_floor;
   c.tikhonov = prm->tikhonov != 0;
+  c.method = prm->method;
   return c;
 }
 
@@ -355,7 +356,11 @@ void check_params(const tk_sgmres_params* prm) {
   TK_CHECK(prm->k_trunc >= 1, kErrInvalidArg, "k_trunc must be >= 1");
   TK_CHECK(prm->rank_cap >= 1 && prm->oversample >= 0 && prm->rank_cap + prm->oversample <= 64, kErrUnsupported,
            "rank_cap + oversample must be in [1, 64]");
-  TK_CHECK(prm->s >= prm->maxiter && prm->s <= 256, kErrUnsupported, "sketch size must be in [maxiter, 256]");
+  TK_CHECK(prm->method == 0 || prm->method == 1, kErrInvalidArg, "method must be 0 (sGMRES) or 1 (GMRES)");
+  TK_CHECK(prm->method == 1 || (prm->s >= prm->maxiter && prm->s <= 256), kErrUnsupported,
+           "sketch size must be in [maxiter, 256]");
+  TK_CHECK(prm->method == 0 || prm->precond_q == 0, kErrUnsupported,
+           "the preconditioner runs with the sketched cycles only (method 0)");
   TK_CHECK(prm->precond_q >= 0 && prm->precond_q <= 400, kErrInvalidArg, "precond_q must be in [0, 400]");
   TK_CHECK(prm->precond_q == 0 || (prm->precond_V != nullptr && prm->precond_lambda != nullptr), kErrInvalidArg,
            "preconditioner eigenpairs missing");
@@ -412,7 +417,7 @@ int do_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* p
   check_op(op, b->d, b->n);
   check_tucker(b, "b", b->d, b->n);
   check_params(prm);
-  TK_CHECK(S != nullptr && omega != nullptr, kErrInvalidArg, "sketch matrices missing");
+  TK_CHECK((S != nullptr || prm->method == 1) && omega != nullptr, kErrInvalidArg, "sketch matrices missing");
   const int d = b->d;
   int rc = prm->rank_cap;
   for (int k = 0; k < d; ++k) rc = std::max<int>(rc, int(b->r[k]));
@@ -432,7 +437,7 @@ int do_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* p
   }
   std::array<const double*, kMaxD> Sk{}, Ok{};
   for (int k = 0; k < d; ++k) {
-    Sk[k] = S[k];
+    Sk[k] = S ? S[k] : nullptr;
     Ok[k] = omega[k];
   }
   auto solver = make_solver(ar, sh, op_dev(op), bi, solve_cfg(prm), Sk, Ok, prm->x0 ? &x0i : nullptr, st,
@@ -458,6 +463,7 @@ int do_backward(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xb
   check_tucker(x, "x", x->d, x->n);
   TK_CHECK(prm == nullptr || prm->tikhonov == 0, kErrUnsupported,
            "the adjoint gradients assume an unregularised solve (tikhonov must be 0)");
+  TK_CHECK(prm == nullptr || prm->method == 0, kErrUnsupported, "the adjoint solve runs sGMRES cycles (method 0)");
   check_params(prm);
   TK_CHECK(S != nullptr && omega != nullptr, kErrInvalidArg, "sketch matrices missing");
   const int d = x->d;

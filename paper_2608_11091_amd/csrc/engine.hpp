@@ -254,6 +254,7 @@ struct SolveCfg {
   double eps_trunc = -1, eps_min = -1, tol_inner_floor = -1;
   bool transpose = false;
   bool tikhonov = false;  // projected Tikhonov with GCV on the sketched least squares
+  int method = 0;         // 0: sketched GMRES cycles (Alg. 2); 1: full Arnoldi (Alg. 1)
 };
 
 struct SolveInfo {

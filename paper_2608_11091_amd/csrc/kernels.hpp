@@ -202,6 +202,10 @@ void ints_at_least(const int* src, int* dst, int n, int lo, hipStream_t st);
 void copy_ints(const int* src, int* dst, int n, hipStream_t st);
 // dst[i] = sqrt(src[i]) for i < n.
 void vec_sqrt(const double* src, double* dst, int n, hipStream_t st);
+// col[0..nh) = h, col[nh] = sqrt(*norm2), zeros up to len (a Hessenberg column).
+void hess_column(const double* h, int nh, const double* norm2, double* col, int len, hipStream_t st);
+// v = (*beta) e_1, length len.
+void scaled_unit(const double* beta, double* v, int len, hipStream_t st);
 // Per-iteration status: omega = sqrt(sumsq[1]), ||W|| = sqrt(sumsq[0]); breakdown when
 // omega <= bd_tol * ||W||; packs LS flags, residual and the ranks of the new basis tensor.
 struct IterStatus {

@@ -142,6 +142,19 @@ __global__ void vec_sqrt_kernel(const double* src, double* dst, int n) {
   if (i < n) dst[i] = sqrt(src[i]);
 }
 
+// Column k of the Arnoldi Hessenberg matrix (Alg. 1): h_0..h_k, then
+// h_{k+1,k} = sqrt(norm2), then zeros up to len.
+__global__ void hess_column_kernel(const double* h, int nh, const double* norm2, double* col, int len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) col[i] = i < nh ? h[i] : (i == nh ? sqrt(fmax(*norm2, 0.0)) : 0.0);
+}
+
+// v = (*beta) e_1 of length len.
+__global__ void scaled_unit_kernel(const double* beta, double* v, int len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) v[i] = i == 0 ? *beta : 0.0;
+}
+
 __global__ void iter_status_kernel(const double* sumsq2, const int* ls_flags, const double* res_k, const int* rank,
                                    int d, double bd_tol, double* omega, IterStatus* out) {
   if (threadIdx.x != 0) return;
@@ -279,6 +292,16 @@ void copy_ints(const int* src, int* dst, int n, hipStream_t st) {
 
 void vec_sqrt(const double* src, double* dst, int n, hipStream_t st) {
   hipLaunchKernelGGL(vec_sqrt_kernel, dim3(1), dim3(64), 0, st, src, dst, n);
+  TK_LAUNCH_CHECK();
+}
+
+void hess_column(const double* h, int nh, const double* norm2, double* col, int len, hipStream_t st) {
+  hipLaunchKernelGGL(hess_column_kernel, dim3(ceil_div(len, 64)), dim3(64), 0, st, h, nh, norm2, col, len);
+  TK_LAUNCH_CHECK();
+}
+
+void scaled_unit(const double* beta, double* v, int len, hipStream_t st) {
+  hipLaunchKernelGGL(scaled_unit_kernel, dim3(ceil_div(len, 64)), dim3(64), 0, st, beta, v, len);
   TK_LAUNCH_CHECK();
 }
 

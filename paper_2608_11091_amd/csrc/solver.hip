@@ -52,6 +52,11 @@ struct Cycle {
   Shape sh;
   int maxiter = 60, kt = 2, s = 120;
   bool tikhonov = false;
+  // Full Arnoldi (Alg. 1): the window holds every basis tensor and the least
+  // squares run on the Hessenberg columns (h, ||W||) against beta e_1 instead
+  // of the sketches; the cycle stops at res_k < tol.
+  bool full = false;
+  int ls_rows = 0;  // rows of the least-squares problem: s, or maxiter + 1
   TT<T> rhs, W, dsol;
   std::vector<TT<T>> V;
   std::vector<TT<T>> Z;  // preconditioned basis (flexible cycle), when pc.q > 0
@@ -88,20 +93,23 @@ struct Cycle {
     for (int k = 0; k <= maxiter; ++k) V.push_back(alloc_tt<T>(ar, sh));
     if (flexible)
       for (int k = 0; k < maxiter; ++k) Z.push_back(alloc_tt<T>(ar, sh));
+    if (full) kt = maxiter;
+    ls_rows = full ? maxiter + 1 : s;
+    const int lr = ls_rows;
     eps_pair = ar.alloc<double>(2);
     beta2 = ar.alloc<double>(1);
     beta = ar.alloc<double>(1);
-    bs = ar.alloc<double>(s);
+    bs = ar.alloc<double>(lr);
     bsn2 = ar.alloc<double>(1);
     bsn = ar.alloc<double>(1);
-    Mcols = ar.alloc<double>(size_t(s) * maxiter);
+    Mcols = ar.alloc<double>(size_t(lr) * maxiter);
     h = ar.alloc<double>(size_t(maxiter) * kt);
     sumsq2 = ar.alloc<double>(size_t(maxiter) * 2);
     omega = ar.alloc<double>(maxiter);
-    Hv = ar.alloc<double>(size_t(s) * maxiter);
+    Hv = ar.alloc<double>(size_t(lr) * maxiter);
     tau = ar.alloc<double>(maxiter);
     R = ar.alloc<double>(size_t(maxiter) * maxiter);
-    qtb = ar.alloc<double>(s);
+    qtb = ar.alloc<double>(lr);
     y = ar.alloc<double>(maxiter);
     res = ar.alloc<double>(maxiter);
     nrmM2 = ar.alloc<double>(1);
@@ -127,10 +135,17 @@ struct Cycle {
         vec_sqrt(beta2, beta, 1, st);
       });
       emit_copy_tt<T>(setup, sh, rhs, V[0], 1.0, beta);
-      Blocks<T> bb;
-      bb.add(rhs, nullptr, 1.0);
-      plan_sketch<T>(setup, pl, sh, bb, S, s, bs);
-      const int ss = s;
+      if (full) {
+        // Hessenberg right-hand side beta e_1
+        double* bsv = bs;
+        const double* be = beta;
+        setup.steps.push_back([=](hipStream_t st) { scaled_unit(be, bsv, lr, st); });
+      } else {
+        Blocks<T> bb;
+        bb.add(rhs, nullptr, 1.0);
+        plan_sketch<T>(setup, pl, sh, bb, S, s, bs);
+      }
+      const int ss = lr;
       double* n2 = bsn2;
       double* n1 = bsn;
       LsState lsv = ls;
@@ -163,7 +178,7 @@ struct Cycle {
       plan_roundsum<T>(q, pl, sh, LV, rcfg, omega_, W, nullptr);
       Blocks<T> wb;
       wb.add(W, nullptr, 1.0);
-      plan_sketch<T>(q, pl, sh, wb, S, s, Mcols + size_t(k) * s);
+      if (!full) plan_sketch<T>(q, pl, sh, wb, S, s, Mcols + size_t(k) * s);
       const int j0 = std::max(0, k - kt + 1);
       std::vector<TT<T>> win(V.begin() + j0, V.begin() + k + 1);
       double* hk = h + size_t(k) * kt;
@@ -180,15 +195,18 @@ struct Cycle {
       const double* resk = res + k;
       const int* rk = V[k + 1].rank;
       T* vc = V[k + 1].core;
-      const int ss = s, mx = maxiter;
+      const int ss = lr, mx = maxiter;
       LsState lsv = ls;
       const double* ctol = &conv_tol;
       const double bdt = bd_tol;
       IterStatus* sd = st_dev;
       int* fl = flags;
-      const bool tik = tikhonov;
+      const bool tik = tikhonov, fa = full;
+      double* hcol = Mcols + size_t(k) * lr;
       q.steps.push_back([=](hipStream_t st) {
         dot_batched<T>(bl->at<const T*>(off), bl->at<const T*>(off), cl, 2, 1.0, s2, st);
+        // Alg. 1: Hessenberg column (h_{1..k}, ||W||) in place of the sketch
+        if (fa) hess_column(hk, k + 1, s2 + 1, hcol, ss, st);
         ls_add_column(lsv, ss, mx, k, *ctol, bdt, st);
         // regularised y_k and residual (Sec. 4.3); the breakdown test keeps
         // the unregularised R factor
@@ -212,7 +230,7 @@ struct Cycle {
   std::pair<int, int> run(hipStream_t st, double eps, double tol_in, double eta, SolveInfo& info) {
     const double ep[2] = {eps, eps};
     TK_HIP(hipMemcpyAsync(eps_pair, ep, sizeof(ep), hipMemcpyHostToDevice, st));
-    conv_tol = eta * tol_in;
+    conv_tol = (full ? 1.0 : eta) * tol_in;
     setup.run(st);
     int status = kNotConverged, kend = maxiter;
     for (int k = 0; k < maxiter; ++k) {
@@ -284,7 +302,11 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
   const int d = sh.d;
   TK_CHECK(cfg.maxiter >= 1 && cfg.maxiter <= 64, kErrInvalidArg, "maxiter must be in [1, 64]");
   TK_CHECK(cfg.k_trunc >= 1, kErrInvalidArg, "k_trunc must be >= 1");
-  TK_CHECK(cfg.s >= cfg.maxiter && cfg.s <= 256, kErrInvalidArg, "sketch size must be in [maxiter, 256]");
+  TK_CHECK(cfg.method == 0 || cfg.method == 1, kErrInvalidArg, "method must be 0 (sGMRES) or 1 (GMRES)");
+  TK_CHECK(cfg.method == 1 || (cfg.s >= cfg.maxiter && cfg.s <= 256), kErrInvalidArg,
+           "sketch size must be in [maxiter, 256]");
+  TK_CHECK(cfg.method == 0 || precond.q == 0, kErrUnsupported,
+           "the preconditioner runs with the sketched cycles only (method 0)");
   s.bo = alloc_tt<double>(ar, sh);
   s.x[0] = alloc_tt<double>(ar, sh);
   s.x[1] = alloc_tt<double>(ar, sh);
@@ -341,6 +363,7 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
     c.kt = cfg.k_trunc;
     c.s = cfg.s;
     c.tikhonov = cfg.tikhonov;
+    c.full = cfg.method == 1;
     c.plan(pl, op, cfg.transpose, S, omega, precond);
     s.r = c.rhs;     // the cycle reads its right-hand side in place
     s.d64 = c.dsol;  // and leaves its solution in place
@@ -363,14 +386,15 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
         s.op32.A.push_back(A ? to32(A, size_t(sh.n[k]) * sh.n[k]) : nullptr);
       }
     std::array<const float*, kMaxD> S32{}, O32{};
+    const bool sketched = cfg.method == 0;  // full Arnoldi reads no sketch S
     for (int k = 0; k < d; ++k) {
       const double* src_s = S[k];
       const double* src_o = omega[k];
-      const size_t ls = size_t(sh.n[k]) * cfg.s, lo = size_t(sh.n[k]) * sh.sc();
-      float* ds = ar.alloc<float>(ls);
+      const size_t ls = sketched ? size_t(sh.n[k]) * cfg.s : 0, lo = size_t(sh.n[k]) * sh.sc();
+      float* ds = sketched ? ar.alloc<float>(ls) : nullptr;
       float* dom = ar.alloc<float>(lo);
       s.s_setup.steps.push_back([=](hipStream_t st) {
-        cast_copy<double, float>(src_s, ds, ls, st);
+        if (ls) cast_copy<double, float>(src_s, ds, ls, st);
         cast_copy<double, float>(src_o, dom, lo, st);
       });
       S32[k] = ds;
@@ -391,6 +415,7 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
     c.kt = cfg.k_trunc;
     c.s = cfg.s;
     c.tikhonov = cfg.tikhonov;
+    c.full = cfg.method == 1;
     c.bd_tol = 1e-6;
     c.plan(pl, s.op32, cfg.transpose, S32, O32, pc32);
     s.r = alloc_tt<double>(ar, sh);
