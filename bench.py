@@ -62,7 +62,7 @@ TRAFFIC = {
                    sources={"paper_2608_11091_amd/csrc/eig.hip":
                             "ed3dda42d480fa733f8f2c2b4fd0c8cfcaa07a08b9e2074312b6510f2b47fe84",
                             "paper_2608_11091_amd/csrc/common.hpp":
-                            "4c69bc4b5fa7702b065187f8a03356bf28eea6a4eb39b7ef47949b76efcf3b1c"},
+                            "af5e847ac6721fe9377fb2e2d663dbfa81b5ba58d44b4087ccc09f43dc299c71"},
                    profile="profiles/jacobi_vec_traffic_deblur3d_n512.md"),
 }
 
