@@ -179,7 +179,10 @@ int tucker_rhosvd_workspace(const tk_block_sum* in, const tk_round_params* prm, 
 
 /* Restarted RHOSVD-Tucker sGMRES (Alg. 2 cycles wrapped in FP64 iterative
  * refinement): solves L(X) = B to relative residual tol.  Returns the status
- * (TK_OK / TK_NOT_CONVERGED / TK_BREAKDOWN / TK_RANK_FLOOR) or an error. */
+ * (TK_OK / TK_NOT_CONVERGED / TK_BREAKDOWN / TK_RANK_FLOOR) or an error.
+ * Without convergence x is the iterate with the smallest true residual (an
+ * initial guess included) and info->true_relres is that residual;
+ * info->hist_true keeps every cycle's. */
 int tsgmres_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* prm, const double* const* S,
                   const double* const* omega, tk_tucker* x, tk_sgmres_info* info, void* ws, size_t ws_bytes,
                   void* stream);

@@ -24,7 +24,10 @@ x_0 = 0, r_0 = B; per cycle solve L d = r_c to relative tolerance
 ``tol ||B|| / ||r_c||`` (floored), ``x <- RoundSum(x + d)``, then the exact FP64
 residual ``||B - L(x)|| / ||B||`` (QR of concatenated factors) decides;
 ``r_{c+1} = RoundSum(B - L(x))``.  Two cycles in a row that reduce the true
-residual by less than 10% stop the solve with a rank-floor status.  These
+residual by less than 10% stop the solve with a rank-floor status.  A solve
+that stops without converging returns the iterate with the smallest true
+residual (cycles on a rank floor can raise it: x + d is rounded back to the
+rank cap).  These
 outer RoundSums use the full sketch width cap + p: the effective-rank rule of
 Sec. 3.1 sizes the sketch from the weighted factor Gram, where a correction d
 far smaller than x (or a residual far smaller than B and L(x)) sits below the
@@ -178,6 +181,7 @@ def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False
         r, _ = roundsum(Rb, Omega, rep.next(rpo))
     true_hist, iters, status = [], 0, NOT_CONVERGED
     cycles = 0
+    best = (rnorm, x) if x is not None else (np.inf, None)
     for c in range(prm.max_restarts):
         if rnorm <= prm.tol * bnorm:
             status = OK
@@ -200,6 +204,8 @@ def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False
         Rb = _residual_blocks(terms, B, x, transpose)
         rnorm = exact_norm(Rb)
         true_hist.append(rnorm / bnorm)
+        if rnorm < best[0]:
+            best = (rnorm, x)
         if rnorm <= prm.tol * bnorm:
             status = OK
             break
@@ -207,8 +213,9 @@ def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False
             status = RANK_FLOOR
             break
         r, _ = roundsum(Rb, Omega, rep.next(rpo))
+    if status != OK and best[1] is not None and best[0] < rnorm:
+        rnorm, x = best
     if x is None:
         x = Tucker(np.zeros((1,) * B.d), [np.eye(nk, 1) for nk in B.n])
     return x, dict(status=status, iters=iters, cycles=cycles, true_hist=true_hist,
-                   true_relres=true_hist[-1] if true_hist else rnorm / bnorm,
-                   seconds=time.perf_counter() - t0)
+                   true_relres=rnorm / bnorm if bnorm > 0 else 0.0, seconds=time.perf_counter() - t0)

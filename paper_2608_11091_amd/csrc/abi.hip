@@ -502,10 +502,10 @@ int do_backward(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xb
   scfg.transpose = true;
   OpDev<double> od = op_dev(op);
   auto solver = make_solver(ar, sh, od, xbr, scfg, Sk, Ok, nullptr, st, precond_of(prm, d));
-  // gradient contractions, planned for both solution slots of the solver
+  // gradient contractions, planned for every solution slot of the solver
   double* dal = ar.alloc<double>(op->nterms);
-  Seq grad[2];
-  for (int slot = 0; slot < 2; ++slot) {
+  Seq grad[3];
+  for (int slot = 0; slot < 3; ++slot) {
     const TT<double> lam = solver_slot(*solver, slot);
     Seq& q = grad[slot];
     Blocks<double> lx = plan_apply<double>(q, pl, sh, od, xi, false);

@@ -277,7 +277,7 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
                                     hipStream_t st, const PrecondT<double>& precond = PrecondT<double>{});
 void solver_run(Solver& s, TT<double>& x_out, SolveInfo& info, hipStream_t st);
 TT<double> solver_solution(Solver& s);
-TT<double> solver_slot(Solver& s, int i);  // the two buffers the solution alternates between
+TT<double> solver_slot(Solver& s, int i);  // 0, 1: the buffers the iterate alternates between; 2: best iterate
 int solver_slot_index(Solver& s);           // slot holding the solution after solver_run
 
 }  // namespace tk

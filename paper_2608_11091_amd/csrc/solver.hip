@@ -6,9 +6,11 @@
 // one small status record back to the host, which decides whether to stop.
 // The outer loop is FP64: x <- RoundSum(x + d), the exact residual norm via
 // QR of concatenated factors, and RoundSum(B - L(x)) as the next right-hand
-// side.
+// side.  A solve that stops without converging returns the iterate with the
+// smallest true residual.
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <map>
 
 #include "engine.hpp"
@@ -272,11 +274,12 @@ class Solver {
   Blob blob;
   OpDev<double> op64;
   OpDev<float> op32;
-  TT<double> b_in, bo, x[2], r, d64;
+  // x[0], x[1]: the iterate alternates between them; x[2]: best iterate so far
+  TT<double> b_in, bo, x[3], r, d64;
   bool have_x0 = false;
   std::unique_ptr<Cycle<double>> c64;
   std::unique_ptr<Cycle<float>> c32;
-  Seq s_setup, s_x0, s_to_cycle, s_from_cycle, s_first_x, s_xupd[2], s_rnorm[2], s_rround[2];
+  Seq s_setup, s_x0, s_to_cycle, s_from_cycle, s_first_x, s_xupd[2], s_rnorm[2], s_rround[2], s_keep[2];
   double *bnorm2, *rnorm2;
   double* host2 = nullptr;  // pinned scratch
   int xc = 0;
@@ -310,6 +313,7 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
   s.bo = alloc_tt<double>(ar, sh);
   s.x[0] = alloc_tt<double>(ar, sh);
   s.x[1] = alloc_tt<double>(ar, sh);
+  s.x[2] = alloc_tt<double>(ar, sh);
   s.bnorm2 = ar.alloc<double>(1);
   s.rnorm2 = ar.alloc<double>(1);
   if (!ar.measuring()) TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&s.host2), 2 * sizeof(double), 0));
@@ -452,6 +456,7 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
     for (int j = 0; j < lx.size(); ++j) rb.add(lx.core[j], lx.U[j], lx.rank[j], nullptr, -lx.cscale[j]);
     plan_exact_norm2(s.s_rnorm[c], pl, sh, rb, s.rnorm2);
     plan_roundsum<double>(s.s_rround[c], pl, sh, rb, outer, omega, s.r, nullptr);
+    emit_copy_tt<double>(s.s_keep[c], sh, s.x[c], s.x[2]);
   }
   // upload the tables
   s.blob.dev = ar.alloc<unsigned char>(std::max<size_t>(s.blob.host.size(), 16));
@@ -478,11 +483,17 @@ void solver_run(Solver& s, TT<double>& x_out, SolveInfo& info, hipStream_t st) {
   s.xc = 0;
   bool have_x = false;
   double rnorm = bnorm;
+  // best iterate: refinement cycles on a rank floor can raise the residual
+  // (x + d rounded back to the rank cap), so a solve that does not converge
+  // returns the iterate with the smallest true residual
+  double best = std::numeric_limits<double>::infinity();
   if (s.have_x0) {
     s.s_x0.run(st);
     have_x = true;
     s.s_rnorm[0].run(st);
     rnorm = std::sqrt(read_scalar(s, s.rnorm2, st));
+    s.s_keep[0].run(st);
+    best = rnorm;
     s.s_rround[0].run(st);
   }
   int status = kNotConverged;
@@ -514,6 +525,10 @@ void solver_run(Solver& s, TT<double>& x_out, SolveInfo& info, hipStream_t st) {
     s.s_rnorm[s.xc].run(st);
     rnorm = std::sqrt(read_scalar(s, s.rnorm2, st));
     if (!std::isfinite(rnorm)) throw Error{kErrNonFinite, "non-finite residual norm"};
+    if (rnorm < best) {
+      best = rnorm;
+      s.s_keep[s.xc].run(st);
+    }
     info.hist_true.push_back(rnorm / bnorm);
     info.hist_time.push_back(std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     if (rnorm <= cfg.tol * bnorm) {
@@ -543,15 +558,19 @@ void solver_run(Solver& s, TT<double>& x_out, SolveInfo& info, hipStream_t st) {
     TK_HIP(hipStreamSynchronize(st));
     s.xc = 0;
   }
+  if (status != kOk && have_x && best < rnorm) {
+    s.xc = 2;
+    rnorm = best;
+  }
   x_out = s.x[s.xc];
   info.status = status;
-  info.true_relres = info.hist_true.empty() ? rnorm / (bnorm > 0 ? bnorm : 1.0) : info.hist_true.back();
+  info.true_relres = rnorm / (bnorm > 0 ? bnorm : 1.0);
   TK_HIP(hipStreamSynchronize(st));
   info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 TT<double> solver_solution(Solver& s) { return s.x[s.xc]; }
-TT<double> solver_slot(Solver& s, int i) { return s.x[i]; }
+TT<double> solver_slot(Solver& s, int i) { return s.x[i]; }  // i in [0, 3)
 int solver_slot_index(Solver& s) { return s.xc; }
 
 template struct Cycle<double>;

@@ -216,3 +216,58 @@ def test_gradient_central_differences(tk):
         tm[k] -= h
         fd = (loss(tp)[0] - loss(tm)[0]) / (2 * h)
         assert abs(dalpha[k] - fd) <= 1e-4 * abs(fd), (k, dalpha[k], fd)
+
+
+def test_gradient_central_differences_fullsize_preconditioned(tk):
+    # The differentiation workload at its full size (n = 256, rank cap 32):
+    # unpreconditioned the method does not converge there, so the forward and
+    # adjoint solves use the exponential-sum preconditioner (Sec. 3.4) built on
+    # the eigenpairs of each mode's theta_k L (the DST-I basis, eigenvalues
+    # scaled by theta_k).  Asked for 1e-12 (which also tightens the truncation
+    # tolerances), the forward solve stops at the rank cap's floor, below
+    # 1e-10.  The adjoint right-hand side x - x_target has high multilinear
+    # rank (the target's factors are Gaussian), so the adjoint solve floors
+    # at 5.7e-3 at rank cap 32 (gradient errors up to 1.5e-3) and at 1.8e-3 at
+    # cap 48 (errors up to 1.5e-4): the adjoint runs at cap 48.  The adjoint
+    # gradient dL/dtheta_k against central differences at h = 1e-6, whose
+    # solver noise (~ ||x - x_target|| 1e-10 ||x|| / h) is below 1e-4 of
+    # |dL/dtheta_k|; the bound is 1e-3.
+    from workloads import make_config
+    w = make_config(4)
+    n = w.n[0]
+    theta = np.array(w.extra["theta"], dtype=float)
+    L = w.extra["L"]
+    Xt = O.Tucker(w.extra["x_target_core"], w.extra["x_target_factors"])
+    xt = _gpu(tk, Xt)
+    S = [_cm(s) for s in w.S]
+    Om = [_cm(o) for o in w.Omega]
+    b = tk.Tucker.from_numpy(w.b_core, w.b_factors, rcap=(w.cap,) * 3)
+    Vs, lams = tk.laplacian_precond((n,) * 3)
+
+    def prm_of(th, cap):
+        return tk.SolveParams(form=0, tol=1e-12, eta=w.eta, maxiter=40, max_restarts=4, k_trunc=w.k_trunc,
+                              rank_cap=cap, oversample=w.p, precond_q=49,
+                              precond=(Vs, [l * float(th[k]) for k, l in enumerate(lams)]))
+
+    def terms_of(th):
+        return [(float(th[k]), [L if j == k else None for j in range(3)]) for k in range(3)]
+
+    def loss(th):
+        x, info = tk.solve(tk.KronOp.from_terms(terms_of(th)), b, S, Om, prm_of(th, w.cap))
+        assert info["true_relres"] <= 1e-10, info["true_hist"]
+        return 0.5 * tk.norm([(1.0, x), (-1.0, xt)]) ** 2, x
+
+    l0, x0 = loss(theta)
+    op = tk.KronOp.from_terms(terms_of(theta))
+    _, dalpha, _, binfo = tk.backward(op, x0, [(1.0, x0), (-1.0, xt)], S, Om, prm_of(theta, 48), want_dA=False)
+    print(f"full-size gradient: loss {l0:.6e}, adjoint {binfo['status_name']} true {binfo['true_relres']:.2e}, "
+          f"dL/dtheta {dalpha}", flush=True)
+    assert binfo["true_relres"] <= 5e-3
+    h = 1e-6
+    for k in range(3):
+        tp, tm = theta.copy(), theta.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (loss(tp)[0] - loss(tm)[0]) / (2 * h)
+        print(f"  k={k}: adjoint {dalpha[k]:.8e} central difference {fd:.8e}", flush=True)
+        assert abs(dalpha[k] - fd) <= 1e-3 * abs(fd), (k, dalpha[k], fd)

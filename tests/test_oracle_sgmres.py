@@ -156,3 +156,8 @@ def test_rank_floor_is_reported():
     X, info = O.solve(w.terms, B, w.S, w.Omega, prm)
     assert info["status"] == RANK_FLOOR
     assert 1e-8 < info["true_relres"] < 1.0
+    # without convergence the solve returns its best iterate, and reports
+    # that iterate's residual (evaluated here independently)
+    assert info["true_relres"] == min(info["true_hist"])
+    rel = O.exact_norm([(1.0, B)] + [(-c, T) for c, T in O.apply_op(w.terms, X)]) / O.exact_norm([(1.0, B)])
+    assert abs(rel - info["true_relres"]) <= 1e-12
