@@ -318,7 +318,7 @@ def main():
     ap.add_argument("--mln-cpu-iters", type=int, default=20)
     ap.add_argument("--no-precond", action="store_true", help="skip the preconditioned Laplacian measurement")
     ap.add_argument("--precond-n", type=int, default=512)
-    ap.add_argument("--precond-cap", type=int, default=32)
+    ap.add_argument("--precond-cap", type=int, default=48)
     ap.add_argument("--precond-q", type=int, default=49)
     ap.add_argument("--no-gmres", action="store_true", help="skip the full-Arnoldi GMRES (Alg. 1) measurement")
     ap.add_argument("--gmres-only", action="store_true", help="run only the full-Arnoldi GMRES measurement")
