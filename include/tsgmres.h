@@ -52,9 +52,11 @@ extern "C" {
 
 /* status codes */
 #define TK_OK 0
-#define TK_NOT_CONVERGED 1   /* x is the last iterate */
+#define TK_NOT_CONVERGED 1   /* tsgmres_solve: x is the iterate with the smallest true residual;
+                                tsgmres_mln_solve: x is the last iterate */
 #define TK_BREAKDOWN 2       /* exact solution in the Krylov space (lucky breakdown) */
-#define TK_RANK_FLOOR 3      /* two cycles in a row reduced the true residual by < 10% */
+#define TK_RANK_FLOOR 3      /* two cycles in a row reduced the true residual by < 10%
+                                (x: the iterate with the smallest true residual) */
 #define TK_ERR_INVALID_ARG -1
 #define TK_ERR_SHAPE -2
 #define TK_ERR_CAPACITY -3    /* an output rank exceeds the caller's capacity */
