@@ -122,6 +122,17 @@ constexpr double kGcvDecades = 12.0;
 constexpr int kGcvGolden = 60;
 constexpr int kJacobiSweeps = 60;
 
+// Sum over each aligned group of 8 lanes (all lanes active): quad_perm
+// [1,0,3,2] and [2,3,0,1] give every lane its quad's sum, row_half_mirror
+// (lane j <-> 7 - j within 8) adds the other quad's; every lane of the group
+// ends with the same total.
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  return v;
+}
+
 __device__ __forceinline__ double gcv_g(double s2, double l2) {
   const double den = s2 + l2;
   return den > 0.0 ? l2 / den : 1.0;
@@ -172,11 +183,9 @@ __global__ __launch_bounds__(LS_NT) void ls_tikhonov_kernel(LsState S, int s, in
           b = fma(y, y, b);
           c = fma(x, y, c);
         }
-      for (int o = 1; o < 8; o <<= 1) {
-        a += __shfl_xor(a, o, 64);
-        b += __shfl_xor(b, o, 64);
-        c += __shfl_xor(c, o, 64);
-      }
+      a = group8_sum(a);
+      b = group8_sum(b);
+      c = group8_sum(c);
       if (act && fabs(c) > jtol * sqrt(a) * sqrt(b)) {
         const double zeta = (b - a) / (2.0 * c);
         const double az = fabs(zeta);
