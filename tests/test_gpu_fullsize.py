@@ -271,3 +271,71 @@ def test_gradient_central_differences_fullsize_preconditioned(tk):
         fd = (loss(tp)[0] - loss(tm)[0]) / (2 * h)
         print(f"  k={k}: adjoint {dalpha[k]:.8e} central difference {fd:.8e}", flush=True)
         assert abs(dalpha[k] - fd) <= 1e-3 * abs(fd), (k, dalpha[k], fd)
+
+
+def test_fullsize_gmres_cycle(tk):
+    # RHOSVD-Tucker GMRES (Alg. 1) on the deblurring workload at n = 512,
+    # rank cap 48 (the benchmark's full-Arnoldi leg), one cycle of 16
+    # iterations: equal iteration count and per-iteration ranks, Hessenberg
+    # residual histories within the FP64 parity bound 1e-10 (fractions of
+    # ||B||), and the true residuals of the two cycle solutions within 1e-10.
+    from oracle.gmres import gmres_cycle
+    from workloads import make_config
+    w = make_config(3)
+    B = O.Tucker(w.b_core, w.b_factors)
+    it = 16
+    log = []
+    Xo, oi = gmres_cycle(w.terms, B, w.Omega, O.SGMRESParams(maxiter=it, cap=w.cap, p=w.p), tol=1e-12, log=log)
+    prm = tk.SolveParams(form=0, tol=1e-12, maxiter=it, rank_cap=w.cap, oversample=w.p, max_restarts=1, method=1)
+    x, info = tk.solve(tk.KronOp.from_terms(w.terms), _gpu(tk, B, rcap=(w.cap,) * 3), None,
+                       [_cm(o) for o in w.Omega], prm)
+    print(f"full-size gmres: gpu iters {info['iters']} last {info['hist'][it - 1]:.6e}; oracle {oi['iters']} "
+          f"last {oi['hist'][-1]:.6e}", flush=True)
+    assert info["iters"] == oi["iters"] == it
+    its = [e for e in log if "k" in e]
+    assert [tuple(e["r2"]) for e in its] == info["ranks"][:it]
+    assert np.max(np.abs(np.array(info["hist"][:it]) - np.array(oi["hist"]))) <= 1e-10
+    bn = O.exact_norm([(1.0, B)])
+    res = [O.exact_norm([(1.0, B)] + [(-c, T) for c, T in O.apply_op(w.terms, X)]) / bn
+           for X in (_cpu(tk, x), Xo)]
+    assert abs(res[0] - res[1]) <= 1e-10
+
+
+def test_fullsize_regularised_deblur_cycle(tk):
+    # Projected Tikhonov + GCV on the benchmark's regularised deblurring
+    # workload (n = 256, rank cap 48, sketch size 120), one cycle of 24
+    # iterations: lambda_k, the sketched residuals and the solution within
+    # 1e-6 or ten times the oracle's own spread under 1e-15 input changes.
+    from test_gpu_tikhonov import _oracle_spread
+    from workloads import deblur_gcv_problem, draw_sketches
+    n, cap, p, it = 256, 48, 5, 24
+    K, (bc, bU), (xc, xU) = deblur_gcv_problem(n)
+    terms = [(1.0, [K, K, K])]
+    B = O.Tucker(bc, bU)
+    S, Om = draw_sketches([n] * 3, 120, cap, p, seed=0)
+    oprm = O.SGMRESParams(maxiter=it, k_trunc=2, cap=cap, p=p, tikhonov=True)
+    xt = O.Tucker(xc, xU)
+    nxt = O.exact_norm([(1.0, xt)])
+
+    def run(Bx):
+        X, oi = O.sgmres_cycle(terms, Bx, S, Om, oprm, tol=1e-13)
+        assert oi["iters"] == it
+        rre = O.exact_norm([(1.0, X), (-1.0, xt)]) / nxt
+        return np.array(oi["lam"]), np.array(oi["hist"]), rre, O.to_dense(X)
+
+    (lo, ho, rre_o, Xo), lam_s, hist_s, rre_s, x_s = _oracle_spread(run, B)
+    prm = tk.SolveParams(form=0, tol=1e-14, maxiter=it, k_trunc=2, rank_cap=cap, oversample=p, max_restarts=1,
+                         tikhonov=True)
+    x, info = tk.solve(tk.KronOp.from_terms(terms), _gpu(tk, B, rcap=(cap,) * 3), [_cm(s) for s in S],
+                       [_cm(o) for o in Om], prm)
+    Xg = _cpu(tk, x)
+    rre_g = O.exact_norm([(1.0, Xg), (-1.0, xt)]) / nxt
+    dist = np.linalg.norm(O.to_dense(Xg) - Xo) / np.linalg.norm(Xo)
+    print(f"full-size regularised cycle: gpu rre {rre_g:.6f} lam[-1] {info['lam'][it - 1]:.6e}; oracle rre "
+          f"{rre_o:.6f} lam[-1] {lo[-1]:.6e}; spread lam {lam_s.max():.1e} rre {rre_s:.1e}; dist {dist:.2e}",
+          flush=True)
+    assert info["iters"] == it
+    assert np.all(np.abs(np.array(info["lam"][:it]) / lo - 1) <= np.maximum(1e-6, 10 * lam_s))
+    assert np.all(np.abs(np.array(info["hist"][:it]) / ho - 1) <= np.maximum(1e-6, 10 * hist_s))
+    assert abs(rre_g / rre_o - 1) <= max(1e-6, 10 * rre_s)
+    assert dist <= max(1e-6, 10 * x_s)
