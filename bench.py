@@ -211,6 +211,22 @@ def precond_bench(tk, torch, args):
                          true_relres=inf["true_relres"], true_hist=inf["true_hist"],
                          seconds_per_solve=dt / args.steps,
                          iters_per_s=sum(i["iters"] for i in infos) / dt, workspace_bytes=ws.numel())
+    if not args.no_cpu_baseline:
+        # the oracle's whole FP64 solve to the same tolerance (a few iterations)
+        import oracle as O
+        from oracle import precond as P
+        Sn, On = draw_sketches([n] * 3, 2 * maxiter, cap, p, seed=0)
+        eig = [P.laplacian_eig(n)] * 3
+        t2 = time.perf_counter()
+        _, oi = O.solve(terms, O.Tucker(np.ones((1, 1, 1)), [np.ones((n, 1)) / np.sqrt(n), e1, e1]), Sn, On,
+                        O.SGMRESParams(tol=args.tol, eta=0.4, maxiter=maxiter, k_trunc=1, cap=cap, p=p, max_restarts=8),
+                        precond=lambda V, rf: P.precond_apply(V, eig, q, rf))
+        dto = time.perf_counter() - t2
+        out["cpu_baseline"] = dict(value=oi["iters"] / dto, unit="sGMRES iterations/s", kind="oracle",
+                                   seconds_per_solve=dto, status={0: "ok"}.get(oi["status"], str(oi["status"])),
+                                   true_relres=oi["true_relres"],
+                                   sample=f"the whole preconditioned FP64 solve ({oi['iters']} iterations, "
+                                          f"{oi['cycles']} cycle(s)), {dto:.1f} s")
     return out
 
 
@@ -293,10 +309,22 @@ def gmres_bench(tk, torch, w, op, b, Om, args):
     inf = infos[-1]
     target = args.tol
     t_target = next((t for r, t in zip(inf["true_hist"], inf["cycle_seconds"]) if r <= target), None)
-    return dict(method="RHOSVD-Tucker GMRES (Alg. 1), FP64 form", iters=inf["iters"], cycles=inf["cycles"],
-                status=inf["status_name"], true_relres=inf["true_relres"], true_hist=inf["true_hist"],
-                seconds_per_solve=dt / args.steps, seconds_to_target=t_target,
-                iters_per_s=sum(i["iters"] for i in infos) / dt, workspace_bytes=ws.numel())
+    out = dict(method="RHOSVD-Tucker GMRES (Alg. 1), FP64 form", iters=inf["iters"], cycles=inf["cycles"],
+               status=inf["status_name"], true_relres=inf["true_relres"], true_hist=inf["true_hist"],
+               seconds_per_solve=dt / args.steps, seconds_to_target=t_target,
+               iters_per_s=sum(i["iters"] for i in infos) / dt, workspace_bytes=ws.numel())
+    if not args.no_cpu_baseline:
+        import oracle as O
+        from oracle.gmres import gmres_cycle
+        it = 16
+        t2 = time.perf_counter()
+        _, oi = gmres_cycle(w.terms, O.Tucker(w.b_core, w.b_factors), w.Omega,
+                            O.SGMRESParams(maxiter=it, cap=w.cap, p=w.p), tol=1e-30)
+        dto = time.perf_counter() - t2
+        out["cpu_baseline"] = dict(value=oi["iters"] / dto, unit="GMRES iterations/s", kind="oracle",
+                                   sample=f"first {oi['iters']} full-Arnoldi iterations (plus final assembly) of "
+                                          f"one cycle of the same workload, {dto:.1f} s")
+    return out
 
 
 def main():
