@@ -27,7 +27,11 @@ residual ``||B - L(x)|| / ||B||`` (QR of concatenated factors) decides;
 residual by less than 10% stop the solve with a rank-floor status.  A solve
 that stops without converging returns the iterate with the smallest true
 residual (cycles on a rank floor can raise it: x + d is rounded back to the
-rank cap).  These
+rank cap).  A floor reached while every rank of x is below the cap comes
+from the update's truncation tolerance (on an operator of condition number
+kappa, rounding x + d to relative accuracy eps moves the residual by up to
+about kappa eps): the tolerance is then divided by 100, down to 1e-15, and
+the refinement goes on, with the floor test counting cycles afresh.  These
 outer RoundSums use the full sketch width cap + p: the effective-rank rule of
 Sec. 3.1 sizes the sketch from the weighted factor Gram, where a correction d
 far smaller than x (or a residual far smaller than B and L(x)) sits below the
@@ -47,6 +51,7 @@ from .tikhonov import projected_tikhonov
 from .tucker import Tucker, apply_op, exact_norm, inner, scale, sketch_krp
 
 OK, NOT_CONVERGED, BREAKDOWN, RANK_FLOOR = 0, 1, 2, 3
+EPS_OUTER_MIN = 1e-15
 
 
 @dataclasses.dataclass
@@ -181,6 +186,7 @@ def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False
         r, _ = roundsum(Rb, Omega, rep.next(rpo))
     true_hist, iters, status = [], 0, NOT_CONVERGED
     cycles = 0
+    floor_from = 0          # the floor test looks at cycles from this index on
     best = (rnorm, x) if x is not None else (np.inf, None)
     for c in range(prm.max_restarts):
         if rnorm <= prm.tol * bnorm:
@@ -209,9 +215,14 @@ def solve(terms, B: Tucker, S, Omega, prm: SGMRESParams, transpose: bool = False
         if rnorm <= prm.tol * bnorm:
             status = OK
             break
-        if len(true_hist) >= 3 and true_hist[-1] > 0.9 * true_hist[-2] and true_hist[-2] > 0.9 * true_hist[-3]:
-            status = RANK_FLOOR
-            break
+        h = true_hist[floor_from:]
+        if len(h) >= 3 and h[-1] > 0.9 * h[-2] and h[-2] > 0.9 * h[-3]:
+            if max(x.ranks) < prm.cap and rpo.eps > EPS_OUTER_MIN:
+                rpo = dataclasses.replace(rpo, eps=max(1e-2 * rpo.eps, EPS_OUTER_MIN))
+                floor_from = len(true_hist) - 1
+            else:
+                status = RANK_FLOOR
+                break
         r, _ = roundsum(Rb, Omega, rep.next(rpo))
     if status != OK and best[1] is not None and best[0] < rnorm:
         rnorm, x = best

@@ -7,7 +7,9 @@
 // The outer loop is FP64: x <- RoundSum(x + d), the exact residual norm via
 // QR of concatenated factors, and RoundSum(B - L(x)) as the next right-hand
 // side.  A solve that stops without converging returns the iterate with the
-// smallest true residual.
+// smallest true residual.  A rank floor reached with every rank of x below
+// the cap tightens the truncation of the refinement RoundSums (x100, down to
+// 1e-15) instead of stopping.
 #include <chrono>
 #include <cmath>
 #include <limits>
@@ -18,6 +20,8 @@
 namespace tk {
 
 namespace {
+
+constexpr double kEpsOuterMin = 1e-15;  // floor of the refinement truncation tolerance
 
 template <typename T>
 void emit_copy_tt(Seq& q, const Shape& sh, const TT<T>& src, const TT<T>& dst, double scale = 1.0,
@@ -282,10 +286,17 @@ class Solver {
   Seq s_setup, s_x0, s_to_cycle, s_from_cycle, s_first_x, s_xupd[2], s_rnorm[2], s_rround[2], s_keep[2];
   double *bnorm2, *rnorm2;
   double* host2 = nullptr;  // pinned scratch
+  // truncation tolerance of the refinement RoundSums, on the device so the
+  // loop can tighten it (see solver_run); pinned staging for it and the ranks
+  double* eps_out_dev = nullptr;
+  double* host_eps = nullptr;
+  int* host_rank = nullptr;
   int xc = 0;
 
   ~Solver() {
     if (host2) (void)hipHostFree(host2);
+    if (host_eps) (void)hipHostFree(host_eps);
+    if (host_rank) (void)hipHostFree(host_rank);
   }
 };
 
@@ -316,7 +327,12 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
   s.x[2] = alloc_tt<double>(ar, sh);
   s.bnorm2 = ar.alloc<double>(1);
   s.rnorm2 = ar.alloc<double>(1);
-  if (!ar.measuring()) TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&s.host2), 2 * sizeof(double), 0));
+  s.eps_out_dev = ar.alloc<double>(2);
+  if (!ar.measuring()) {
+    TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&s.host2), 2 * sizeof(double), 0));
+    TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&s.host_eps), 2 * sizeof(double), 0));
+    TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&s.host_rank), kMaxD * sizeof(int), 0));
+  }
   Blob* bl = &s.blob;
 
   // ---- orthonormalise the right-hand side: U_k = Q_k R_k, core <- core x_k R_k
@@ -352,6 +368,7 @@ SolverPtr make_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const
   // ---- cycle in the requested precision
   RoundCfg outer;
   outer.eps = 1e-2 * cfg.tol;
+  outer.eps_dev = s.eps_out_dev;  // {eps, tau}, set by solver_run
   // full sketch width in the refinement RoundSums: a correction far below x
   // (a residual far below B and L(x)) is invisible to the effective-rank rule,
   // whose Gram of weighted factors puts it under its rounding level
@@ -478,6 +495,16 @@ void solver_run(Solver& s, TT<double>& x_out, SolveInfo& info, hipStream_t st) {
   const double eps_min = cfg.eps_min > 0 ? cfg.eps_min : (fp32 ? 1e-6 : 1e-13);
   const double tin_floor = cfg.tol_inner_floor > 0 ? cfg.tol_inner_floor : (fp32 ? 1e-5 : 1e-13);
   info = SolveInfo{};
+  // truncation tolerance of the refinement RoundSums: 1e-2 tol, tightened below
+  double eps_out = 1e-2 * cfg.tol;
+  auto set_eps_out = [&](double e) {
+    s.host_eps[0] = e;
+    s.host_eps[1] = e;
+    TK_HIP(hipMemcpyAsync(s.eps_out_dev, s.host_eps, 2 * sizeof(double), hipMemcpyHostToDevice, st));
+    TK_HIP(hipStreamSynchronize(st));
+  };
+  set_eps_out(eps_out);
+  size_t floor_from = 0;  // the floor test looks at cycles from this index on
   s.s_setup.run(st);
   const double bnorm = std::sqrt(read_scalar(s, s.bnorm2, st));
   s.xc = 0;
@@ -536,10 +563,23 @@ void solver_run(Solver& s, TT<double>& x_out, SolveInfo& info, hipStream_t st) {
       break;
     }
     const size_t nh = info.hist_true.size();
-    if (nh >= 3 && info.hist_true[nh - 1] > 0.9 * info.hist_true[nh - 2] &&
+    if (nh >= floor_from + 3 && info.hist_true[nh - 1] > 0.9 * info.hist_true[nh - 2] &&
         info.hist_true[nh - 2] > 0.9 * info.hist_true[nh - 3]) {
-      status = kRankFloor;
-      break;
+      // A floor reached with every rank of x below the cap comes from the
+      // update's truncation (rounding x + d to relative accuracy eps moves the
+      // residual by up to about kappa eps): tighten it and go on.
+      TK_HIP(hipMemcpyAsync(s.host_rank, s.x[s.xc].rank, s.sh.d * sizeof(int), hipMemcpyDeviceToHost, st));
+      TK_HIP(hipStreamSynchronize(st));
+      int rmax = 0;
+      for (int k = 0; k < s.sh.d; ++k) rmax = std::max(rmax, s.host_rank[k]);
+      if (rmax < s.sh.cap && eps_out > kEpsOuterMin) {
+        eps_out = std::max(1e-2 * eps_out, kEpsOuterMin);
+        set_eps_out(eps_out);
+        floor_from = nh - 1;
+      } else {
+        status = kRankFloor;
+        break;
+      }
     }
     s.s_rround[s.xc].run(st);
   }

@@ -82,3 +82,35 @@ def test_preconditioned_solve_parity(tk, n, q, form):
                        precond=lambda V, rf: P.precond_apply(V, eig, q, rf))
         h_o = np.array([e["res"] for e in log if "k" in e])[:n1]
         assert np.max(np.abs(np.array(info["hist"][:len(h_o)]) - h_o)) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_update_truncation_tightening_parity(tk, n):
+    # Preconditioned Poisson, all-ones right-hand side, tol 1e-8, cap 32: both
+    # sides floor near kappa 1e-2 tol with ranks below the cap, tighten the
+    # update truncation and converge; equal status, iterations and cycles; the
+    # first cycle's true residual is the truncation floor itself, the norm of
+    # what rounding at eps = 1e-10 discards, whose relative sensitivity to
+    # rounding is about u / eps = 1e-6: held to 1e-4; later cycles (restart
+    # residuals: rounding-level differences of the basis amplify) within 5e-2
+    from workloads import draw_sketches, laplacian_1d
+    cap, p, q = 32, 5, 36
+    L = laplacian_1d(n)
+    terms = [(1.0, [L if j == k else None for j in range(3)]) for k in range(3)]
+    B = O.Tucker(np.ones((1, 1, 1)), [np.ones((n, 1))] * 3)
+    S, Om = draw_sketches([n] * 3, 120, cap, p)
+    eig = [P.laplacian_eig(n)] * 3
+    oprm = O.SGMRESParams(tol=1e-8, maxiter=60, k_trunc=2, cap=cap, p=p, max_restarts=8)
+    Xo, oi = O.solve(terms, B, S, Om, oprm, precond=lambda V, rf: P.precond_apply(V, eig, q, rf))
+    prm = tk.SolveParams(tol=1e-8, maxiter=60, k_trunc=2, rank_cap=cap, oversample=p, max_restarts=8,
+                         precond_q=q, precond=tk.laplacian_precond((n,) * 3))
+    x, info = tk.solve(tk.KronOp.from_terms(terms), tk.Tucker.from_numpy(B.core, B.U, rcap=(cap,) * 3),
+                       [_cm(a) for a in S], [_cm(a) for a in Om], prm)
+    print(f"tightening n={n}: gpu {info['status_name']} iters {info['iters']} cycles {info['cycles']} hist "
+          f"{['%.2e' % v for v in info['true_hist']]}; oracle {oi['status']} iters {oi['iters']} cycles "
+          f"{oi['cycles']} hist {['%.2e' % v for v in oi['true_hist']]}", flush=True)
+    assert info["status"] == oi["status"] == 0
+    assert info["iters"] == oi["iters"] and info["cycles"] == oi["cycles"]
+    assert abs(info["true_hist"][0] / oi["true_hist"][0] - 1) <= 1e-4
+    assert np.allclose(info["true_hist"], oi["true_hist"], rtol=5e-2)
+    assert info["true_relres"] <= 1e-8

@@ -161,3 +161,26 @@ def test_rank_floor_is_reported():
     assert info["true_relres"] == min(info["true_hist"])
     rel = O.exact_norm([(1.0, B)] + [(-c, T) for c, T in O.apply_op(w.terms, X)]) / O.exact_norm([(1.0, B)])
     assert abs(rel - info["true_relres"]) <= 1e-12
+
+
+def test_update_truncation_is_tightened_below_the_cap():
+    # Preconditioned Poisson n = 64 (kappa ~ 1.7e3), all-ones right-hand side,
+    # tol 1e-8: rounding x + d at 1e-2 tol floors the true residual near 2e-8
+    # with every rank (11) below the cap 32; the refinement then tightens the
+    # update truncation and reaches the tolerance
+    from oracle import precond as P
+    n, cap, p = 64, 32, 5
+    L = laplacian_1d(n)
+    terms = [(1.0, [L if j == k else None for j in range(3)]) for k in range(3)]
+    B = O.Tucker(np.ones((1, 1, 1)), [np.ones((n, 1))] * 3)
+    from workloads import draw_sketches
+    S, Om = draw_sketches([n] * 3, 120, cap, p)
+    eig = [P.laplacian_eig(n)] * 3
+    prm = O.SGMRESParams(tol=1e-8, maxiter=60, k_trunc=2, cap=cap, p=p, max_restarts=8)
+    X, info = O.solve(terms, B, S, Om, prm, precond=lambda V, rf: P.precond_apply(V, eig, 36, rf))
+    h = info["true_hist"]
+    assert info["status"] == OK and info["true_relres"] <= 1e-8
+    assert len(h) >= 4 and min(h[:3]) > 1e-8 and max(h[:3]) < 1.1 * min(h[:3])   # the floor, then the drop
+    assert max(X.ranks) < cap
+    rel = O.exact_norm([(1.0, B)] + [(-c, T) for c, T in O.apply_op(terms, X)]) / O.exact_norm([(1.0, B)])
+    assert abs(rel - info["true_relres"]) <= 1e-12
