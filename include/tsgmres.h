@@ -184,7 +184,10 @@ int tucker_rhosvd_workspace(const tk_block_sum* in, const tk_round_params* prm, 
  * (TK_OK / TK_NOT_CONVERGED / TK_BREAKDOWN / TK_RANK_FLOOR) or an error.
  * Without convergence x is the iterate with the smallest true residual (an
  * initial guess included) and info->true_relres is that residual;
- * info->hist_true keeps every cycle's. */
+ * info->hist_true keeps every cycle's.  The refinement rounds x + d to
+ * relative accuracy 1e-2 tol; when the true residual stalls for two cycles
+ * while every rank of x is below rank_cap, that tolerance is divided by 100
+ * (down to 1e-15) and the refinement goes on. */
 int tsgmres_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* prm, const double* const* S,
                   const double* const* omega, tk_tucker* x, tk_sgmres_info* info, void* ws, size_t ws_bytes,
                   void* stream);
