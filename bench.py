@@ -276,6 +276,29 @@ def gcv_bench(tk, torch, args):
                      tikhonov_kernel=dict(launches=nl, avg_us=ms * 1e3 / max(nl, 1),
                                           share_of_solve=(ms * 1e-3) / dt))
         out[name] = r
+    # the other solvers of the inverse-problem comparison, one 60-iteration run
+    # each, with projected Tikhonov + GCV: MLN-Tucker sGMRES (plain and
+    # memory-efficient) and full-Arnoldi RHOSVD-Tucker GMRES
+    from workloads import draw_mln_sketches
+    Psi = [_cm(torch, P) for P in draw_mln_sketches([n] * 3, 48, 48)]
+    bm = tk.Tucker.from_numpy(bc, bU, rcap=(48,) * 3)
+    runs = {
+        "mln_gcv": lambda: tk.mln_solve(op, bm, Psi, tk.MlnParams(r=48, p=48, tol=1e-14, maxiter=it, k_trunc=2,
+                                                                 tikhonov=True)),
+        "mln_save_memory_gcv": lambda: tk.mln_solve(op, bm, Psi, tk.MlnParams(
+            r=48, p=48, tol=1e-14, maxiter=it, k_trunc=2, save_memory=True, r_sol=24, p_sol=24, tikhonov=True)),
+        "gmres_gcv": lambda: tk.solve(op, b, None, Om, tk.SolveParams(
+            form=0, tol=1e-14, maxiter=it, rank_cap=cap, oversample=p, max_restarts=1, tikhonov=True, method=1)),
+    }
+    for name, fn in runs.items():
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, inf = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = dict(iters=inf["iters"], iters_per_s=inf["iters"] / dt, seconds_per_solve=dt,
+                         rre=tk.norm([(1.0, x), (-1.0, xt)]) / nxt, lambda_last=inf["lam"][inf["iters"] - 1])
     if not args.no_cpu_baseline:
         import oracle as O
         from workloads import draw_sketches as ds
