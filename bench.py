@@ -384,7 +384,7 @@ def main():
                          "(a kernel of known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 

@@ -29,7 +29,7 @@
  *   - Return value: 0 = success; > 0 = informational solver status;
  *     < 0 = error (outputs unspecified, message via tk_last_error()).
  *     Nothing throws across the ABI.  The error message is thread-local.
- *   - Limits of this build: 2 <= d <= 4, n_k <= 512, rank_cap + oversample
+ *   - Limits of this library: 2 <= d <= 4, n_k <= 512, rank_cap + oversample
  *     <= 64, sketch size s <= 256, maxiter <= 64; multilinear Nystrom calls:
  *     target rank r <= 64 and r + p <= 256.
  *   - Forms: tensors cross the ABI in FP64.  TK_FORM_FP32 runs a call in the
