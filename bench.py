@@ -276,13 +276,16 @@ def gcv_bench(tk, torch, args):
                      tikhonov_kernel=dict(launches=nl, avg_us=ms * 1e3 / max(nl, 1),
                                           share_of_solve=(ms * 1e-3) / dt))
         out[name] = r
-    # the other solvers of the inverse-problem comparison, one 60-iteration run
-    # each, with projected Tikhonov + GCV: MLN-Tucker sGMRES (plain and
-    # memory-efficient) and full-Arnoldi RHOSVD-Tucker GMRES
+    # the FP32 form and the other solvers of the inverse-problem comparison,
+    # one 60-iteration run each, with projected Tikhonov + GCV: MLN-Tucker
+    # sGMRES (plain and memory-efficient) and full-Arnoldi RHOSVD-Tucker GMRES
     from workloads import draw_mln_sketches
     Psi = [_cm(torch, P) for P in draw_mln_sketches([n] * 3, 48, 48)]
     bm = tk.Tucker.from_numpy(bc, bU, rcap=(48,) * 3)
     runs = {
+        "gcv_fp32_form": lambda: tk.solve(op, b, S, Om, tk.SolveParams(
+            form=1, tol=1e-14, eta=0.4, maxiter=it, k_trunc=2, rank_cap=cap, oversample=p, max_restarts=1,
+            tikhonov=True)),
         "mln_gcv": lambda: tk.mln_solve(op, bm, Psi, tk.MlnParams(r=48, p=48, tol=1e-14, maxiter=it, k_trunc=2,
                                                                  tikhonov=True)),
         "mln_save_memory_gcv": lambda: tk.mln_solve(op, bm, Psi, tk.MlnParams(
