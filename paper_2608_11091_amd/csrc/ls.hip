@@ -159,7 +159,8 @@ __global__ __launch_bounds__(LS_NT) void ls_tikhonov_kernel(LsState S, int s, in
   // ---- one-sided Jacobi
   const int np = K + (K & 1), m = np - 1;
   const int g = tid >> 3, sub = tid & 7;
-  const double jtol = sqrt(double(K)) * 2.220446049250313e-16;
+  // rotate when |c| > sqrt(K) u sqrt(a b), tested squared (no square roots)
+  const double jtol2 = double(K) * 2.220446049250313e-16 * 2.220446049250313e-16;
   for (int sweep = 0; sweep < kJacobiSweeps && K > 1; ++sweep) {
     if (tid == 0) rot_any = 0;
     __syncthreads();
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(LS_NT) void ls_tikhonov_kernel(LsState S, int s, in
       a = group8_sum(a);
       b = group8_sum(b);
       c = group8_sum(c);
-      if (act && fabs(c) > jtol * sqrt(a) * sqrt(b)) {
+      if (act && c * c > jtol2 * (a * b)) {
         const double zeta = (b - a) / (2.0 * c);
         const double az = fabs(zeta);
         const double t = (az > 1e150 ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az))) * (zeta >= 0.0 ? 1.0 : -1.0);
