@@ -308,7 +308,10 @@ int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, doub
 
 /* Message of the last error on this thread ("" if none). */
 const char* tk_last_error(void);
-/* ABI version (major * 100 + minor). */
+/* ABI version (major * 100 + minor).  2.0 (200): tk_sgmres_params gained
+ * tikhonov and method, tk_mln_params gained tikhonov, tk_sgmres_info gained
+ * hist_lambda (all appended), and tsgmres_projected_tikhonov was added. */
+#define TK_ABI_VERSION 200
 int tk_version(void);
 
 #ifdef __cplusplus

@@ -17,6 +17,9 @@ STATUS = {0: "ok", 1: "not_converged", 2: "breakdown", 3: "rank_floor"}
 ERRORS = {-1: "invalid argument", -2: "shape", -3: "capacity", -4: "workspace", -5: "hip",
           -6: "non-finite", -7: "unsupported"}
 
+# the structures below mirror include/tsgmres.h at this ABI version
+ABI_VERSION = 200
+
 EXPORTS = [
     "tucker_apply_op", "tucker_apply_op_workspace", "tucker_sketch", "tucker_sketch_workspace",
     "tucker_rhosvd", "tucker_rhosvd_workspace", "tsgmres_solve", "tsgmres_solve_workspace",
@@ -114,6 +117,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     for name in EXPORTS:
         if not hasattr(lib, name):
             raise RuntimeError(f"{path} does not export {name}")
+    if lib.tk_version() != ABI_VERSION:
+        raise RuntimeError(f"{path} has ABI version {lib.tk_version()}, the binding expects {ABI_VERSION}: rebuild")
     _lib = lib
     return lib
 

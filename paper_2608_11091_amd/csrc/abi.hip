@@ -940,6 +940,6 @@ int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, doub
 }
 
 const char* tk_last_error(void) { return tk::last_error(); }
-int tk_version(void) { return 100; }
+int tk_version(void) { return TK_ABI_VERSION; }
 
 }  // extern "C"

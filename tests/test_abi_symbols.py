@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
     from paper_2608_11091_amd import _abi
     assert sorted(_abi.EXPORTS) == _declared()
-    assert _abi.load().tk_version() >= 100
+    assert _abi.load().tk_version() == _abi.ABI_VERSION
 
 
 def test_storage_helper_matches_worked_example():
