@@ -38,9 +38,12 @@ Parity status (see the pins in ``tests/test_oracle_*.py``):
     closed-form minimiser for equal singular values, brute-force
     minimisation on a fine grid, the lambda -> 0 limit, and the removal of
     semiconvergence on a noisy blur problem).
-  * effective-rank heuristic's choice of sketch size beyond the exactness
-    test: parity unpinned (a heuristic; only its invariance and monotone
-    behaviour are tested).
+  * effective-rank heuristic (Sec. 3.1): pinned (the threshold and the
+    |c| ||G|| weighting on a constructed sum whose Gram tail sits just above
+    and just below tau^2 sum(lambda); the numerical rank of a wide
+    concatenation counted from its SVD; invariance under splitting a summand
+    and under a global scale).  Whether the width it picks gives a good
+    range sketch is probabilistic and stays unpinned.
 """
 from .tucker import (Tucker, to_dense, ttm, multi_ttm, unfold, apply_op, transpose_terms,
                      dense_operator, sketch_krp, sketch_kron, inner, exact_norm,

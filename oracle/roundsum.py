@@ -13,12 +13,11 @@ Steps, in the paper's order:
 
 Readings where the paper leaves a choice:
   * weights are |c_i| ||G^(i)||_F (the coefficient of a summand scales its
-    energy); the Gram is formed on the smaller side (R_k x R_k or n_k x n_k);
+    energy); the Gram is formed on the smaller side (R_k x R_k or n_k x n_k),
+    at every size: both sides have the same nonzero eigenvalues;
   * eigenvalues below ``delta * lambda_max`` (delta = 1e-12, ~30x above the
     rounding level of a 512-wide FP64 Gram) are treated as zero, then
     ``r~_k = min{r : sum_{i>r} lambda_i <= tau^2 sum_i lambda_i}``;
-  * when ``min(R_k, n_k) > eig_max`` (160) the estimate is skipped and the
-    width takes its cap ``cap + p`` (the paper calls the width conservative);
   * ``s = min(max_k r~_k + p, cap + p)``; the range-finder test matrices are
     the leading s columns of a fixed pool Omega_k drawn once, and mode k keeps
     ``min(s, n_k)`` orthonormal columns from its QR;
@@ -39,7 +38,6 @@ import numpy as np
 from .tucker import Tucker, multi_ttm, ttm, unfold
 
 DELTA_CLAMP = 1e-12
-EIG_MAX = 160
 ZERO_TOL = 16.0 * 2.0 ** -53
 
 
@@ -51,7 +49,6 @@ class RoundParams:
     tau: Optional[float] = None     # effective-rank threshold (default: eps)
     force_s: Optional[int] = None   # replay the sketch width
     force_ranks: Optional[Sequence[int]] = None   # replay output ranks
-    eig_max: int = EIG_MAX
     delta: float = DELTA_CLAMP
 
 
@@ -65,7 +62,7 @@ def _rank_from_tail(vals_desc: np.ndarray, thresh: float) -> int:
 def effective_sketch_size(blocks, prm: RoundParams):
     """Step 1 (Sec. 3.1): per-mode effective rank of the energy-weighted
     concatenated factors, then the uniform sketch width.  Returns
-    ``(s, [r~_k])`` with ``r~_k = None`` where the estimate was skipped."""
+    ``(s, [r~_k])``."""
     d = blocks[0][1].d
     n = blocks[0][1].n
     tau = prm.eps if prm.tau is None else prm.tau
@@ -74,9 +71,6 @@ def effective_sketch_size(blocks, prm: RoundParams):
     for k in range(d):
         V = np.concatenate([wb * X.U[k] for wb, (_, X) in zip(w, blocks)], axis=1)
         R = V.shape[1]
-        if min(R, n[k]) > prm.eig_max:
-            rt.append(None)
-            continue
         Gm = V.T @ V if R <= n[k] else V @ V.T
         lam = np.sort(np.linalg.eigvalsh(Gm))[::-1]
         if lam.size == 0 or lam[0] <= 0.0:
@@ -85,7 +79,7 @@ def effective_sketch_size(blocks, prm: RoundParams):
         lam = np.where(lam > prm.delta * lam[0], lam, 0.0)
         rt.append(_rank_from_tail(lam, tau * tau * lam.sum()))
     big = prm.cap + prm.p
-    est = max(big if r is None else r + prm.p for r in rt)
+    est = max(r + prm.p for r in rt)
     s = min(est, big)
     return int(s), rt
 

@@ -4,6 +4,10 @@
 //    with the matrix distributed over the registers of 16 waves, then every
 //    eigenvalue by multisection on Sturm counts.  Used by the RoundSum
 //    effective-rank rule, which needs the spectrum but no vectors.
+//  * Eigenvalues only (160 < N <= 512): the same reduction with the matrix in
+//    global memory (it stays in the L2 of the workgroup's XCD), reduced in
+//    place; each step streams the trailing block once, applying the previous
+//    step's rank-2 update and forming the next product A v in the same pass.
 //  * Eigenvalues and vectors (N <= 64): cyclic Jacobi with the round-robin
 //    parallel ordering, full matrix and eigenvector block in LDS, one lane
 //    per row and one wave per rotation pair.  A rotation is taken only when
@@ -20,8 +24,9 @@ namespace tk {
 
 namespace {
 
-constexpr int VAL_NMAX = 160;
+constexpr int VAL_NMAX = kEigRegMax;
 constexpr int VEC_NMAX = 64;
+constexpr int GM_NMAX = 512;
 
 template <typename T> struct Lim;
 template <> struct Lim<double> {
@@ -339,6 +344,177 @@ __global__ __launch_bounds__(TRG_NT) void tridiag_reg_kernel(const EigTask<T>* _
   tridiag_spectrum<T>(tk_, dd, ee, lam, sc, N, tid, TRG_NT);
 }
 
+// Householder tridiagonalisation of an N x N symmetric matrix (160 < N <= 512)
+// held in global memory, column-major with leading dimension lda; only the
+// lower triangle of the input is read and the matrix is overwritten.  One
+// workgroup of 16 waves.  The lower triangle is first mirrored into the upper
+// one through LDS tiles, so that the reduction can keep full storage and form
+// A v as row sums (each lane owns rows, no cross-lane sums per column).
+// Step j (sub-block S = rows/columns j+1..N-1, Householder vector v with
+// v_{j+1} = 1, tau, and the pending update (vp, wp) of step j-1):
+//   1. column j of the updated matrix, x_i = a_ij - vp_i wp_j - wp_i vp_j;
+//      the diagonal entry and ||x_{j+2..}||^2 give v, tau and beta;
+//   2. one pass over S: a <- a - vp wp^T - wp vp^T (stored back), and every
+//      lane accumulates its rows of S v; the same pass accumulates v^T S v;
+//   3. w = tau S v - (tau^2 / 2)(v^T S v) v becomes the pending update.
+// The final 2 x 2 block takes the last pending update; then the spectrum by
+// multisection as above.
+template <typename T>
+__global__ __launch_bounds__(1024) void tridiag_gm_kernel(const EigTask<T>* __restrict__ tasks, int NL) {
+  constexpr int NT = 1024;
+  constexpr int NW = NT / kWave;          // 16 waves
+  constexpr int RCH = GM_NMAX / kWave;    // row chunks of 64
+  const EigTask<T> tk_ = tasks[blockIdx.x];
+  int N = NL;
+  if (tk_.ndyn != nullptr) {
+    const int nd = *tk_.ndyn;
+    if (nd < 0 || nd > NL) {
+      if (threadIdx.x == 0 && tk_.rule.rank_out) *tk_.rule.rank_out = -1;
+      return;
+    }
+    N = nd;
+  }
+  if (N == 0) {
+    if (threadIdx.x == 0 && tk_.rule.rank_out) *tk_.rule.rank_out = 0;
+    return;
+  }
+  T* A = const_cast<T*>(tk_.A);
+  const size_t lda = size_t(tk_.lda);
+  __shared__ T xb[GM_NMAX], vp[GM_NMAX], wp[GM_NMAX];
+  __shared__ T rowp[NW][GM_NMAX];  // per-wave row sums; also the mirror tiles
+  __shared__ T part[NW], qpart[NW];
+  __shared__ T dd[GM_NMAX], ee[GM_NMAX], lam[GM_NMAX];
+  __shared__ T sc[4];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  for (int i = tid; i < GM_NMAX; i += NT) {
+    vp[i] = T(0);
+    wp[i] = T(0);
+  }
+  // ---- mirror the lower triangle into the upper one, 64 x 64 tiles through LDS
+  {
+    T* tile = &rowp[0][0];  // 64 x 65 staging (fits in rowp)
+    const int nt = (N + kWave - 1) / kWave;
+    for (int I = 0; I < nt; ++I)
+      for (int J = 0; J <= I; ++J) {
+        // load tile (I, J): column c of the tile by the threads with c % 16 == wave
+        for (int c = wave; c < kWave; c += NW) {
+          const int r = I * kWave + lane, col = J * kWave + c;
+          tile[c * (kWave + 1) + lane] = (r < N && col < N) ? A[r + size_t(col) * lda] : T(0);
+        }
+        __syncthreads();
+        // store its transpose into tile (J, I), upper-triangle entries only
+        for (int c = wave; c < kWave; c += NW) {
+          const int r = J * kWave + lane, col = I * kWave + c;  // destination (r, col), r < col
+          if (r < N && col < N && r < col) A[r + size_t(col) * lda] = tile[lane * (kWave + 1) + c];
+        }
+        __syncthreads();
+      }
+  }
+  for (int j = 0; j + 2 < N; ++j) {
+    // ---- 1. column j after the pending update, ||x_{j+2..N-1}||^2
+    T s2p = T(0);
+    if (tid >= j && tid < N) {
+      const T x = A[tid + size_t(j) * lda] - (vp[tid] * wp[j] + wp[tid] * vp[j]);
+      xb[tid] = x;
+      if (tid == j) dd[j] = x;
+      if (tid >= j + 2) s2p = x * x;
+    }
+    s2p = wave_sum(s2p);
+    if (lane == 0) part[wave] = s2p;
+    __syncthreads();
+    T s2 = T(0);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s2 += part[w];
+    const T alpha = xb[j + 1];
+    T beta, tau, scal;
+    if (s2 == T(0)) {
+      beta = alpha;
+      tau = T(0);
+      scal = T(0);
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+      tau = (beta - alpha) / beta;
+      scal = T(1) / (alpha - beta);
+    }
+    if (tid == 0) ee[j] = beta;
+    const T vmask = tau != T(0) ? T(1) : T(0);
+    auto vval = [&](int i) -> T {  // Householder vector entry (0 outside j+1..N-1)
+      return i == j + 1 ? vmask : (i > j + 1 && i < N ? xb[i] * scal : T(0));
+    };
+    // ---- 2. pass over the trailing block
+    const int r0 = j + 1;
+    const int t0 = r0 / kWave;  // first row chunk touched (uniform)
+    T vpr[RCH], wpr[RCH], vr[RCH], acc[RCH];
+#pragma unroll
+    for (int t = 0; t < RCH; ++t) {
+      const int i = t * kWave + lane;
+      const bool ok = i >= r0 && i < N;
+      vpr[t] = ok ? vp[i] : T(0);
+      wpr[t] = ok ? wp[i] : T(0);
+      vr[t] = ok ? vval(i) : T(0);
+      acc[t] = T(0);
+    }
+    for (int c = r0 + wave; c < N; c += NW) {
+      const T vpc = vp[c], wpc = wp[c], vc = vval(c);
+      T* col = A + size_t(c) * lda;
+      T a[RCH];
+#pragma unroll
+      for (int t = 0; t < RCH; ++t) {
+        const int i = t * kWave + lane;
+        a[t] = (t >= t0 && i >= r0 && i < N) ? col[i] : T(0);
+      }
+#pragma unroll
+      for (int t = 0; t < RCH; ++t) {
+        const int i = t * kWave + lane;
+        if (t >= t0 && i >= r0 && i < N) {
+          const T v = a[t] - (vpr[t] * wpc + wpr[t] * vpc);
+          col[i] = v;
+          acc[t] += v * vc;
+        }
+      }
+    }
+    T q = T(0);
+#pragma unroll
+    for (int t = 0; t < RCH; ++t) {
+      q += vr[t] * acc[t];
+      const int i = t * kWave + lane;
+      if (i >= r0 && i < N) rowp[wave][i] = acc[t];
+    }
+    q = wave_sum(q);
+    if (lane == 0) qpart[wave] = q;
+    __syncthreads();
+    // ---- 3. the new pending update
+    if (tid >= r0 && tid < N) {
+      T sv = T(0), vav = T(0);
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        sv += rowp[w][tid];
+        vav += qpart[w];
+      }
+      const T vi = vval(tid);
+      const T K = T(0.5) * tau * tau * vav;
+      vp[tid] = vi;
+      wp[tid] = tau * sv - K * vi;
+    }
+    __syncthreads();
+  }
+  // last 2 x 2 block (or the single entry) after the last pending update
+  if (tid == 0) {
+    if (N >= 2) {
+      const int a = N - 2, b = N - 1;
+      dd[a] = A[a + size_t(a) * lda] - T(2) * vp[a] * wp[a];
+      ee[a] = A[b + size_t(a) * lda] - (vp[b] * wp[a] + wp[b] * vp[a]);
+      dd[b] = A[b + size_t(b) * lda] - T(2) * vp[b] * wp[b];
+    } else {
+      dd[0] = A[0];
+    }
+  }
+  __syncthreads();
+  tridiag_spectrum<T>(tk_, dd, ee, lam, sc, N, tid, NT);
+}
+
 // ------------------------------------------------------------ eigenvalues + vectors
 __device__ __forceinline__ int player(int s, int t, int NP) { return s == 0 ? 0 : ((s - 1 + t) % (NP - 1)) + 1; }
 
@@ -547,8 +723,11 @@ void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipSt
     constexpr int nt = sizeof(T) == 4 ? 1024 : 512;
     hipLaunchKernelGGL((jacobi_vec_kernel<T, nt>), dim3(ntasks), dim3(nt), 0, st, tasks_d, N);
   } else {
-    TK_CHECK(N <= VAL_NMAX, kErrUnsupported, "symmetric eigensolver: matrix larger than 160");
-    hipLaunchKernelGGL((tridiag_reg_kernel<T, trg_nt<T>()>), dim3(ntasks), dim3(trg_nt<T>()), 0, st, tasks_d, N);
+    TK_CHECK(N <= GM_NMAX, kErrUnsupported, "symmetric eigensolver: matrix larger than 512");
+    if (N <= VAL_NMAX)
+      hipLaunchKernelGGL((tridiag_reg_kernel<T, trg_nt<T>()>), dim3(ntasks), dim3(trg_nt<T>()), 0, st, tasks_d, N);
+    else
+      hipLaunchKernelGGL((tridiag_gm_kernel<T>), dim3(ntasks), dim3(1024), 0, st, tasks_d, N);
   }
   TK_LAUNCH_CHECK();
   timer_end(kc, st);

@@ -514,7 +514,11 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
   if (rule) {
     for (auto& modes : modes_by_n<T>(sh)) {
       const int n = sh.n[modes[0]];
-      if (n <= cfg.eig_max) {
+      // The Gram goes on the smaller side: n x n when n fits the register
+      // eigensolver or the concatenation can be wider than n, otherwise the
+      // R x R Gram of the concatenation (both have the same nonzero spectrum).
+      const int Rp = nb * rc;
+      if (n <= kEigRegMax || Rp > n) {
         // n-side Gram: sum_b w_b^2 U_b U_b^T
         T* Gn = ar.alloc<T>(size_t(n) * n * modes.size());
         T* lam = ar.alloc<T>(size_t(n) * modes.size());
@@ -551,8 +555,7 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
         q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off_et), ne, n, false, st); });
       } else {
         // R-side Gram of the padded concatenation, compacted to the active ranks
-        const int Rp = nb * rc;
-        const int NM = cfg.eig_max;
+        const int NM = Rp;
         double* enable = ar.alloc<double>(kMaxD);
         int* nact = ar.alloc<int>(kMaxD);
         T* Gp = ar.alloc<T>(size_t(Rp) * Rp * d);

@@ -95,7 +95,6 @@ struct RoundCfg {
   double tau = -1.0;  // <= 0: eps
   const double* eps_dev = nullptr;  // optional device {eps, tau}; overrides eps/tau at run time
   double delta = 1e-12;
-  int eig_max = 160;
   int force_s = -1;
   int force_r[kMaxD] = {-1, -1, -1, -1};
   // range-finder basis by Householder QR (orthonormal to O(u)) instead of the

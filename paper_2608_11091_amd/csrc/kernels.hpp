@@ -138,6 +138,9 @@ struct EigTask {
   const int* ndyn; // optional device size (< launch N); negative: skip, rank_out = -1
   EigRule rule;
 };
+// Eigenvalues only: N <= 512; above kEigRegMax the matrix is reduced in place
+// (A must then be writable scratch).  With vectors: N <= 64.
+constexpr int kEigRegMax = 160;
 template <typename T>
 void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipStream_t st);
 

@@ -93,10 +93,68 @@ def test_effective_rank_invariances():
     s3, rt3 = O.effective_sketch_size([(1e3, X), (2e3, Y)], prm)
     assert rt1 == rt2 == rt3 and s1 == s2 == s3
     assert rt1 == [5, 5, 4]          # generic ranks of the concatenations
-    # capped width and skipped estimate for wide concatenations
-    prm2 = O.RoundParams(eps=1e-10, cap=4, p=2, eig_max=3)
+    # the width is capped at cap + p, while the per-mode estimates stay exact
+    prm2 = O.RoundParams(eps=1e-10, cap=4, p=2)
     s4, rt4 = O.effective_sketch_size([(1.0, X), (2.0, Y)], prm2)
-    assert rt4 == [None, None, None] and s4 == 6
+    assert rt4 == [5, 5, 4] and s4 == 6
+
+
+def _orthonormal_blocks(rng, n, ranks):
+    """Factors whose columns are orthonormal ACROSS the blocks, so that the
+    weighted Gram sum_b w_b^2 U_b U_b^T has the eigenvalues w_b^2 with
+    multiplicity r_b exactly (in every mode)."""
+    d = len(n)
+    tot = sum(r for r in ranks)
+    Q = [np.linalg.qr(rng.standard_normal((nk, tot)))[0] for nk in n]
+    out, off = [], 0
+    for r in ranks:
+        out.append([Q[k][:, off:off + r] for k in range(d)])
+        off += r
+    return out
+
+
+@pytest.mark.parametrize("side", ["below", "above"])
+def test_effective_rank_threshold_is_exact(side):
+    """Pin of the Sec. 3.1 rule's threshold and weighting.  Block 1: c = 1,
+    ||G|| = 1, rank 2 -> Gram eigenvalue 1 (twice).  Block 2: c = 1e-3,
+    ||G|| = 2, rank 1 -> eigenvalue (|c| ||G||)^2 = 4e-6.  The tail beyond
+    r = 2 is exactly 4e-6, so tau^2 sum(lambda) just below it gives r~ = 3 and
+    just above gives r~ = 2.  Weights |c| (no core norm: tail 1e-6), |c| ||G||^2
+    (tail 1.6e-5), ||G|| (tail 4) or an unsquared Gram (tail 2e-3) each flip
+    one of the two cases."""
+    rng = np.random.default_rng(11)
+    n = (9, 8, 7)
+    f1, f2 = _orthonormal_blocks(rng, n, [2, 1])
+    G1 = rng.standard_normal((2, 2, 2))
+    G1 /= np.linalg.norm(G1)
+    G2 = np.full((1, 1, 1), 2.0)
+    blocks = [(1.0, O.Tucker(G1, f1)), (-1e-3, O.Tucker(G2, f2))]
+    total = 2.0 + 4e-6
+    thr = 4e-6 * (1.0 - 1e-6 if side == "below" else 1.0 + 1e-6)
+    prm = O.RoundParams(eps=1e-10, cap=8, p=2, tau=np.sqrt(thr / total))
+    s, rt = O.effective_sketch_size(blocks, prm)
+    want = 3 if side == "below" else 2
+    assert rt == [want] * 3 and s == want + 2
+
+
+def test_effective_rank_wide_concatenation_is_numerical_rank():
+    """Past every kernel-size boundary (n = 200 and R = 240 columns) the rule
+    runs on the n-side Gram: with a tiny tau it returns the numerical rank of
+    the weighted concatenation, counted here independently from its SVD."""
+    rng = np.random.default_rng(12)
+    n = (200, 170, 190)
+    B = [np.linalg.qr(rng.standard_normal((nk, 100)))[0] for nk in n]   # 100-dim subspaces
+    blocks = []
+    for b in range(30):
+        U = [Bk @ rng.standard_normal((100, 8)) for Bk in B]
+        blocks.append((float(rng.uniform(0.5, 2.0)), O.Tucker(rng.standard_normal((8, 8, 8)), U)))
+    prm = O.RoundParams(eps=1e-13, cap=120, p=5)
+    s, rt = O.effective_sketch_size(blocks, prm)
+    for k in range(3):
+        V = np.concatenate([abs(c) * np.linalg.norm(X.core) * X.U[k] for c, X in blocks], axis=1)
+        sv = np.linalg.svd(V, compute_uv=False)
+        assert rt[k] == int(np.sum(sv > 1e-5 * sv[0])) == 100
+    assert s == 105
 
 
 def test_rank_tail_rule():
