@@ -24,7 +24,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6, "fp32": 157.3}   # MI355X dense matrix-core TFLOP/s (FP32 vector peak is also 157.3)
+PEAK = {"fp64": 78.6, "fp32": 157.3}   # MI355X dense matrix-core TFLOP/s
+# Vector ALU peak without packed FP32 (the library is built with packed FP32
+# instructions disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz,
+# the same for FP32 and FP64
+VALU_PEAK = 78.6
 HBM_PEAK = 8000.0                        # GB/s
 
 CLASSES = ["gemm", "jacobi", "qr", "krp", "ls", "eigvals"]
@@ -37,15 +41,16 @@ KERNEL_NAME = {
     "eigvals": "tridiag_reg_kernel: eigenvalues for the effective-rank rule",
 }
 # FP32 form: eigensolvers and GEMMs inside cycles run in FP32 (vector ALU / MFMA)
-BOUND = {"gemm": ("mfma", PEAK["fp32"]), "jacobi": ("alu", 157.3), "qr": ("alu", 78.6), "krp": ("alu", 157.3),
-         "ls": ("alu", 78.6), "eigvals": ("alu", 157.3)}
+BOUND = {"gemm": ("mfma", PEAK["fp32"]), "jacobi": ("alu", VALU_PEAK), "qr": ("alu", VALU_PEAK),
+         "krp": ("alu", VALU_PEAK), "ls": ("alu", VALU_PEAK), "eigvals": ("alu", VALU_PEAK)}
 UNIT = {"gemm": "2*M*N*K flops per product", "jacobi": "9*N^3 flops per eigendecomposition of order N",
         "qr": "none counted", "krp": "none counted", "ls": "none counted",
         "eigvals": "(4/3)*N^3 flops per tridiagonal reduction of order N"}
 NOTE = {
     "gemm": "GEMMs run in FP32 inside cycles and FP64 in the restart steps; peak is the FP32 matrix-core peak",
     "jacobi": "one workgroup per matrix (ST-HOSVD modes are sequential), so the kernel can use at most 1/256 of "
-              "the chip's 157.3 TFLOP/s FP32 vector peak; latency bound (about 1.1 us per rotation round)",
+              "the chip's 78.6 TFLOP/s vector peak (packed FP32 disabled); latency bound (one barrier per rotation "
+              "round, two when the round rotates)",
     "qr": "latency bound single-workgroup factorization",
     "krp": "core reductions, L2 resident",
     "ls": "FP64 single-workgroup update",
@@ -84,23 +89,80 @@ def _cm(torch, M):
     return torch.from_numpy(np.ascontiguousarray(M.T)).cuda()
 
 
-def cpu_baseline(w, iters: int):
-    """The FP64 oracle on a bounded sample: the first `iters` sGMRES
-    iterations of one cycle of the same workload, timed on the host cores."""
-    import oracle as O
+def host_cpu():
+    """Model name and usable core count of the host this runs on."""
+    model = None
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count() or 1
+    return dict(model=model, cpu_count=os.cpu_count(), usable_cores=usable)
+
+
+def cpu_baseline(w, iters: int, iters_1thread: int):
+    """The FP64 oracle on a bounded sample: the first `iters` sGMRES
+    iterations of one cycle of the same workload, timed on the host cores
+    with every BLAS/OpenMP thread, and a shorter sample with one thread."""
+    import oracle as O
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     B = O.Tucker(w.b_core, w.b_factors)
-    prm = O.SGMRESParams(tol=1e-30, eta=w.eta, maxiter=iters, k_trunc=w.k_trunc, cap=w.cap, p=w.p)
-    t = time.perf_counter()
-    X, info = O.sgmres_cycle(w.terms, B, w.S, w.Omega, prm, tol=1e-30)
-    dt = time.perf_counter() - t
-    return dict(value=info["iters"] / dt, unit="sGMRES iterations/s", cores=int(cores), kind="oracle",
-                sample=f"first {info['iters']} iterations (plus final assembly) of one FP64 sGMRES cycle of the "
-                       f"same workload, {dt:.1f} s")
+
+    def run(it):
+        prm = O.SGMRESParams(tol=1e-30, eta=w.eta, maxiter=it, k_trunc=w.k_trunc, cap=w.cap, p=w.p)
+        t = time.perf_counter()
+        X, info = O.sgmres_cycle(w.terms, B, w.S, w.Omega, prm, tol=1e-30)
+        return info["iters"], time.perf_counter() - t
+
+    n_all, dt_all = run(iters)
+    with threadpool_limits(limits=1):
+        n_one, dt_one = run(iters_1thread)
+    return dict(value=n_all / dt_all, unit="sGMRES iterations/s", cores=int(cores), kind="oracle",
+                sample=f"first {n_all} iterations (plus final assembly) of one FP64 sGMRES cycle of the "
+                       f"same workload, {dt_all:.1f} s",
+                one_thread=dict(value=n_one / dt_one, cores=1,
+                                sample=f"first {n_one} iterations (plus final assembly), {dt_one:.1f} s"),
+                host=host_cpu())
+
+
+def flops_per_iteration(d, n, r, sr, s, k_trunc, nfactors, nblocks_apply):
+    """Algorithmic flops of one sGMRES inner iteration (what the method
+    computes, not the dense N-vector work it avoids), with rank r in every
+    mode, RoundSum sketch width sr, sketch size s:
+      operator     2 n^2 r per distinct non-identity factor
+      RoundSum     per mode the weighted Gram (2 n R^2) and its spectrum
+                   (10 R^3), factor-sketch products (4 n r sr per block), the
+                   core contractions of the range sketch (2 d r^d sr per
+                   block), the range QR (4 n sr^2), the core projection
+                   (2 sum_m sr^m r^(d-m+1) per block) and ST-HOSVD (per mode
+                   the unfolding Gram and TTM, 4 sr^(d+1), and 9 sr^3)
+      sketch       2 n r s per mode + 2 r^d s
+      window       k_trunc (2 n r^2 per mode + 2 d r^(d+1))
+    for the two RoundSums of an iteration: L(V_k) (nblocks_apply blocks) and
+    the orthogonalisation (1 + k_trunc blocks)."""
+    op = nfactors * 2.0 * n * n * r
+
+    def roundsum(T):
+        R = T * r
+        f = d * (2.0 * n * R * R + 10.0 * R ** 3)
+        f += d * T * 4.0 * n * r * sr
+        f += T * d * 2.0 * r ** d * sr
+        f += d * 4.0 * n * sr * sr
+        f += T * sum(2.0 * sr ** m * r ** (d - m + 1) for m in range(1, d + 1))
+        f += d * (4.0 * sr ** (d + 1) + 9.0 * sr ** 3)
+        return f
+
+    sk = d * 2.0 * n * r * s + 2.0 * r ** d * s
+    win = k_trunc * (d * 2.0 * n * r * r + 2.0 * d * r ** (d + 1))
+    return op + roundsum(nblocks_apply) + roundsum(1 + k_trunc) + sk + win
 
 
 def mln_bench(tk, torch, w, op, b, args):
@@ -182,7 +244,7 @@ def precond_bench(tk, torch, args):
     terms; both forms, time to 1e-8 and iterations/s."""
     import numpy as np
 
-    from workloads import draw_sketches, laplacian_1d
+    from workloads import draw_sketches, laplacian_1d, laplacian_eigenpairs
     n, cap, p, q, maxiter = args.precond_n, args.precond_cap, 5, args.precond_q, 40
     L = laplacian_1d(n)
     terms = [(1.0, [L if j == k else None for j in range(3)]) for k in range(3)]
@@ -193,7 +255,7 @@ def precond_bench(tk, torch, args):
     S, Om = draw_sketches([n] * 3, 2 * maxiter, cap, p, seed=0)
     S = [_cm(torch, a) for a in S]
     Om = [_cm(torch, a) for a in Om]
-    pre = tk.laplacian_precond((n,) * 3)
+    pre = tk.precond_tensors(*laplacian_eigenpairs((n,) * 3))
     out = dict(workload=f"poisson3d_n{n}, rhs ones/||ones|| x e1 x e1 (Laplacian experiment at n = {n})",
                q=q, terms=2 * q + 1, rank_cap=cap, oversample=p, k_trunc=1, sketch_size=2 * maxiter, maxiter=maxiter)
     for form, name in ((1, "fp32_form"), (0, "fp64_form")):
@@ -276,32 +338,6 @@ def gcv_bench(tk, torch, args):
                      tikhonov_kernel=dict(launches=nl, avg_us=ms * 1e3 / max(nl, 1),
                                           share_of_solve=(ms * 1e-3) / dt))
         out[name] = r
-    # the FP32 form and the other solvers of the inverse-problem comparison,
-    # one 60-iteration run each, with projected Tikhonov + GCV: MLN-Tucker
-    # sGMRES (plain and memory-efficient) and full-Arnoldi RHOSVD-Tucker GMRES
-    from workloads import draw_mln_sketches
-    Psi = [_cm(torch, P) for P in draw_mln_sketches([n] * 3, 48, 48)]
-    bm = tk.Tucker.from_numpy(bc, bU, rcap=(48,) * 3)
-    runs = {
-        "gcv_fp32_form": lambda: tk.solve(op, b, S, Om, tk.SolveParams(
-            form=1, tol=1e-14, eta=0.4, maxiter=it, k_trunc=2, rank_cap=cap, oversample=p, max_restarts=1,
-            tikhonov=True)),
-        "mln_gcv": lambda: tk.mln_solve(op, bm, Psi, tk.MlnParams(r=48, p=48, tol=1e-14, maxiter=it, k_trunc=2,
-                                                                 tikhonov=True)),
-        "mln_save_memory_gcv": lambda: tk.mln_solve(op, bm, Psi, tk.MlnParams(
-            r=48, p=48, tol=1e-14, maxiter=it, k_trunc=2, save_memory=True, r_sol=24, p_sol=24, tikhonov=True)),
-        "gmres_gcv": lambda: tk.solve(op, b, None, Om, tk.SolveParams(
-            form=0, tol=1e-14, maxiter=it, rank_cap=cap, oversample=p, max_restarts=1, tikhonov=True, method=1)),
-    }
-    for name, fn in runs.items():
-        fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x, inf = fn()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        out[name] = dict(iters=inf["iters"], iters_per_s=inf["iters"] / dt, seconds_per_solve=dt,
-                         rre=tk.norm([(1.0, x), (-1.0, xt)]) / nxt, lambda_last=inf["lam"][inf["iters"] - 1])
     if not args.no_cpu_baseline:
         import oracle as O
         from workloads import draw_sketches as ds
@@ -364,6 +400,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-restarts", type=int, default=8)
     ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--cpu-iters-1thread", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mln", action="store_true", help="skip the MLN-Tucker sGMRES measurement")
@@ -371,6 +408,8 @@ def main():
     ap.add_argument("--mln-p", type=int, default=48)
     ap.add_argument("--mln-cpu-iters", type=int, default=20)
     ap.add_argument("--no-precond", action="store_true", help="skip the preconditioned Laplacian measurement")
+    ap.add_argument("--precond-only", action="store_true",
+                    help="run only the preconditioned Laplacian measurement (for profiling)")
     ap.add_argument("--precond-n", type=int, default=512)
     ap.add_argument("--precond-cap", type=int, default=48)
     ap.add_argument("--precond-q", type=int, default=49)
@@ -399,6 +438,9 @@ def main():
 
     if args.gcv_only:
         print(json.dumps({"regularised_deblur": gcv_bench(tk, torch, args)}))
+        return
+    if args.precond_only:
+        print(json.dumps({"precond": precond_bench(tk, torch, args)}))
         return
     w = make_config(args.config, n=args.n, cap=args.cap, tol=args.tol)
     op = tk.KronOp.from_terms(w.terms)
@@ -471,13 +513,15 @@ def main():
                     true_relres=i64["true_relres"], true_hist=i64["true_hist"], cycle_seconds=i64["cycle_seconds"])
 
     i32 = infos32[-1]
-    # time-to-target: 1e-8 when the FP64 form reaches it; otherwise (rank floor
-    # far above 1e-8 at this cap) 1.1 x the FP64 form's residual after its first
-    # cycle, a level both forms reach, so the two times compare like for like
+    # time-to-target: 1e-8 when the FP64 form reaches it; otherwise (a rank
+    # floor far above 1e-8 at this cap) 1.1 x the FP64 form's floor (its
+    # final, best true residual) -- labelled, never to be read as 1e-8
     if fp64 and fp64["true_relres"] > args.tol:
-        target = 1.1 * fp64["true_hist"][0]
+        target = 1.1 * fp64["true_relres"]
+        target_kind = "1.1 x the FP64 form's rank floor (the tolerance 1e-8 is not reachable at this rank cap)"
     else:
         target = args.tol
+        target_kind = "the tolerance"
     t_target32 = next((t for r, t in zip(i32["true_hist"], i32["cycle_seconds"]) if r <= target), None)
     t_target64 = (next((t for r, t in zip(fp64["true_hist"], fp64["cycle_seconds"]) if r <= target), None)
                   if fp64 else None)
@@ -514,12 +558,29 @@ def main():
                           seconds_to_target=t_target32),
         "fp64_form": fp64 if fp64 is None else dict(fp64, seconds_to_target=t_target64),
         "target_relres": target,
+        "target_kind": target_kind,
         "speedup_fp32_vs_fp64_time_to_target": (t_target64 / t_target32) if (t_target32 and t_target64) else None,
         "roofline": roofline,
         "kernel_classes": classes,
     }
+    # iteration-level roofline: the algorithmic flops of an inner iteration at
+    # the cap (every rank at the cap, the widest sketch) times iterations per
+    # second; the solve time also holds the per-cycle assembly and the FP64
+    # restart work, so this is a lower bound on the iteration's own fraction
+    nfac = len({(id(A), k) for _, As in w.terms for k, A in enumerate(As) if A is not None})
+    nbl = len(w.terms)
+    fpi = flops_per_iteration(w.d, w.n[0], w.cap, w.cap + w.p, w.s, w.k_trunc, nfac, nbl)
+    it_roof = {"flops_per_iteration": fpi,
+               "formula": "operator + two RoundSums (L(V_k), orthogonalisation) + Khatri-Rao sketch + window "
+                          "inner products at rank cap r, sketch width cap + p (bench.flops_per_iteration)",
+               "fp32_form": dict(achieved=fpi * value / 1e12, peak=PEAK["fp32"], unit="TFLOP/s",
+                                 frac=fpi * value / 1e12 / PEAK["fp32"])}
+    if fp64:
+        it_roof["fp64_form"] = dict(achieved=fpi * fp64["iters_per_s"] / 1e12, peak=PEAK["fp64"], unit="TFLOP/s",
+                                    frac=fpi * fp64["iters_per_s"] / 1e12 / PEAK["fp64"])
+    out["iteration_roofline"] = it_roof
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters, args.cpu_iters_1thread)
     if not args.no_mln:
         out["mln"] = mln_bench(tk, torch, w, op, b, args)
     if not args.no_precond:

@@ -31,7 +31,7 @@ Readings where the paper leaves a choice:
 from __future__ import annotations
 
 import dataclasses
-from typing import List, Optional, Sequence
+from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
@@ -50,6 +50,13 @@ class RoundParams:
     force_s: Optional[int] = None   # replay the sketch width
     force_ranks: Optional[Sequence[int]] = None   # replay output ranks
     delta: float = DELTA_CLAMP
+    # step 3's orthonormal basis of range(Y_k): None = Householder QR.  Sec.
+    # 3.1 fixes the range, not the basis; tests pass another valid basis
+    # routine to measure how far that choice alone moves a trajectory.
+    range_basis: Optional[Callable[[np.ndarray], np.ndarray]] = None
+    # rounding applied to every summand's core and factors on entry (None:
+    # none); tests pass a round-to-FP32 map to model a reduced-precision form
+    operand_rounding: Optional[Callable[[np.ndarray], np.ndarray]] = None
 
 
 def _rank_from_tail(vals_desc: np.ndarray, thresh: float) -> int:
@@ -129,6 +136,9 @@ def roundsum(blocks, Omega: Sequence[np.ndarray], prm: RoundParams):
     """RoundSum of Sec. 3.1 applied to ``sum_b c_b X_b``.  Returns
     ``(Tucker, info)`` with ``info = dict(s=..., ranks=..., rtilde=...)``."""
     d = blocks[0][1].d
+    if prm.operand_rounding is not None:
+        f = prm.operand_rounding
+        blocks = [(c, Tucker(f(X.core), [f(u) for u in X.U])) for c, X in blocks]
     # 1. effective-rank heuristic -> sketch width
     s, rt = effective_sketch_size(blocks, prm)
     if prm.force_s is not None:
@@ -140,8 +150,11 @@ def roundsum(blocks, Omega: Sequence[np.ndarray], prm: RoundParams):
         M = [X.U[j].T @ Om[j] for j in range(d)]          # r_j x s
         for k in range(d):
             Y[k] = Y[k] + c * (X.U[k] @ _mttkrp(X.core, M, k))
-    # 3. economy QR (Householder)
-    Uh = [np.linalg.qr(Yk, mode="reduced")[0] for Yk in Y]
+    # 3. economy QR (Householder), or the given basis routine
+    if prm.range_basis is None:
+        Uh = [np.linalg.qr(Yk, mode="reduced")[0] for Yk in Y]
+    else:
+        Uh = [prm.range_basis(Yk) for Yk in Y]
     # 4. core projection
     C = None
     for c, X in blocks:

@@ -41,7 +41,7 @@ from __future__ import annotations
 
 import dataclasses
 import time
-from typing import List, Optional
+from typing import Callable, List, Optional
 
 import numpy as np
 from scipy.linalg import solve_triangular
@@ -69,6 +69,8 @@ class SGMRESParams:
     eps_outer: Optional[float] = None      # x-update / residual RoundSums (default 1e-2 * tol)
     breakdown_tol: float = 1e-14
     replay: Optional[dict] = None          # rank replay: {"s": [...], "ranks": [...]} consumed in order
+    range_basis: Optional[Callable] = None  # basis routine of the cycle's RoundSums (None: Householder)
+    operand_rounding: Optional[Callable] = None  # rounding of the cycle's RoundSum operands (None: none)
     tikhonov: bool = False                 # projected Tikhonov with GCV on the sketched LS (Sec. 4.3)
 
 
@@ -105,7 +107,8 @@ def sgmres_cycle(terms, B: Tucker, S, Omega, prm: SGMRESParams, tol: Optional[fl
     solution is RoundSum(sum_i y_i Z_i)."""
     tol = prm.tol if tol is None else tol
     eps = prm.eps_trunc if prm.eps_trunc is not None else max(1e-2 * tol, prm.eps_min)
-    rp = RoundParams(eps=eps, cap=prm.cap, p=prm.p)
+    rp = RoundParams(eps=eps, cap=prm.cap, p=prm.p, range_basis=prm.range_basis,
+                     operand_rounding=prm.operand_rounding)
     rep = replay if replay is not None else _Replay(prm.replay)
     beta = exact_norm([(1.0, B)])
     V = [scale(B, 1.0 / beta)]

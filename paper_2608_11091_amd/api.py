@@ -30,7 +30,7 @@ from ._abi import (TK_MAX_D, TkBlockSum, TkKronOp, TkMlnParams, TkRoundParams, T
 __all__ = ["Tucker", "KronOp", "SolveParams", "apply_op", "sketch", "rhosvd", "norm", "solve", "backward",
            "TuckerSGMRESLoss", "storage_floats", "kernel_timer", "kernel_timer_read", "solve_workspace_bytes",
            "MlnParams", "mln_sketch", "mln_recover", "mln_solve", "mln_solve_workspace_bytes",
-           "laplacian_precond"]
+           "precond_tensors", "project_core"]
 
 
 def _stream():
@@ -249,7 +249,7 @@ class SolveParams:
     tol_inner_floor: float = -1.0
     # exponential-sum preconditioner (Sec. 3.4): q and the per-mode eigenpairs
     # (lists of device tensors: V_k as (n_k, n_k) holding the column-major
-    # matrix, lambda_k of length n_k), e.g. from ``laplacian_precond``
+    # matrix, lambda_k of length n_k), e.g. ``precond_tensors(*workloads.laplacian_eigenpairs(n))``
     precond_q: int = 0
     precond: Optional[Tuple[list, list]] = None
     # projected Tikhonov with GCV on the sketched least squares (Sec. 4.3)
@@ -282,17 +282,11 @@ class SolveParams:
         return p, keep
 
 
-def laplacian_precond(n: Sequence[int], device="cuda"):
-    """Eigenpairs of the 1D Laplacian (n+1)^2 tridiag(-1, 2, -1) per mode (the
-    DST-I basis, closed form) as device tensors, for ``SolveParams.precond``."""
-    Vs, lams = [], []
-    for nk in n:
-        i = np.arange(1, nk + 1)
-        V = np.sqrt(2.0 / (nk + 1)) * np.sin(np.outer(i, i) * np.pi / (nk + 1))
-        lam = 4.0 * (nk + 1) ** 2 * np.sin(i * np.pi / (2 * (nk + 1))) ** 2
-        Vs.append(torch.from_numpy(np.ascontiguousarray(V.T)).to(device))
-        lams.append(torch.from_numpy(lam).to(device))
-    return Vs, lams
+def precond_tensors(V: Sequence[np.ndarray], lam: Sequence[np.ndarray], device="cuda"):
+    """Uploads per-mode eigenpairs (V_k n_k x n_k, lambda_k) of the 1D operator
+    for ``SolveParams.precond`` (column-major device layout)."""
+    return ([torch.from_numpy(np.ascontiguousarray(np.asarray(v, dtype=np.float64).T)).to(device) for v in V],
+            [torch.from_numpy(np.ascontiguousarray(np.asarray(l, dtype=np.float64))).to(device) for l in lam])
 
 
 def _info(hist_cap: int):
@@ -337,13 +331,16 @@ def solve(op: KronOp, b: Tucker, S, omega, prm: SolveParams, x0: Optional[Tucker
     ps, k2 = prm.struct(s, x0)
     nb = C.c_size_t()
     check(lib.tsgmres_solve_workspace(C.byref(ops), C.byref(bst), C.byref(ps), C.byref(nb)))
-    ws = workspace if workspace is not None and workspace.numel() >= nb.value else _workspace(nb.value, b.core.device)
+    # a caller's workspace is used as given: one that is too small makes the
+    # library fail with TK_ERR_WORKSPACE before anything is launched
+    ws = workspace if workspace is not None else _workspace(nb.value, b.core.device)
     x = Tucker.empty(b.n, (prm.rank_cap,) * b.d, b.core.device)
     xs = x.struct()
     info, keep = _info(_hist_cap(prm))
     check(lib.tsgmres_solve(C.byref(ops), C.byref(bst), C.byref(ps), _ptr_array(S) if S is not None else None,
                             _ptr_array(omega), C.byref(xs),
-                            C.byref(info), C.c_void_p(ws.data_ptr()), nb.value, _stream()))
+                            C.byref(info), C.c_void_p(ws.data_ptr()), int(ws.numel() * ws.element_size()),
+                            _stream()))
     x.ranks = tuple(int(xs.r[k]) for k in range(b.d))
     return x, _info_dict(info, keep, b.d)
 
@@ -383,35 +380,75 @@ def backward(op: KronOp, x: Tucker, xbar_blocks, S, omega, prm: SolveParams, wan
     return lam, np.array([dal[j] for j in range(op.nterms)]), dA, _info_dict(info, keep, x.d)
 
 
-class TuckerSGMRESLoss(torch.autograd.Function):
-    """loss(alpha) = ||x(alpha) - x_target||^2 / 2 with L(alpha) x = b solved by
-    Tucker sGMRES; the backward pass is the hand-written adjoint solve.
+def project_core(x: Tucker, U: Sequence[torch.Tensor]) -> torch.Tensor:
+    """``x x_1 U_1^T ... x_d U_d^T`` (a ``(m,) * d`` tensor) for factors
+    ``U_k`` of shape ``(m, n_k)`` (column-major n_k x m): the projected core
+    of the multilinear Nystrom sketch with Psi_k = U_k, computed by
+    ``tucker_mln_sketch``."""
+    m = int(U[0].shape[0])
+    if any(int(u.shape[0]) != m for u in U):
+        raise ValueError("project_core needs factors of one width in every mode")
+    core, _, _ = mln_sketch([(1.0, x)], U, 1 if m > 1 else m)
+    return core
 
-    ``problem`` is a dict with keys op (KronOp, its alphas are overridden),
-    b, x_target (Tucker), S, omega, prm (SolveParams).  After ``backward`` the
-    adjoint solution (= dl/db) is left in ``problem['lambda']``."""
+
+_OK_STATUS = (0, 2)   # converged, or exact in the Krylov space (lucky breakdown)
+
+
+class TuckerSGMRESLoss(torch.autograd.Function):
+    """``loss(alpha, G_b) = ||x - x_target||^2 / 2`` where ``L(alpha) x = b``
+    is solved by Tucker sGMRES and ``b = G_b x_1 U_1 ... x_d U_d`` has the
+    differentiable core ``b_core`` and the fixed factors of ``problem['b']``.
+    The backward pass is the hand-written adjoint: one transposed solve
+    ``L^T lambda = x - x_target`` and the contractions
+    ``dl/dalpha_j = -<lambda, x x_k A_j^(k)>`` (``tsgmres_backward``) and
+    ``dl/dG_b = lambda x_k U_k^T`` (dl/db = lambda, projected on b's factors).
+
+    ``problem``: op (KronOp, its alphas are replaced by ``alpha``), b (Tucker,
+    factors of one rank capacity), x_target (Tucker), S, omega, prm
+    (SolveParams).  A solve that ends other than converged or in a lucky
+    breakdown raises.  After ``backward`` the adjoint solution (dl/db as a
+    Tucker tensor) is in ``problem['lambda']``."""
 
     @staticmethod
-    def forward(ctx, alpha: torch.Tensor, problem: dict):
+    def forward(ctx, alpha: torch.Tensor, b_core: torch.Tensor, problem: dict):
         op = KronOp([float(a) for a in alpha.detach().cpu().tolist()], problem["op"].A)
-        x, info = solve(op, problem["b"], problem["S"], problem["omega"], problem["prm"])
+        b0 = problem["b"]
+        if tuple(b_core.shape) != b0.rcap:
+            raise ValueError("b_core must have the shape of problem['b'].core")
+        b = Tucker(b_core.detach().to(dtype=torch.float64, device=b0.core.device).contiguous(), b0.U, b0.ranks)
+        x, info = solve(op, b, problem["S"], problem["omega"], problem["prm"])
+        if info["status"] not in _OK_STATUS:
+            raise RuntimeError(f"forward solve ended with status {info['status_name']} "
+                               f"(true relative residual {info['true_relres']:.3e})")
         xt = problem["x_target"]
         loss = 0.5 * norm([(1.0, x), (-1.0, xt)]) ** 2
         ctx.problem = problem
         ctx.op = op
         ctx.x = x
+        ctx.b = b
+        ctx.meta = (alpha.dtype, alpha.device, b_core.dtype, b_core.device)
         problem["x"] = x
         problem["forward_info"] = info
-        return torch.tensor(loss, dtype=torch.float64)
+        return torch.tensor(loss, dtype=torch.float64, device=alpha.device)
 
     @staticmethod
     def backward(ctx, g):
         p = ctx.problem
+        adt, adev, bdt, bdev = ctx.meta
         lam, dalpha, _, info = backward(ctx.op, ctx.x, [(1.0, ctx.x), (-1.0, p["x_target"])], p["S"], p["omega"],
                                         p["prm"], want_dA=False)
+        if info["status"] not in _OK_STATUS:
+            raise RuntimeError(f"adjoint solve ended with status {info['status_name']} "
+                               f"(true relative residual {info['true_relres']:.3e})")
         p["lambda"] = lam
         p["backward_info"] = info
-        return g * torch.from_numpy(dalpha), None
+        gs = g.detach().to(torch.float64)
+        dal = (torch.as_tensor(dalpha, dtype=torch.float64, device=gs.device) * gs).to(dtype=adt, device=adev)
+        db = None
+        if ctx.needs_input_grad[1]:
+            db = (project_core(lam, ctx.b.U) * gs.to(lam.core.device)).to(dtype=bdt, device=bdev)
+        return dal, db, None
 
 
 KERNEL_CLASSES = {"gemm": 0, "jacobi": 1, "qr": 2, "krp": 3, "ls": 4, "eigvals": 5, "tikhonov": 6}
@@ -520,7 +557,9 @@ def mln_solve(op: KronOp, b: Tucker, Psi: Sequence[torch.Tensor], prm: MlnParams
     ps = prm.struct()
     nb = C.c_size_t()
     check(lib.tsgmres_mln_solve_workspace(C.byref(ops), C.byref(bst), C.byref(ps), C.byref(nb)))
-    ws = workspace if workspace is not None and workspace.numel() >= nb.value else _workspace(nb.value, b.core.device)
+    # a caller's workspace is used as given: one that is too small makes the
+    # library fail with TK_ERR_WORKSPACE before anything is launched
+    ws = workspace if workspace is not None else _workspace(nb.value, b.core.device)
     x = Tucker.empty(b.n, (prm.r,) * b.d, b.core.device)
     xs = x.struct()
     info, keep = _info(prm.maxiter + 8)

@@ -189,6 +189,61 @@ int do_apply(const tk_kron_op* op, const tk_tucker* x, int transpose, int form, 
   return 0;
 }
 
+// Finiteness check of the inputs of a solve, run before any other kernel
+// reads them: a non-finite entry makes the call fail with TK_ERR_NONFINITE.
+// Tensors are checked after their import into the capacity layout, where the
+// entries beyond the ranks are zero.
+struct FiniteCheck {
+  std::vector<const double*> ptr;
+  std::vector<size_t> len;
+  const double** dptr = nullptr;
+  size_t* dlen = nullptr;
+  int* count = nullptr;
+  void add(const double* p, size_t n) {
+    if (p != nullptr && n > 0) {
+      ptr.push_back(p);
+      len.push_back(n);
+    }
+  }
+  void add_tt(const Shape& sh, const TT<double>& t) {
+    add(t.core, sh.core_len());
+    for (int k = 0; k < sh.d; ++k) add(t.U[k], size_t(sh.n[k]) * sh.rc);
+  }
+  void add_inputs(const Shape& sh, const tk_kron_op* op, const double* const* S, int64_t s,
+                  const double* const* omega, int wo, const tk_sgmres_params* prm) {
+    const int d = sh.d;
+    for (int j = 0; j < op->nterms; ++j)
+      for (int k = 0; k < d; ++k) add(op->A[j * d + k], size_t(sh.n[k]) * sh.n[k]);
+    for (int k = 0; k < d; ++k) {
+      if (S) add(S[k], size_t(sh.n[k]) * size_t(s));
+      add(omega[k], size_t(sh.n[k]) * size_t(wo));
+      if (prm->precond_q > 0 && prm->precond_V && prm->precond_lambda) {
+        add(prm->precond_V[k], size_t(sh.n[k]) * sh.n[k]);
+        add(prm->precond_lambda[k], size_t(sh.n[k]));
+      }
+    }
+  }
+  void alloc(Arena& ar) {
+    dptr = ar.alloc<const double*>(std::max<size_t>(ptr.size(), 1));
+    dlen = ar.alloc<size_t>(std::max<size_t>(len.size(), 1));
+    count = ar.alloc<int>(1);
+  }
+  void run(hipStream_t st) const {
+    if (ptr.empty()) return;
+    TK_HIP(hipMemcpyAsync(dptr, ptr.data(), sizeof(const double*) * ptr.size(), hipMemcpyHostToDevice, st));
+    TK_HIP(hipMemcpyAsync(dlen, len.data(), sizeof(size_t) * len.size(), hipMemcpyHostToDevice, st));
+    size_t mx = 0;
+    for (size_t l : len) mx = std::max(mx, l);
+    count_nonfinite(dptr, dlen, int(ptr.size()), mx, count, st);
+    int h = 0;
+    TK_HIP(hipMemcpyAsync(&h, count, sizeof(int), hipMemcpyDeviceToHost, st));
+    TK_HIP(hipStreamSynchronize(st));
+    TK_CHECK(h == 0, kErrNonFinite,
+             std::to_string(h) + " non-finite input entries (right-hand side, initial guess, operator, sketches "
+                                 "or preconditioner)");
+  }
+};
+
 // ---------------------------------------------------------------- block sums
 struct Imported {
   Shape sh;
@@ -442,9 +497,15 @@ int do_solve(const tk_kron_op* op, const tk_tucker* b, const tk_sgmres_params* p
   }
   auto solver = make_solver(ar, sh, op_dev(op), bi, solve_cfg(prm), Sk, Ok, prm->x0 ? &x0i : nullptr, st,
                             precond_of(prm, d));
+  FiniteCheck fin;
+  fin.add_tt(sh, bi);
+  if (prm->x0) fin.add_tt(sh, x0i);
+  fin.add_inputs(sh, op, S, prm->s, omega, sh.sc(), prm);
+  fin.alloc(ar);
   if (ar.measuring()) return 0;
   TK_CHECK(x != nullptr, kErrInvalidArg, "x is NULL");
   imp.run(st);
+  fin.run(st);
   TT<double> xo;
   SolveInfo si;
   solver_run(*solver, xo, si, st);
@@ -478,14 +539,18 @@ int do_backward(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xb
   Shape sh = shape_of(d, x->n, rc, prm->rank_cap, prm->oversample);
   Blob blob;
   Planner pl(ar, blob);
-  Seq pre, post;
+  Seq imp, pre, post;
   // import x and the cotangent blocks, round the cotangent (FP64)
   TT<double> xi = alloc_tt<double>(ar, sh);
-  emit_import<double>(pre, sh, *x, xi);
+  emit_import<double>(imp, sh, *x, xi);
+  FiniteCheck fin;
+  fin.add_tt(sh, xi);
   Blocks<double> xb;
   for (int b = 0; b < xbar->nblocks; ++b) {
     TT<double> t = alloc_tt<double>(ar, sh);
-    emit_import<double>(pre, sh, xbar->blocks[b], t);
+    emit_import<double>(imp, sh, xbar->blocks[b], t);
+    fin.add_tt(sh, t);
+    TK_CHECK(std::isfinite(xbar->coef[b]), kErrNonFinite, "cotangent coefficient is not finite");
     xb.add(t, nullptr, xbar->coef[b]);
   }
   std::array<const double*, kMaxD> Sk{}, Ok{};
@@ -536,8 +601,12 @@ int do_backward(const tk_kron_op* op, const tk_tucker* x, const tk_block_sum* xb
                           -op->alpha[j], 0.0);
       }
   }
+  fin.add_inputs(sh, op, S, prm->s, omega, sh.sc(), prm);
+  fin.alloc(ar);
   finish_blob(ar, blob, st);
   if (ar.measuring()) return 0;
+  imp.run(st);
+  fin.run(st);
   pre.run(st);
   TT<double> lam;
   SolveInfo si;

@@ -46,6 +46,10 @@ void scale_copy(const T* x, T* y, size_t len, double scale, const double* num, c
                 hipStream_t st);
 template <typename T>
 void fill(T* y, size_t len, T v, hipStream_t st);
+// *count = number of non-finite entries over the arrays xs[t] (length lens[t],
+// device tables of ntasks entries, maxlen >= every length).
+void count_nonfinite(const double* const* xs, const size_t* lens, int ntasks, size_t maxlen, int* count,
+                     hipStream_t st);
 template <typename A, typename B>
 void cast_copy(const A* x, B* y, size_t len, hipStream_t st);
 // Copy a d-way core between capacity layouts: src has layout dims sd[] of

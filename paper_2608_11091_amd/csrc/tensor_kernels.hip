@@ -171,6 +171,17 @@ __global__ void fill_kernel(T* y, size_t len, T v) {
     y[e] = v;
 }
 
+// Counts the non-finite entries of every task's array into *count (zeroed by
+// the caller); one atomic per non-finite entry found.
+__global__ void nonfinite_kernel(const double* const* xs, const size_t* lens, int ntasks, int* count) {
+  const int t = blockIdx.y;
+  if (t >= ntasks) return;
+  const double* x = xs[t];
+  const size_t len = lens[t];
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(x[e])) atomicAdd(count, 1);
+}
+
 template <typename A, typename B>
 __global__ void cast_kernel(const A* __restrict__ x, B* __restrict__ y, size_t len) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
@@ -293,6 +304,16 @@ void dot_batched(const T* const* xs, const T* const* ys, size_t len, int n, doub
 template <typename T>
 void scale_copy(const T* x, T* y, size_t len, double scale, const double* num, const double* den, hipStream_t st) {
   hipLaunchKernelGGL((scale_kernel<T>), dim3(grid_for(len)), dim3(256), 0, st, x, y, len, scale, num, den);
+  TK_LAUNCH_CHECK();
+}
+
+void count_nonfinite(const double* const* xs, const size_t* lens, int ntasks, size_t maxlen, int* count,
+                     hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(fill_kernel<int>, dim3(1), dim3(64), 0, st, count, size_t(1), 0);
+  TK_LAUNCH_CHECK();
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(std::min<unsigned>(grid_for(maxlen), 256u), ntasks), dim3(256), 0, st, xs,
+                     lens, ntasks, count);
   TK_LAUNCH_CHECK();
 }
 

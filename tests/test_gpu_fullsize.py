@@ -10,10 +10,15 @@ restart cycle (the oracle's cost grows with every cycle); properties that hold
 at any size (reported residual against an independent evaluation, orthonormal
 factors, monotone sketched residual, finite-difference gradients) cover the
 reduced-precision form and the adjoint."""
+import dataclasses
+
 import numpy as np
 import pytest
 
 import oracle as O
+from workloads import laplacian_eigenpairs
+
+from _spread import cholesky_qr3, first_divergence, history_bound, perturbed_rhs
 
 pytestmark = pytest.mark.gpu
 
@@ -115,14 +120,15 @@ def test_fullsize_orthogonalisation_roundsum(tk):
 def test_fullsize_deblur_first_cycle_fp64(tk):
     # One FP64 cycle of the benchmark workload (d = 3, n = 512, cap 48, 60
     # iterations, k_trunc 2): same iteration count and per-iteration ranks as
-    # the oracle and sketched residuals within the FP64 bound for the
+    # the oracle, and sketched residuals within the FP64 bound 1e-10 for the
     # iterations before the cap binds.  Once the cap binds, the cut falls
     # inside the core's singular-value continuum, where the kept subspace is
-    # not determined beyond rounding: rounding-level differences in the bases
-    # grow over the remaining iterations (to about 15% by iteration 60), so
-    # there the history is checked for what every valid trajectory shares --
-    # a non-increasing sketched residual at the oracle's level (25%) -- and the
-    # returned tensor's true residual against an independent evaluation.
+    # not determined beyond rounding and the short recurrence amplifies
+    # rounding-level differences.  There the bound is measured (_spread.py):
+    # ten times the oracle's own spread over a one-ulp change of the
+    # right-hand side and over the range-finder basis choice, per iteration
+    # (running maximum), for the sketched residuals, the true residual and the
+    # solution.
     w = _workload(3)
     op = tk.KronOp.from_terms(w.terms)
     b = tk.Tucker.from_numpy(w.b_core, w.b_factors)
@@ -131,23 +137,37 @@ def test_fullsize_deblur_first_cycle_fp64(tk):
     x, info = tk.solve(op, b, [_cm(s) for s in w.S], [_cm(o) for o in w.Omega], prm)
     oprm = O.SGMRESParams(tol=w.tol, eta=w.eta, maxiter=w.maxiter, max_restarts=1, k_trunc=w.k_trunc, cap=w.cap,
                           p=w.p)
-    log = []
-    Xo, oinfo = O.solve(w.terms, O.Tucker(w.b_core, w.b_factors), w.S, w.Omega, oprm, log=log)
+    B = O.Tucker(w.b_core, w.b_factors)
+    log, logp, logc = [], [], []
+    Xo, oinfo = O.solve(w.terms, B, w.S, w.Omega, oprm, log=log)
+    Xp, pinfo = O.solve(w.terms, perturbed_rhs(B), w.S, w.Omega, oprm, log=logp)
+    Xq, qinfo = O.solve(w.terms, B, w.S, w.Omega, dataclasses.replace(oprm, range_basis=cholesky_qr3), log=logc)
     its = [e for e in log if "k" in e]
     assert info["iters"] == oinfo["iters"] == len(its)
     ro = [tuple(e["r2"]) for e in its]
     assert ro == info["ranks"]
     h_o = np.array([e["res"] for e in its])
+    h_p = np.array([e["res"] for e in logp if "k" in e])
+    h_q = np.array([e["res"] for e in logc if "k" in e])
     h_g = np.array(info["hist"])
     below = [i for i, r in enumerate(ro) if max(r) < w.cap]
     nb = (max(below) + 1) if below else 0
     assert np.max(np.abs(h_g[:nb] - h_o[:nb]), initial=0.0) <= 1e-10
     assert np.all(np.diff(h_g) <= 1e-12 * h_g[:-1])
-    assert np.max(np.abs(h_g - h_o) / h_o) <= 0.25
-    assert abs(info["true_relres"] / oinfo["true_relres"] - 1.0) <= 0.25
-    # the reported true residual is the residual of the returned tensor
+    bound = history_bound(h_o, [h_p, h_q])
+    dev = np.abs(h_g - h_o) / h_o
+    spread_t = max(abs(i["true_relres"] / oinfo["true_relres"] - 1.0) for i in (pinfo, qinfo))
+    dev_t = abs(info["true_relres"] / oinfo["true_relres"] - 1.0)
     X = _cpu(tk, x)
-    B = O.Tucker(w.b_core, w.b_factors)
+    spread_x, dev_x = max(_dist(Xp, Xo), _dist(Xq, Xo)), _dist(X, Xo)
+    print(f"deblur n=512 cycle: cap binds from iteration {nb}; first divergence above 1e-10 at "
+          f"{first_divergence(h_g, h_o)}; sketched residuals max dev {dev.max():.2e} (oracle spread x10 "
+          f"{bound.max():.2e}); true residual dev {dev_t:.2e} (spread {spread_t:.2e}); solution dev {dev_x:.2e} "
+          f"(spread {spread_x:.2e})", flush=True)
+    assert np.all(dev <= bound), np.nonzero(dev > bound)[0]
+    assert dev_t <= max(1e-10, 10 * spread_t)
+    assert dev_x <= max(1e-10, 10 * spread_x)
+    # the reported true residual is the residual of the returned tensor
     rel = O.exact_norm([(1.0, B)] + [(-c, T) for c, T in O.apply_op(w.terms, X)]) / O.exact_norm([(1.0, B)])
     assert abs(rel / info["true_relres"] - 1.0) <= 1e-8
 
@@ -242,7 +262,7 @@ def test_gradient_central_differences_fullsize_preconditioned(tk):
     S = [_cm(s) for s in w.S]
     Om = [_cm(o) for o in w.Omega]
     b = tk.Tucker.from_numpy(w.b_core, w.b_factors, rcap=(w.cap,) * 3)
-    Vs, lams = tk.laplacian_precond((n,) * 3)
+    Vs, lams = tk.precond_tensors(*laplacian_eigenpairs((n,) * 3))
 
     def prm_of(th, cap):
         return tk.SolveParams(form=0, tol=1e-12, eta=w.eta, maxiter=40, max_restarts=4, k_trunc=w.k_trunc,

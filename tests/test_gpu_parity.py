@@ -6,10 +6,14 @@ inputs, through the C ABI.  Tolerances:
   * rank decisions (sketch width, output ranks): bit-exact, or replayed from
     the oracle where the test says so.
 Sizes span several 64-wide GEMM tiles with ragged tails (n = 77, 130, ...)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
 import oracle as O
+
+from _spread import cholesky_qr3, first_divergence, history_bound, perturbed_rhs
 
 pytestmark = pytest.mark.gpu
 
@@ -224,9 +228,26 @@ def test_solve_config1_parity_fp64(tk):
     # histories are fractions of ||b_s||: absolute differences are residual
     # differences relative to ||b||, held to the FP64 parity bound 1e-10
     assert np.max(np.abs(h_g[:n1] - h_o[:n1])) <= 1e-10
-    assert np.max(np.abs(h_g[n1:] - h_o[n1:]) / h_o[n1:]) <= 5e-2
+    # later cycles: 10x the oracle's own spread over a one-ulp change of the
+    # right-hand side and over the range-finder basis choice (running maximum
+    # per iteration and per cycle; _spread.py)
+    logp, logq = [], []
+    Xp, pinfo = O.solve(w.terms, perturbed_rhs(O.Tucker(w.b_core, w.b_factors)), w.S, w.Omega, oprm, log=logp)
+    Xq, qinfo = O.solve(w.terms, O.Tucker(w.b_core, w.b_factors), w.S, w.Omega,
+                        dataclasses.replace(oprm, range_basis=cholesky_qr3), log=logq)
+    h_p = np.array([e["res"] for e in logp if "k" in e])
+    h_q = np.array([e["res"] for e in logq if "k" in e])
+    assert len(h_p) == len(h_o) == len(h_q)
+    bound = history_bound(h_o, [h_p, h_q])
+    dev = np.abs(h_g - h_o) / h_o
+    tb = history_bound(oinfo["true_hist"], [pinfo["true_hist"], qinfo["true_hist"]])
+    tdev = np.abs(np.array(info["true_hist"]) - np.array(oinfo["true_hist"])) / np.array(oinfo["true_hist"])
+    print(f"config 1 cap 16: first divergence above 1e-10 at iteration {first_divergence(h_g, h_o)}; "
+          f"later-cycle max dev {dev[n1:].max(initial=0):.2e} (bound {bound[n1:].max(initial=0):.2e}); "
+          f"true residual devs {tdev} (bounds {tb})", flush=True)
+    assert np.all(dev <= bound), np.nonzero(dev > bound)[0]
     assert abs(info["true_hist"][0] - oinfo["true_hist"][0]) <= 1e-6 * oinfo["true_hist"][0]
-    assert np.allclose(info["true_hist"], oinfo["true_hist"], rtol=5e-2)
+    assert np.all(tdev <= np.maximum(tb, 1e-6))
     assert info["true_relres"] <= 1e-8
     # both solutions have relative residual <= 1e-8, so they differ by at most
     # 2 kappa(L) 1e-8 relative (L = Kronecker sum of 1D Laplacians)

@@ -11,6 +11,7 @@ import pytest
 
 import oracle as O
 from oracle import precond as P
+from workloads import laplacian_eigenpairs
 
 pytestmark = pytest.mark.gpu
 
@@ -49,7 +50,7 @@ def test_preconditioned_solve_parity(tk, n, q, form):
     oprm = O.SGMRESParams(tol=1e-8, maxiter=40, k_trunc=2, cap=cap, p=p, max_restarts=6)
     Xo, oi = O.solve(terms, B, S, Om, oprm, precond=lambda V, rf: P.precond_apply(V, eig, q, rf))
     prm = tk.SolveParams(form=form, tol=1e-8, eta=0.4, maxiter=40, k_trunc=2, rank_cap=cap, oversample=p,
-                         max_restarts=6, precond_q=q, precond=tk.laplacian_precond((n,) * 3))
+                         max_restarts=6, precond_q=q, precond=tk.precond_tensors(*laplacian_eigenpairs((n,) * 3)))
     x, info = tk.solve(tk.KronOp.from_terms(terms), tk.Tucker.from_numpy(B.core, B.U, rcap=(cap,) * 3),
                        [_cm(a) for a in S], [_cm(a) for a in Om], prm)
     print(f"precond n={n} q={q} form={form}: gpu iters {info['iters']} cycles {info['cycles']} "
@@ -103,7 +104,7 @@ def test_update_truncation_tightening_parity(tk, n):
     oprm = O.SGMRESParams(tol=1e-8, maxiter=60, k_trunc=2, cap=cap, p=p, max_restarts=8)
     Xo, oi = O.solve(terms, B, S, Om, oprm, precond=lambda V, rf: P.precond_apply(V, eig, q, rf))
     prm = tk.SolveParams(tol=1e-8, maxiter=60, k_trunc=2, rank_cap=cap, oversample=p, max_restarts=8,
-                         precond_q=q, precond=tk.laplacian_precond((n,) * 3))
+                         precond_q=q, precond=tk.precond_tensors(*laplacian_eigenpairs((n,) * 3)))
     x, info = tk.solve(tk.KronOp.from_terms(terms), tk.Tucker.from_numpy(B.core, B.U, rcap=(cap,) * 3),
                        [_cm(a) for a in S], [_cm(a) for a in Om], prm)
     print(f"tightening n={n}: gpu {info['status_name']} iters {info['iters']} cycles {info['cycles']} hist "
@@ -114,3 +115,41 @@ def test_update_truncation_tightening_parity(tk, n):
     assert abs(info["true_hist"][0] / oi["true_hist"][0] - 1) <= 1e-4
     assert np.allclose(info["true_hist"], oi["true_hist"], rtol=5e-2)
     assert info["true_relres"] <= 1e-8
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_preconditioned_fullsize_fp32_against_fp64_oracle(tk, form):
+    # The benchmark's preconditioned leg at its size (3D Poisson, n = 512,
+    # q = 49, rank cap 48, k_trunc 1, 40 iterations, s = 80): both forms
+    # reach the tolerance after FP64 refinement, and each solution lies within
+    # the conditioning bound of the FP64 oracle's solution,
+    # ||x - x_oracle|| / ||x_oracle|| <= kappa(L) (res + res_oracle), with
+    # kappa(L) = (1 + cos(pi/(n+1))) / (1 - cos(pi/(n+1))) ~ 1.07e5.
+    from workloads import draw_sketches, laplacian_1d
+    n, cap, p, q, maxiter = 512, 48, 5, 49, 40
+    L = laplacian_1d(n)
+    terms = [(1.0, [L if j == k else None for j in range(3)]) for k in range(3)]
+    e1 = np.zeros((n, 1))
+    e1[0] = 1.0
+    B = O.Tucker(np.ones((1, 1, 1)), [np.ones((n, 1)) / np.sqrt(n), e1, e1])
+    S, Om = draw_sketches([n] * 3, 2 * maxiter, cap, p, seed=0)
+    eig = [P.laplacian_eig(n)] * 3
+    Xo, oi = O.solve(terms, B, S, Om, O.SGMRESParams(tol=1e-8, eta=0.4, maxiter=maxiter, k_trunc=1, cap=cap, p=p,
+                                                    max_restarts=8),
+                     precond=lambda V, rf: P.precond_apply(V, eig, q, rf))
+    prm = tk.SolveParams(form=form, tol=1e-8, eta=0.4, maxiter=maxiter, k_trunc=1, rank_cap=cap, oversample=p,
+                         max_restarts=8, precond_q=q, precond=tk.precond_tensors(*laplacian_eigenpairs((n,) * 3)))
+    x, info = tk.solve(tk.KronOp.from_terms(terms), tk.Tucker.from_numpy(B.core, B.U, rcap=(cap,) * 3),
+                       [_cm(a) for a in S], [_cm(a) for a in Om], prm)
+    X = O.Tucker(*x.to_numpy())
+    res = O.exact_norm([(1.0, B)] + [(-c, T) for c, T in O.apply_op(terms, X)]) / O.exact_norm([(1.0, B)])
+    c = np.cos(np.pi / (n + 1))
+    kappa = (1 + c) / (1 - c)
+    dist = O.exact_norm([(1.0, X), (-1.0, Xo)]) / O.exact_norm([(1.0, Xo)])
+    print(f"precond n=512 form {form}: gpu {info['status_name']} iters {info['iters']} cycles {info['cycles']} "
+          f"true {info['true_relres']:.3e} (oracle evaluation {res:.3e}); oracle iters {oi['iters']} true "
+          f"{oi['true_relres']:.3e}; distance {dist:.2e} (bound {kappa * (res + oi['true_relres']):.2e})", flush=True)
+    assert oi["status"] == 0 and info["status"] == 0
+    assert info["true_relres"] <= 1e-8 and res <= 1e-8
+    assert abs(res / info["true_relres"] - 1.0) <= 1e-6
+    assert dist <= kappa * (res + oi["true_relres"])

@@ -49,3 +49,14 @@ def test_deblur_gcv_problem_compression(tmp_path, monkeypatch):
     # cached: the same arrays come back
     K2, (core2, Q2), _ = W.deblur_gcv_problem(n=20, rank_b=6, seed=1)
     assert np.array_equal(core, core2) and all(np.array_equal(a, b) for a, b in zip(Q, Q2))
+
+
+def test_laplacian_eigenpairs_diagonalise_the_1d_laplacian():
+    # the closed-form DST-I pairs handed to the GPU preconditioner: V^T V = I
+    # and V diag(lambda) V^T = (n+1)^2 tridiag(-1, 2, -1)
+    from workloads import laplacian_1d, laplacian_eigenpairs
+    Vs, lams = laplacian_eigenpairs([7, 16])
+    for V, lam, n in zip(Vs, lams, [7, 16]):
+        assert np.allclose(V.T @ V, np.eye(n), atol=1e-13)
+        L = laplacian_1d(n)
+        assert np.linalg.norm(V @ np.diag(lam) @ V.T - L) <= 1e-12 * np.linalg.norm(L)

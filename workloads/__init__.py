@@ -87,6 +87,20 @@ def laplacian_1d(n: int) -> np.ndarray:
     return L * float(n + 1) ** 2
 
 
+def laplacian_eigenpairs(n: Sequence[int]):
+    """Eigenpairs of ``laplacian_1d(n_k)`` for every mode in closed form (the
+    DST-I basis): ``V[i, j] = sqrt(2/(n+1)) sin((i+1)(j+1) pi/(n+1))`` and
+    ``lambda_j = 4 (n+1)^2 sin^2((j+1) pi/(2(n+1)))``.  Input data of the
+    exponential-sum preconditioner of Sec. 3.4 on the GPU path; returns
+    ``([V_k], [lambda_k])`` as NumPy arrays."""
+    Vs, lams = [], []
+    for nk in n:
+        i = np.arange(1, nk + 1)
+        Vs.append(np.sqrt(2.0 / (nk + 1)) * np.sin(np.outer(i, i) * np.pi / (nk + 1)))
+        lams.append(4.0 * (nk + 1) ** 2 * np.sin(i * np.pi / (2 * (nk + 1))) ** 2)
+    return Vs, lams
+
+
 def centered_difference_1d(n: int) -> np.ndarray:
     """(n+1)/2 * tridiag(-1, 0, +1): centred first difference, sub-diagonal
     -1 and super-diagonal +1."""
