@@ -172,6 +172,19 @@ int tucker_sketch(const tk_block_sum* x, const double* const* S, int64_t s, int3
                   size_t ws_bytes, void* stream);
 int tucker_sketch_workspace(const tk_block_sum* x, int64_t s, int32_t form, size_t* bytes);
 
+/* Allocation-free variant of tucker_sketch, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, result and errors as tucker_sketch,
+ * without the workspace: its temporaries live in a static device array of
+ * 64 MiB that the library holds on every GPU it runs on until the process
+ * ends.  A call whose workspace query (tucker_sketch_workspace) exceeds
+ * 64 MiB launches nothing and returns TK_ERR_WORKSPACE.  The call allocates
+ * no device memory (no hipMalloc / hipFree).  All calls on one GPU share that
+ * array: calls that overlap in time on the same GPU (different streams or
+ * host threads) race and must be serialised by the caller. */
+int tucker_sketch_noalloc(const tk_block_sum* x, const double* const* S, int64_t s, int32_t form, double* out,
+                          void* stream);
+
 /* RoundSum (Sec. 3.1): randomized RHOSVD recompression of a block sum into
  * `out` (ranks written to out->r; out->rcap must hold them).  *s_out (host,
  * optional) receives the sketch width used. */
@@ -310,8 +323,9 @@ int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, doub
 const char* tk_last_error(void);
 /* ABI version (major * 100 + minor).  2.0 (200): tk_sgmres_params gained
  * tikhonov and method, tk_mln_params gained tikhonov, tk_sgmres_info gained
- * hist_lambda (all appended), and tsgmres_projected_tikhonov was added. */
-#define TK_ABI_VERSION 200
+ * hist_lambda (all appended), and tsgmres_projected_tikhonov was added.
+ * 2.1 (201): tucker_sketch_noalloc was added. */
+#define TK_ABI_VERSION 201
 int tk_version(void);
 
 #ifdef __cplusplus

@@ -18,10 +18,11 @@ ERRORS = {-1: "invalid argument", -2: "shape", -3: "capacity", -4: "workspace", 
           -6: "non-finite", -7: "unsupported"}
 
 # the structures below mirror include/tsgmres.h at this ABI version
-ABI_VERSION = 200
+ABI_VERSION = 201
 
 EXPORTS = [
     "tucker_apply_op", "tucker_apply_op_workspace", "tucker_sketch", "tucker_sketch_workspace",
+    "tucker_sketch_noalloc",
     "tucker_rhosvd", "tucker_rhosvd_workspace", "tsgmres_solve", "tsgmres_solve_workspace",
     "tsgmres_backward", "tsgmres_backward_workspace", "tucker_norm", "tucker_norm_workspace",
     "tucker_mln_sketch", "tucker_mln_sketch_workspace", "tucker_mln_recover", "tucker_mln_recover_workspace",
@@ -90,6 +91,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.tucker_apply_op_workspace.argtypes = [P(TkKronOp), P(TkTucker), C.c_int32, P(SZ)]
     lib.tucker_sketch.argtypes = [P(TkBlockSum), P(VP), C.c_int64, C.c_int32, VP, VP, SZ, VP]
     lib.tucker_sketch_workspace.argtypes = [P(TkBlockSum), C.c_int64, C.c_int32, P(SZ)]
+    lib.tucker_sketch_noalloc.argtypes = [P(TkBlockSum), P(VP), C.c_int64, C.c_int32, VP, VP]
     lib.tucker_rhosvd.argtypes = [P(TkBlockSum), P(TkRoundParams), P(VP), P(TkTucker), P(C.c_int32), VP, SZ, VP]
     lib.tucker_rhosvd_workspace.argtypes = [P(TkBlockSum), P(TkRoundParams), P(SZ)]
     lib.tsgmres_solve.argtypes = [P(TkKronOp), P(TkTucker), P(TkSgmresParams), P(VP), P(VP), P(TkTucker),

@@ -195,6 +195,20 @@ def sketch(blocks, S: Sequence[torch.Tensor], form: int = 0) -> torch.Tensor:
     return out
 
 
+def sketch_noalloc(blocks, S: Sequence[torch.Tensor], out: torch.Tensor, form: int = 0) -> torch.Tensor:
+    """The Khatri-Rao sketch through the allocation-free entry point: the
+    library uses its static device scratch instead of a workspace; ``out``
+    (float64, length s, on the blocks' device) is written in place."""
+    lib = _abi.load()
+    bs, keep = _blocks_struct(blocks)
+    s = int(S[0].shape[0])
+    if out.dtype != torch.float64 or out.numel() < s or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of length >= s")
+    check(lib.tucker_sketch_noalloc(C.byref(bs), _ptr_array(S), s, int(form), C.c_void_p(out.data_ptr()),
+                                    _stream()))
+    return out
+
+
 def rhosvd(blocks, omega: Sequence[torch.Tensor], eps: float, cap: int, p: int = 5, tau: float = -1.0,
            force_s: int = -1, force_ranks: Optional[Sequence[int]] = None, out_rcap: Optional[Sequence[int]] = None,
            form: int = 0):

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <mutex>
 
 #include "../../include/tsgmres.h"
 #include "engine.hpp"
@@ -796,6 +797,35 @@ using namespace tk;
 
 static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Static device scratch of the allocation-free sketch entry point.  Each GPU
+// the library runs on holds its own copy of this array until the process
+// ends.  In host code the array's name is only a host-side stand-in: kernels
+// and copies get the device address that hipGetSymbolAddress returns for the
+// current device, looked up once per device and kept.
+namespace tk {
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* noalloc_scratch() {
+  int dev = -1;
+  TK_HIP(hipGetDevice(&dev));
+  TK_CHECK(dev >= 0 && dev < kMaxDevices, kErrUnsupported, "device index outside the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    TK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    TK_CHECK(p != nullptr, kErrHip, "hipGetSymbolAddress returned no address for the static scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+}  // namespace tk
+
 extern "C" {
 
 int tucker_apply_op(const tk_kron_op* op, const tk_tucker* x, int32_t transpose, int32_t form, double* const* AU,
@@ -822,6 +852,21 @@ int tucker_sketch(const tk_block_sum* x, const double* const* S, int64_t s, int3
   return guarded([&] {
     TK_CHECK(ws != nullptr, kErrInvalidArg, "workspace pointer is NULL");
     Arena ar(ws, ws_bytes);
+    return do_sketch(x, S, s, form, out, ar, as_stream(stream));
+  });
+}
+int tucker_sketch_noalloc(const tk_block_sum* x, const double* const* S, int64_t s, int32_t form, double* out,
+                          void* stream) {
+  return guarded([&] {
+    {
+      // size check first, so that an oversized call launches nothing
+      Arena probe(nullptr, 0);
+      do_sketch(x, S, s, form, out, probe, nullptr);
+      TK_CHECK(probe.used() <= kNoAllocScratchBytes, kErrWorkspace,
+               "tucker_sketch_noalloc: needs " + std::to_string(probe.used()) +
+                   " bytes of scratch, above its static maximum of " + std::to_string(kNoAllocScratchBytes));
+    }
+    Arena ar(noalloc_scratch(), kNoAllocScratchBytes);
     return do_sketch(x, S, s, form, out, ar, as_stream(stream));
   });
 }
