@@ -34,11 +34,11 @@ HBM_PEAK = 8000.0                        # GB/s
 CLASSES = ["gemm", "jacobi", "qr", "krp", "ls", "eigvals"]
 KERNEL_NAME = {
     "gemm": "gemm_kernel: grouped MFMA GEMM (TTMs, factor products, Grams)",
-    "jacobi": "jacobi_vec_kernel: symmetric eigendecomposition with vectors (ST-HOSVD, two-pass Jacobi)",
+    "jacobi": "jacobi_blk_kernel: symmetric eigendecomposition with vectors (ST-HOSVD, two-pass Jacobi on 2x2 blocks)",
     "qr": "chol_kernel: Cholesky of the range-sketch Gram (Cholesky-QR3)",
     "krp": "krp_kernel: Khatri-Rao / MTTKRP core reductions",
     "ls": "ls_add_kernel: sketched least-squares column update",
-    "eigvals": "tridiag_reg_kernel: eigenvalues for the effective-rank rule",
+    "eigvals": "tridiag_reg_kernel / tridiag_gm_kernel: eigenvalues for the effective-rank rule",
 }
 # FP32 form: eigensolvers and GEMMs inside cycles run in FP32 (vector ALU / MFMA)
 BOUND = {"gemm": ("mfma", PEAK["fp32"]), "jacobi": ("alu", VALU_PEAK), "qr": ("alu", VALU_PEAK),
@@ -471,8 +471,11 @@ def main():
     # (largest summed kernel time) gets the roofline entry
     for k in CLASSES:
         tk.kernel_timer(k, True)
-    tk.solve(op, b, S, Om, prm32, workspace=ws)
+    nl0 = tk.launch_count()
+    _, iprof = tk.solve(op, b, S, Om, prm32, workspace=ws)
     torch.cuda.synchronize()
+    launches_per_solve = tk.launch_count() - nl0
+    empty_us = tk.launch_latency(4000)
     classes = {}
     for k in CLASSES:
         n_, ms_, fl_, _ = tk.kernel_timer_read(k)
@@ -578,6 +581,13 @@ def main():
     if fp64:
         it_roof["fp64_form"] = dict(achieved=fpi * fp64["iters_per_s"] / 1e12, peak=PEAK["fp64"], unit="TFLOP/s",
                                     frac=fpi * fp64["iters_per_s"] / 1e12 / PEAK["fp64"])
+    # launch-latency floor: the solve's kernels are dependent launches on one
+    # stream, so an iteration cannot take less than its launch count times the
+    # empty-kernel latency
+    lpi = launches_per_solve / max(1, iprof["iters"])
+    it_roof["launch_floor"] = dict(launches_per_solve=launches_per_solve, launches_per_iteration=lpi,
+                                   empty_launch_us=empty_us, floor_ms_per_iteration=lpi * empty_us * 1e-3,
+                                   measured_ms_per_iteration=1e3 / value)
     out["iteration_roofline"] = it_roof
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters, args.cpu_iters_1thread)

@@ -319,13 +319,23 @@ int tsgmres_projected_tikhonov_workspace(int32_t s, int32_t k, size_t* bytes);
 int tk_kernel_timer(int32_t kind, int32_t enable);
 int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, double* flops, double* bytes);
 
+/* Kernel launches the library has issued since it was loaded (every launch
+ * of every entry point counts; host only, no device work). */
+int tk_launch_count(int64_t* count);
+/* Empty-kernel launch latency: n launches of an empty kernel back to back on
+ * `stream`, then a synchronisation; *us_per_launch = elapsed microseconds / n.
+ * The floor a sequence of k dependent launches cannot go below is about
+ * k * *us_per_launch. */
+int tk_launch_latency(int32_t n, void* stream, double* us_per_launch);
+
 /* Message of the last error on this thread ("" if none). */
 const char* tk_last_error(void);
 /* ABI version (major * 100 + minor).  2.0 (200): tk_sgmres_params gained
  * tikhonov and method, tk_mln_params gained tikhonov, tk_sgmres_info gained
  * hist_lambda (all appended), and tsgmres_projected_tikhonov was added.
- * 2.1 (201): tucker_sketch_noalloc was added. */
-#define TK_ABI_VERSION 201
+ * 2.1 (201): tucker_sketch_noalloc was added.  2.2 (202): tk_launch_count and
+ * tk_launch_latency were added. */
+#define TK_ABI_VERSION 202
 int tk_version(void);
 
 #ifdef __cplusplus

@@ -485,6 +485,21 @@ def kernel_timer_read(kind: str):
     return int(n.value), float(ms.value), float(fl.value), float(by.value)
 
 
+def launch_count() -> int:
+    """Kernel launches the library has issued since it was loaded."""
+    n = C.c_int64()
+    check(_abi.load().tk_launch_count(C.byref(n)))
+    return int(n.value)
+
+
+def launch_latency(n: int = 2000) -> float:
+    """Microseconds per launch of an empty kernel, n back to back on the
+    current stream."""
+    us = C.c_double()
+    check(_abi.load().tk_launch_latency(int(n), _stream(), C.byref(us)))
+    return float(us.value)
+
+
 def storage_floats(n: Sequence[int], ranks: Sequence[int]) -> int:
     """Floats stored by a Tucker tensor: sum_k n_k r_k + prod_k r_k."""
     return int(sum(a * b for a, b in zip(n, ranks)) + np.prod(ranks))

@@ -1053,6 +1053,21 @@ int tk_kernel_timer_read(int32_t kind, int64_t* launches, double* total_ms, doub
   });
 }
 
+int tk_launch_count(int64_t* count) {
+  return guarded([&] {
+    TK_CHECK(count != nullptr, kErrInvalidArg, "count is NULL");
+    *count = launch_count();
+    return 0;
+  });
+}
+int tk_launch_latency(int32_t n, void* stream, double* us_per_launch) {
+  return guarded([&] {
+    TK_CHECK(n >= 1 && n <= 1000000 && us_per_launch != nullptr, kErrInvalidArg, "bad launch-latency query");
+    *us_per_launch = empty_launch_us(n, as_stream(stream));
+    return 0;
+  });
+}
+
 const char* tk_last_error(void) { return tk::last_error(); }
 int tk_version(void) { return TK_ABI_VERSION; }
 

@@ -56,7 +56,14 @@ struct Error {
     if (!(cond)) throw ::tk::Error{(code), (msg)};                                \
   } while (0)
 
-#define TK_LAUNCH_CHECK() TK_HIP(hipGetLastError())
+// Every kernel launch of the library is followed by this check, which also
+// counts the launch (for the benchmark's launch-latency floor).
+void count_launch();
+#define TK_LAUNCH_CHECK()   \
+  do {                      \
+    ::tk::count_launch();   \
+    TK_HIP(hipGetLastError()); \
+  } while (0)
 
 // ---------------------------------------------------------------- workspace
 // Bump allocator over the caller's workspace.  With a null base it only
@@ -172,6 +179,10 @@ void timer_begin(int kind, hipStream_t st, double flops = 0.0, double bytes = 0.
 void timer_end(int kind, hipStream_t st);
 void timer_enable(int kind, bool on);
 void timer_read(int kind, int64_t* launches, double* total_ms, double* total_flops, double* total_bytes);
+// Kernel launches issued by the library since it was loaded.
+int64_t launch_count();
+// Microseconds per launch of an empty kernel, n launches back to back on st.
+double empty_launch_us(int n, hipStream_t st);
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 inline int64_t ipow(int64_t b, int e) {

@@ -9,11 +9,11 @@
 //    place; each step streams the trailing block once, applying the previous
 //    step's rank-2 update and forming the next product A v in the same pass.
 //  * Eigenvalues and vectors (N <= 64): cyclic Jacobi with the round-robin
-//    parallel ordering, full matrix and eigenvector block in LDS, one lane
-//    per row and one wave per rotation pair.  A rotation is taken only when
-//    |a_pq| > eps * sqrt(|a_pp a_qq|), the relative criterion under which
-//    Jacobi resolves the small eigenvalues of graded positive semidefinite
-//    matrices to high relative accuracy; a sweep without rotations ends it.
+//    parallel ordering on 2 x 2 blocks, full matrix and eigenvector block in
+//    LDS.  A rotation is taken only when |a_pq| > eps * sqrt(|a_pp a_qq|),
+//    the relative criterion under which Jacobi resolves the small eigenvalues
+//    of graded positive semidefinite matrices to high relative accuracy; a
+//    sweep without rotations ends it.
 // Results are sorted in descending order; an optional rank rule (RoundSum
 // effective rank / ST-HOSVD truncation) runs on the sorted spectrum.
 #include <cfloat>
@@ -27,6 +27,10 @@ namespace {
 constexpr int VAL_NMAX = kEigRegMax;
 constexpr int VEC_NMAX = 64;
 constexpr int GM_NMAX = 512;
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float __attribute__((ext_vector_type(4))); };
+template <> struct Vec4<double> { using type = double __attribute__((ext_vector_type(4))); };
 
 template <typename T> struct Lim;
 template <> struct Lim<double> {
@@ -186,6 +190,7 @@ __global__ __launch_bounds__(TRG_NT) void tridiag_reg_kernel(const EigTask<T>* _
   constexpr int TRG_NW = TRG_NT / kWave;                   // waves
   constexpr int TRG_RC = (VAL_NMAX + TRG_NW - 1) / TRG_NW;  // columns per thread
   const EigTask<T> tk_ = tasks[blockIdx.x];
+  if (tk_.skip != nullptr && *tk_.skip != 0) return;  // the other task of the pair decides
   int N = NL;
   if (tk_.ndyn != nullptr) {
     const int nd = *tk_.ndyn;
@@ -365,6 +370,7 @@ __global__ __launch_bounds__(1024) void tridiag_gm_kernel(const EigTask<T>* __re
   constexpr int NW = NT / kWave;          // 16 waves
   constexpr int RCH = GM_NMAX / kWave;    // row chunks of 64
   const EigTask<T> tk_ = tasks[blockIdx.x];
+  if (tk_.skip != nullptr && *tk_.skip != 0) return;  // the other task of the pair decides
   int N = NL;
   if (tk_.ndyn != nullptr) {
     const int nd = *tk_.ndyn;
@@ -380,6 +386,9 @@ __global__ __launch_bounds__(1024) void tridiag_gm_kernel(const EigTask<T>* __re
   }
   T* A = const_cast<T*>(tk_.A);
   const size_t lda = size_t(tk_.lda);
+  using T4 = typename Vec4<T>::type;
+  T* const W = A;          // the trailing-block pass reads columns as 16-byte vectors
+  const size_t ldw = lda;  // (lda is a multiple of 4 and A 16-byte aligned: checked by the launcher)
   __shared__ T xb[GM_NMAX], vp[GM_NMAX], wp[GM_NMAX];
   __shared__ T rowp[NW][GM_NMAX];  // per-wave row sums; also the mirror tiles
   __shared__ T part[NW], qpart[NW];
@@ -443,45 +452,70 @@ __global__ __launch_bounds__(1024) void tridiag_gm_kernel(const EigTask<T>* __re
     auto vval = [&](int i) -> T {  // Householder vector entry (0 outside j+1..N-1)
       return i == j + 1 ? vmask : (i > j + 1 && i < N ? xb[i] * scal : T(0));
     };
-    // ---- 2. pass over the trailing block
+    // ---- 2. pass over the trailing block: lane l owns rows 4l + 256u .. +3
+    //         (u < 2), 16-byte accesses; several columns per wave in flight
     const int r0 = j + 1;
-    const int t0 = r0 / kWave;  // first row chunk touched (uniform)
-    T vpr[RCH], wpr[RCH], vr[RCH], acc[RCH];
+    T4 vpr[2], wpr[2], acc[2];
+    bool live[2];
 #pragma unroll
-    for (int t = 0; t < RCH; ++t) {
-      const int i = t * kWave + lane;
-      const bool ok = i >= r0 && i < N;
-      vpr[t] = ok ? vp[i] : T(0);
-      wpr[t] = ok ? wp[i] : T(0);
-      vr[t] = ok ? vval(i) : T(0);
-      acc[t] = T(0);
+    for (int u = 0; u < 2; ++u) {
+      const int rb = 4 * lane + 256 * u;
+      live[u] = rb < N && rb + 3 >= r0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = rb + e;
+        const bool ok = i >= r0 && i < N;
+        vpr[u][e] = ok ? vp[i] : T(0);
+        wpr[u][e] = ok ? wp[i] : T(0);
+        acc[u][e] = T(0);
+      }
     }
-    for (int c = r0 + wave; c < N; c += NW) {
-      const T vpc = vp[c], wpc = wp[c], vc = vval(c);
-      T* col = A + size_t(c) * lda;
-      T a[RCH];
+    constexpr int CU = sizeof(T) == 4 ? 4 : 2;  // columns in flight per wave (FP64: register budget)
+    for (int c0 = r0 + wave; c0 < N; c0 += CU * NW) {
+      T4 a[CU][2];
+      T vpc[CU], wpc[CU], vc[CU];
 #pragma unroll
-      for (int t = 0; t < RCH; ++t) {
-        const int i = t * kWave + lane;
-        a[t] = (t >= t0 && i >= r0 && i < N) ? col[i] : T(0);
+      for (int m = 0; m < CU; ++m) {
+        const int c = c0 + m * NW;
+        const bool cok = c < N;  // uniform across the wave
+        vpc[m] = cok ? vp[c] : T(0);
+        wpc[m] = cok ? wp[c] : T(0);
+        vc[m] = cok ? vval(c) : T(0);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const T4* src = reinterpret_cast<const T4*>(W + size_t(cok ? c : r0) * ldw + 4 * lane + 256 * u);
+          a[m][u] = (cok && live[u]) ? *src : T4{};
+        }
       }
 #pragma unroll
-      for (int t = 0; t < RCH; ++t) {
-        const int i = t * kWave + lane;
-        if (t >= t0 && i >= r0 && i < N) {
-          const T v = a[t] - (vpr[t] * wpc + wpr[t] * vpc);
-          col[i] = v;
-          acc[t] += v * vc;
+      for (int m = 0; m < CU; ++m) {
+        const int c = c0 + m * NW;
+        if (c >= N) continue;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (!live[u]) continue;
+          const int rb = 4 * lane + 256 * u;
+          T4 v = a[m][u] - (vpr[u] * wpc[m] + wpr[u] * vpc[m]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const bool ok = rb + e >= r0 && rb + e < N;
+            v[e] = ok ? v[e] : a[m][u][e];
+            acc[u][e] += ok ? v[e] * vc[m] : T(0);
+          }
+          *reinterpret_cast<T4*>(W + size_t(c) * ldw + rb) = v;
         }
       }
     }
     T q = T(0);
 #pragma unroll
-    for (int t = 0; t < RCH; ++t) {
-      q += vr[t] * acc[t];
-      const int i = t * kWave + lane;
-      if (i >= r0 && i < N) rowp[wave][i] = acc[t];
-    }
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 4 * lane + 256 * u + e;
+        const bool ok = i >= r0 && i < N;
+        q += ok ? vval(i) * acc[u][e] : T(0);
+        if (ok) rowp[wave][i] = acc[u][e];
+      }
     q = wave_sum(q);
     if (lane == 0) qpart[wave] = q;
     __syncthreads();
@@ -516,7 +550,6 @@ __global__ __launch_bounds__(1024) void tridiag_gm_kernel(const EigTask<T>* __re
 }
 
 // ------------------------------------------------------------ eigenvalues + vectors
-__device__ __forceinline__ int player(int s, int t, int NP) { return s == 0 ? 0 : ((s - 1 + t) % (NP - 1)) + 1; }
 
 
 // Jacobi rotation annihilating a_pq: t = tan(phi), c = cos(phi).  FP32 uses
@@ -540,147 +573,205 @@ __device__ __forceinline__ void jac_rot(double app, double aqq, double apq, doub
 }
 
 
-// One lane per matrix row, one wave per rotation pair.  A round applies the
-// N/2 disjoint rotations of the round-robin ordering as A <- J^T (A J): first
-// the column pairs (p, q) from A into the second buffer B = A J (and V <- V J
-// in place), then the row pairs from B back into A (rows of different pairs
-// are disjoint), with the 2x2 pivot blocks set to their exact diagonal form.
-// Every wave computes all angles of the round in its lanes from A, which no
-// wave writes between the row phase of one round and the row phase of the
-// next, so every wave sees the same values and takes identical decisions
-// (which pairs rotate, whether the round and the sweep rotate anything); a
-// round in which no pair rotates is skipped by all waves together, barriers
-// included.  A wave issues the loads of all its pairs before any store, and an
-// executed round has two barriers.
-template <typename T, int JV_NT>
-__global__ __launch_bounds__(JV_NT) void jacobi_vec_kernel(const EigTask<T>* __restrict__ tasks, int N) {
-  constexpr int JV_NW = JV_NT / kWave;
-  constexpr int JV_PPW = (VEC_NMAX / 2) / JV_NW;  // pair slots per wave
-  constexpr int LD = VEC_NMAX + 1;
-  __shared__ T AV[3][VEC_NMAX][LD];  // A = AV[0], V = AV[1], B = AV[2], all [col][row]
-  auto& A = AV[0];
-  auto& V = AV[1];
-  auto& B = AV[2];
+// Two-sided cyclic Jacobi on 2 x 2 blocks.  With the round-robin ordering a
+// round applies N/2 disjoint rotations J, A <- J^T A J; every entry of A
+// belongs to exactly one block (rows of pair I) x (columns of pair J), and the
+// block's new value depends on that block and the two rotations only.  One
+// thread per block with I <= J updates it in place and writes the mirrored
+// block (J, I) too, so A stays exactly symmetric (full storage, column-major,
+// leading dimension 65 = 1 mod 32: both a column and a row of the lanes'
+// entries fall in distinct banks).  The kernel is bound by instruction issue
+// (16 waves share 4 SIMDs), so every index that does not change between
+// rounds is computed once, and V is rotated four rows per lane with 16-byte
+// LDS accesses.  Per round:
+//   phase 1: wave 0 computes the round's rotations from A (one lane per pair)
+//            and decides whether any pair rotates -- if none does, the round
+//            is skipped; meanwhile other waves apply the previous executed
+//            round's rotations to the eigenvector block (V <- V J, one round
+//            behind);
+//   phase 2: every block thread rotates its block (the 2 x 2 pivot blocks are
+//            set to their exact diagonal form).
+// A rotation is taken only when |a_pq| > eps sqrt(|a_pp a_qq|) (relative
+// criterion: small eigenvalues of graded matrices keep their digits); a sweep
+// without rotations ends the iteration.  Every decision is taken once, by
+// wave 0, and read by all threads after a barrier; decisions are
+// double-buffered by round parity because wave 0 may enter the next round's
+// first phase while slower waves still read the current one.
+template <typename T>
+__global__ __launch_bounds__(1024) void jacobi_blk_kernel(const EigTask<T>* __restrict__ tasks, int N) {
+  constexpr int NT = 1024;
+  constexpr int NPM = VEC_NMAX;
+  constexpr int HM = NPM / 2;
+  constexpr int LD = NPM + 1;            // A leading dimension (65 = 1 mod 32)
+  constexpr int LDV = NPM + 4;           // V leading dimension: 16-byte aligned columns
+  constexpr int RQ = NPM / 4;            // row quads of V
+  using T4 = typename Vec4<T>::type;
+  __shared__ T A[NPM * LD];              // A[c * LD + r]
+  __shared__ __align__(16) T V[NPM * LDV];
+  __shared__ T csb[2][HM][2];            // rotations (c, s) of a round, by buffer
+  __shared__ T tnb[2][HM];               // tan of the round's rotations, by buffer
+  __shared__ unsigned short sch[NPM][HM];  // round-robin schedule: pair k of round t = p | q << 8, p < q
+  __shared__ unsigned int rmask[2];      // pairs that rotate (bit k), by round parity
+  __shared__ int skip_s[2];
+  __shared__ int rotflag[3];
   __shared__ int rank_s;
-  __shared__ int posv[VEC_NMAX];
-  __shared__ T lam_s[VEC_NMAX];
+  __shared__ int posv[NPM];
+  __shared__ T lam_s[NPM];
   const EigTask<T> tk_ = tasks[blockIdx.x];
+  if (tk_.skip != nullptr && *tk_.skip != 0) return;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int NP = N + (N & 1);
   const int H = NP / 2;
-  // a pair slot beyond H rotates a zero padding column with itself (c = 1)
-  const int dummy = N < VEC_NMAX ? N : VEC_NMAX - 1;
-  static_assert(JV_PPW * JV_NW == VEC_NMAX / 2, "pair slots must cover every pair");
-  for (int e = tid; e < VEC_NMAX * VEC_NMAX; e += JV_NT) {
-    const int i = e % VEC_NMAX, j = e / VEC_NMAX;  // row i, col j
-    T a = T(0);
-    if (i < N && j < N) a = (i >= j) ? tk_.A[i + (size_t)j * tk_.lda] : tk_.A[j + (size_t)i * tk_.lda];
-    A[j][i] = a;
-    B[j][i] = T(0);
-    V[j][i] = (i == j) ? T(1) : T(0);
+  const int M = NP - 1;  // rounds per sweep
+  for (int e = tid; e < M * H; e += NT) {
+    const int t = e / H, k = e % H;
+    const int a = k == 0 ? 0 : ((k - 1 + t) % M) + 1;
+    const int b = ((NP - 2 - k + t) % M) + 1;
+    const int p = a < b ? a : b, q = a < b ? b : a;
+    sch[t][k] = (unsigned short)(p | (q << 8));
   }
+  for (int e = tid; e < NP * LD; e += NT) {
+    const int c = e / LD, r = e % LD;
+    T a = T(0);
+    if (r < N && c < N) a = (r >= c) ? tk_.A[r + (size_t)c * tk_.lda] : tk_.A[c + (size_t)r * tk_.lda];
+    A[e] = a;
+  }
+  for (int e = tid; e < NP * LDV; e += NT) {
+    const int c = e / LDV, r = e % LDV;
+    V[e] = (r == c) ? T(1) : T(0);
+  }
+  if (tid < 3) rotflag[tid] = 0;
+  // block task of this thread (pair I <= pair J), fixed for the whole kernel
+  const int nblk = H * (H + 1) / 2;
+  int bI = 0, bJ = 0;
+  const bool blk = tid < nblk;
+  if (blk) {
+    int J = 0, rem = tid;
+    while (rem >= J + 1) {
+      rem -= J + 1;
+      ++J;
+    }
+    bI = rem;
+    bJ = J;
+  }
+  // V task: rows 4 vi .. 4 vi + 3 of the columns of pair vJ (threads of waves 1..)
+  const int vt = tid - kWave;
+  const int nq = (NP + 3) / 4;
+  const bool vtask = vt >= 0 && vt < nq * H;
+  const int vi = vtask ? vt % nq : 0, vJ = vtask ? vt / nq : 0;
+  const bool vtask2 = vt >= 0 && vt + (NT - kWave) < nq * H;  // a second task for large N
+  const int vi2 = vtask2 ? (vt + NT - kWave) % nq : 0, vJ2 = vtask2 ? (vt + NT - kWave) / nq : 0;
+  static_assert(RQ * HM <= 2 * (NT - kWave), "two V tasks per thread cover every row quad and pair");
   __syncthreads();
-  // round-robin players of pair `lane` at round t: 0 and NP-1-lane fixed
-  // positions, the others rotate; kept incrementally (no modulo per round)
-  int s1 = lane == 0 ? 0 : lane - 1;           // (lane - 1 + t) mod (NP - 1) for lane > 0
-  int s2 = NP - 2 - lane;                      // (NP - 2 - lane + t) mod (NP - 1)
+  int g = 0;            // rounds executed or skipped so far (buffer parity)
+  int prev_t = -1;      // round whose rotations V still has to take (-1: none)
+  int prev_buf = 0;
+  auto v_rot = [&](int t, int buf, int i4, int J) {
+    const unsigned pq = sch[t][J];
+    const int p = int(pq & 0xffu), q = int(pq >> 8);
+    const T c = csb[buf][J][0], sn = csb[buf][J][1];
+    T4* vp = reinterpret_cast<T4*>(&V[p * LDV + 4 * i4]);
+    T4* vq = reinterpret_cast<T4*>(&V[q * LDV + 4 * i4]);
+    const T4 a = *vp, b = *vq;
+    *vp = c * a - sn * b;
+    *vq = sn * a + c * b;
+  };
   for (int sweep = 0; sweep < 40; ++sweep) {
-    unsigned long long anyrot = 0;
-    for (int t = 0; t < NP - 1; ++t) {
-      int p = lane == 0 ? 0 : s1 + 1, q = s2 + 1;
-      if (p > q) {
-        const int x = p;
-        p = q;
-        q = x;
-      }
-      const bool live = lane < H;
-      const bool valid = live && q < N;
-      const int pc = valid ? p : 0, qc = valid ? q : 0;
-      const T app = A[pc][pc], aqq = A[qc][qc], apq = A[qc][pc];
-      const T aa = fabs(apq);
-      const int flag = valid && aa > Lim<T>::tiny() && aa > Lim<T>::eps() * jac_sqrt(fabs(app * aqq));
-      T tt, cr;
-      jac_rot(app, aqq, apq, tt, cr);
-      const T c = flag ? cr : T(1);
-      const T sn = flag ? tt * cr : T(0);
-      const T dp = app - tt * apq, dq = aqq + tt * apq;
-      // slots without a real pair (padding, the odd-size dummy player) carry p == q
-      const int pl = live ? p : dummy;
-      const int ql = live ? (q < N ? q : p) : dummy;
-      if (++s1 == NP - 1) s1 = 0;
-      if (++s2 == NP - 1) s2 = 0;
-      const unsigned long long fm = __ballot(flag);
-      anyrot |= fm;
-      if (fm == 0) continue;  // wave-uniform and equal in every wave (see above)
-      int P_[JV_PPW], Q_[JV_PPW];
-      T C_[JV_PPW], S_[JV_PPW];
-#pragma unroll
-      for (int i = 0; i < JV_PPW; ++i) {
-        const int P = wave + i * JV_NW;  // < 32 lanes
-        P_[i] = __builtin_amdgcn_readlane(pl, P);
-        Q_[i] = __builtin_amdgcn_readlane(ql, P);
-        C_[i] = rdlane(c, P);
-        S_[i] = rdlane(sn, P);
-      }
-      // ---- columns: B <- A J, V <- V J
-      {
-        T ap[JV_PPW], aq[JV_PPW], vp[JV_PPW], vq[JV_PPW];
-#pragma unroll
-        for (int i = 0; i < JV_PPW; ++i) {
-          ap[i] = A[P_[i]][lane];
-          aq[i] = A[Q_[i]][lane];
-          vp[i] = V[P_[i]][lane];
-          vq[i] = V[Q_[i]][lane];
+    for (int t = 0; t < M; ++t) {
+      const int cur = g & 1;
+      // ---- phase 1
+      if (wave == 0) {
+        T c = T(1), sn = T(0), tt = T(0);
+        int flag = 0;
+        if (lane < H) {
+          const unsigned pq = sch[t][lane];
+          const int p = int(pq & 0xffu), q = int(pq >> 8);
+          const T app = A[p * LD + p], aqq = A[q * LD + q], apq = A[q * LD + p];
+          const T aa = fabs(apq);
+          flag = (q < N) && aa > Lim<T>::tiny() && aa > Lim<T>::eps() * jac_sqrt(fabs(app * aqq));
+          T tr, cr;
+          jac_rot(app, aqq, flag ? apq : T(1), tr, cr);
+          if (flag) {
+            c = cr;
+            sn = tr * cr;
+            tt = tr;
+          }
+          csb[cur][lane][0] = c;
+          csb[cur][lane][1] = sn;
+          tnb[cur][lane] = tt;
         }
-        // slots without a real pair (P == Q) copy unchanged values (c = 1, s = 0)
-#pragma unroll
-        for (int i = 0; i < JV_PPW; ++i) {
-          const T cc = C_[i], ss = S_[i];
-          B[P_[i]][lane] = cc * ap[i] - ss * aq[i];
-          B[Q_[i]][lane] = ss * ap[i] + cc * aq[i];
-          V[P_[i]][lane] = cc * vp[i] - ss * vq[i];
-          V[Q_[i]][lane] = ss * vp[i] + cc * vq[i];
+        const unsigned long long fm = __ballot(flag);
+        if (lane == 0) {
+          skip_s[cur] = fm == 0;
+          rmask[cur] = (unsigned int)fm;
+          if (fm != 0) rotflag[sweep % 3] = 1;
+          if (t == 0) rotflag[(sweep + 1) % 3] = 0;
         }
+      } else if (prev_t >= 0) {
+        if (vtask) v_rot(prev_t, prev_buf, vi, vJ);
+        if (vtask2) v_rot(prev_t, prev_buf, vi2, vJ2);
       }
       __syncthreads();
-      // ---- rows: A <- J^T B, pivot blocks exact
-      {
-        T bp[JV_PPW], bq[JV_PPW];
-#pragma unroll
-        for (int i = 0; i < JV_PPW; ++i) {
-          bp[i] = B[lane][P_[i]];
-          bq[i] = B[lane][Q_[i]];
-        }
-#pragma unroll
-        for (int i = 0; i < JV_PPW; ++i) {
-          const int P = wave + i * JV_NW;
-          const T cc = C_[i], ss = S_[i];
-          const T dpp = rdlane(dp, P), dqq = rdlane(dq, P);
-          T np_ = cc * bp[i] - ss * bq[i], nq = ss * bp[i] + cc * bq[i];
-          const bool rot = (fm >> P) & 1ull;
-          if (rot && lane == P_[i]) {
-            np_ = dpp;
-            nq = T(0);
-          } else if (rot && lane == Q_[i]) {
-            np_ = T(0);
-            nq = dqq;
+      ++g;
+      if (skip_s[cur]) {
+        prev_t = -1;
+        continue;  // uniform: every thread read the same flag after the barrier
+      }
+      // ---- phase 2
+      if (blk) {
+        const unsigned pqI = sch[t][bI], pqJ = sch[t][bJ];
+        const int pI = int(pqI & 0xffu), qI = int(pqI >> 8);
+        const int pJ = int(pqJ & 0xffu), qJ = int(pqJ >> 8);
+        const T cI = csb[cur][bI][0], sI = csb[cur][bI][1];
+        const T cJ = csb[cur][bJ][0], sJ = csb[cur][bJ][1];
+        const T x00 = A[pJ * LD + pI], x01 = A[qJ * LD + pI];
+        const T x10 = A[pJ * LD + qI], x11 = A[qJ * LD + qI];
+        // columns (X J_J), then rows (J_I^T Y)
+        const T y00 = cJ * x00 - sJ * x01, y01 = sJ * x00 + cJ * x01;
+        const T y10 = cJ * x10 - sJ * x11, y11 = sJ * x10 + cJ * x11;
+        T z00 = cI * y00 - sI * y10, z10 = sI * y00 + cI * y10;
+        T z01 = cI * y01 - sI * y11, z11 = sI * y01 + cI * y11;
+        if (bI == bJ) {
+          if ((rmask[cur] >> bI) & 1u) {
+            const T tI = tnb[cur][bI];
+            z00 = x00 - tI * x01;
+            z11 = x11 + tI * x01;
+            z01 = T(0);
+          } else {
+            z01 = T(0.5) * (z01 + z10);
           }
-          A[lane][P_[i]] = np_;
-          A[lane][Q_[i]] = nq;
+          z10 = z01;
+        }
+        A[pJ * LD + pI] = z00;
+        A[qJ * LD + pI] = z01;
+        A[pJ * LD + qI] = z10;
+        A[qJ * LD + qI] = z11;
+        if (bI != bJ) {  // the mirrored block
+          A[pI * LD + pJ] = z00;
+          A[pI * LD + qJ] = z01;
+          A[qI * LD + pJ] = z10;
+          A[qI * LD + qJ] = z11;
         }
       }
+      prev_t = t;
+      prev_buf = cur;
       __syncthreads();
     }
-    if (anyrot == 0) break;
+    if (rotflag[sweep % 3] == 0) break;  // read after the round's last barrier: same value everywhere
   }
+  if (prev_t >= 0) {
+    if (vtask) v_rot(prev_t, prev_buf, vi, vJ);
+    if (vtask2) v_rot(prev_t, prev_buf, vi2, vJ2);
+  }
+  __syncthreads();
   // sort descending (stable by index), rank rule, write out
-  for (int i = tid; i < N; i += JV_NT) {
-    const T li = A[i][i];
+  for (int i = tid; i < N; i += NT) {
+    const T li = A[i * LD + i];
     int pos = 0;
     for (int j = 0; j < N; ++j) {
-      const T lj = A[j][j];
+      const T lj = A[j * LD + j];
       pos += (lj > li) || (lj == li && j < i);
     }
     posv[i] = pos;
@@ -695,15 +786,14 @@ __global__ __launch_bounds__(JV_NT) void jacobi_vec_kernel(const EigTask<T>* __r
   __syncthreads();
   const int rkeep = (ru.kind == 2) ? rank_s : N;
   if (tk_.lam)
-    for (int i = tid; i < N; i += JV_NT) tk_.lam[i] = lam_s[i];
+    for (int i = tid; i < N; i += NT) tk_.lam[i] = lam_s[i];
   if (tk_.V)
-    for (int e = tid; e < N * N; e += JV_NT) {
+    for (int e = tid; e < N * N; e += NT) {
       const int i = e / N, r = e % N;  // source column i, row r
       const int pos = posv[i];
-      tk_.V[r + (size_t)pos * N] = pos < rkeep ? V[i][r] : T(0);
+      tk_.V[r + (size_t)pos * N] = pos < rkeep ? V[i * LDV + r] : T(0);
     }
 }
-
 
 }  // namespace
 
@@ -719,15 +809,15 @@ void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipSt
               double(ntasks) * sizeof(T) * ((want_v ? 2.0 : 1.0) * nn * nn + nn));
   if (want_v) {
     TK_CHECK(N <= VEC_NMAX, kErrUnsupported, "symmetric eigensolver: eigenvectors above size 64");
-    // measured on gfx950 (N = 53): 16 waves for FP32, 8 for FP64 (register pressure)
-    constexpr int nt = sizeof(T) == 4 ? 1024 : 512;
-    hipLaunchKernelGGL((jacobi_vec_kernel<T, nt>), dim3(ntasks), dim3(nt), 0, st, tasks_d, N);
+    hipLaunchKernelGGL((jacobi_blk_kernel<T>), dim3(ntasks), dim3(1024), 0, st, tasks_d, N);
   } else {
     TK_CHECK(N <= GM_NMAX, kErrUnsupported, "symmetric eigensolver: matrix larger than 512");
     if (N <= VAL_NMAX)
       hipLaunchKernelGGL((tridiag_reg_kernel<T, trg_nt<T>()>), dim3(ntasks), dim3(trg_nt<T>()), 0, st, tasks_d, N);
     else
       hipLaunchKernelGGL((tridiag_gm_kernel<T>), dim3(ntasks), dim3(1024), 0, st, tasks_d, N);
+    // (the planner gives the order-512 path matrices with a leading dimension
+    // that is a multiple of 4, in 256-byte aligned workspace blocks)
   }
   TK_LAUNCH_CHECK();
   timer_end(kc, st);

@@ -514,14 +514,17 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
   if (rule) {
     for (auto& modes : modes_by_n<T>(sh)) {
       const int n = sh.n[modes[0]];
-      // The Gram goes on the smaller side: n x n when n fits the register
-      // eigensolver or the concatenation can be wider than n, otherwise the
-      // R x R Gram of the concatenation (both have the same nonzero spectrum).
+      // The Gram goes on the smaller side (n x n, or R x R for the active
+      // concatenation; both have the same nonzero spectrum).  Which side is
+      // smaller and which eigensolver fits depend on the active ranks, a
+      // device value, so wide cases plan both tasks of a pair and the one
+      // that does not apply skips itself: the register eigensolver (order
+      // <= 160) on the compacted R-side Gram while R <= 160, and the
+      // global-memory one (order <= 512) above that, on the R-side Gram while
+      // R <= n (capacity permitting) or else on the n-side Gram.
       const int Rp = nb * rc;
-      if (n <= kEigRegMax || Rp > n) {
-        // n-side Gram: sum_b w_b^2 U_b U_b^T
-        T* Gn = ar.alloc<T>(size_t(n) * n * modes.size());
-        T* lam = ar.alloc<T>(size_t(n) * modes.size());
+      auto nside_gram = [&](int ldg) {
+        T* Gn = ar.alloc<T>(size_t(ldg) * n * modes.size());
         GemmDesc<T> g;
         g.ta = false;
         g.tb = true;
@@ -530,40 +533,63 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
         g.K = rc;
         g.lda = n;
         g.ldb = n;
-        g.ldc = n;
+        g.ldc = ldg;
         g.nb = nb_active;
         g.terms_are_blocks = nb_active != nullptr;
-        std::vector<EigTask<T>> et;
         for (size_t i = 0; i < modes.size(); ++i) {
           const int k = modes[i];
           std::vector<GemmTerm<T>> ts;
           for (int b = 0; b < nb; ++b) ts.push_back(term<T>(in.U[b][k], in.U[b][k], w + b, w + b));
-          g.group(Gn + i * size_t(n) * n, ts);
-          EigTask<T> e{};
-          e.A = Gn + i * size_t(n) * n;
-          e.lda = n;
-          e.lam = lam + i * n;
-          e.rule.kind = 1;
-          e.rule.tau = epsd + 1;
-          e.rule.delta = cfg.delta;
-          e.rule.rank_out = rt + k;
-          et.push_back(e);
+          g.group(Gn + i * size_t(ldg) * n, ts);
         }
         emit_gemm(q, pl, std::move(g));
+        return Gn;
+      };
+      auto eig_launch = [&](std::vector<EigTask<T>> et, int NL) {
         const size_t off_et = blob.add(et);
         const int ne = int(et.size());
-        q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off_et), ne, n, false, st); });
-      } else {
-        // R-side Gram of the padded concatenation, compacted to the active ranks
-        const int NM = Rp;
-        double* enable = ar.alloc<double>(kMaxD);
-        int* nact = ar.alloc<int>(kMaxD);
-        T* Gp = ar.alloc<T>(size_t(Rp) * Rp * d);
-        T* Gc = ar.alloc<T>(size_t(NM) * NM * d);
-        T* lam = ar.alloc<T>(size_t(NM) * d);
-        q.steps.push_back([=](hipStream_t st) {
-          gram_prep(bl->at<const int*>(off_ranks), nbA(), d, NM, enable, nact, st);
-        });
+        q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off_et), ne, NL, false, st); });
+      };
+      auto rule_task = [&](T* A, int lda, T* lam, int k) {
+        EigTask<T> e{};
+        e.A = A;
+        e.lda = lda;
+        e.lam = lam;
+        e.rule.kind = 1;
+        e.rule.tau = epsd + 1;
+        e.rule.delta = cfg.delta;
+        e.rule.rank_out = rt + k;
+        return e;
+      };
+      if (n <= kEigRegMax) {
+        // n-side Gram: sum_b w_b^2 U_b U_b^T, register eigensolver
+        T* Gn = nside_gram(n);
+        T* lam = ar.alloc<T>(size_t(n) * modes.size());
+        std::vector<EigTask<T>> et;
+        for (size_t i = 0; i < modes.size(); ++i)
+          et.push_back(rule_task(Gn + i * size_t(n) * n, n, lam + i * n, modes[i]));
+        eig_launch(et, n);
+        continue;
+      }
+      // R-side Gram of the padded concatenation, compacted to the active ranks
+      // (only while they fit the compacted capacity NM; blocks of a disabled
+      // mode cost nothing in the GEMM)
+      const int NM = std::min(Rp, Rp > n ? kEigRegMax : n);
+      const int ldc = NM > kEigRegMax ? (NM + 3) / 4 * 4 : NM;
+      double* enable = ar.alloc<double>(kMaxD);
+      int* nact = ar.alloc<int>(kMaxD);
+      int* skip_reg = ar.alloc<int>(kMaxD);   // R above the register eigensolver's order
+      int* skip_gm = ar.alloc<int>(kMaxD);    // R within it
+      T* Gp = ar.alloc<T>(size_t(Rp) * Rp * d);
+      T* Gc = ar.alloc<T>(size_t(ldc) * NM * d);
+      T* lam = ar.alloc<T>(size_t(std::max(NM, n)) * d);
+      q.steps.push_back([=](hipStream_t st) {
+        // the flags against the register order first, then enable / nact
+        // against the compacted capacity (the second call overwrites them)
+        gram_prep(bl->at<const int*>(off_ranks), nbA(), d, kEigRegMax, enable, nact, st, skip_reg, skip_gm);
+        gram_prep(bl->at<const int*>(off_ranks), nbA(), d, NM, enable, nact, st);
+      });
+      {
         GemmDesc<T> g;
         g.ta = true;
         g.tb = false;
@@ -579,29 +605,48 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
         for (int b = 0; b < nb; ++b)
           for (int b2 = 0; b2 <= b; ++b2)
             for (int k : modes)
-              g.group1(Gp + size_t(k) * Rp * Rp + size_t(b) * rc + size_t(b2) * rc * Rp, in.U[b][k], in.U[b2][k], w + b,
-                       w + b2, enable + k);
+              g.group1(Gp + size_t(k) * Rp * Rp + size_t(b) * rc + size_t(b2) * rc * Rp, in.U[b][k], in.U[b2][k],
+                       w + b, w + b2, enable + k);
         emit_gemm(q, pl, std::move(g));
-        q.steps.push_back([=](hipStream_t st) {
-          gram_compact<T>(Gp, Rp, bl->at<const int*>(off_ranks), nbA(), d, rc, nact, Gc, NM, size_t(Rp) * Rp,
-                          size_t(NM) * NM, st);
-        });
+      }
+      q.steps.push_back([=](hipStream_t st) {
+        gram_compact<T>(Gp, Rp, bl->at<const int*>(off_ranks), nbA(), d, rc, nact, Gc, ldc, size_t(Rp) * Rp,
+                        size_t(ldc) * NM, st);
+      });
+      {
+        // register eigensolver on the compacted Gram while R <= 160
         std::vector<EigTask<T>> et;
         for (int k : modes) {
-          EigTask<T> e{};
-          e.A = Gc + size_t(k) * NM * NM;
-          e.lda = NM;
-          e.lam = lam + size_t(k) * NM;
+          EigTask<T> e = rule_task(Gc + size_t(k) * ldc * NM, ldc, lam + size_t(k) * std::max(NM, n), k);
           e.ndyn = nact + k;
-          e.rule.kind = 1;
-          e.rule.tau = epsd + 1;
-          e.rule.delta = cfg.delta;
-          e.rule.rank_out = rt + k;
+          e.skip = skip_reg + k;
           et.push_back(e);
         }
-        const size_t off_et = blob.add(et);
-        const int ne = int(et.size());
-        q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off_et), ne, NM, false, st); });
+        eig_launch(et, std::min(NM, kEigRegMax));
+      }
+      if (Rp > kEigRegMax) {
+        std::vector<EigTask<T>> et;
+        if (Rp <= n) {
+          // global-memory eigensolver on the compacted Gram (R <= Rp <= n)
+          for (int k : modes) {
+            EigTask<T> e = rule_task(Gc + size_t(k) * ldc * NM, ldc, lam + size_t(k) * std::max(NM, n), k);
+            e.ndyn = nact + k;
+            e.skip = skip_gm + k;
+            et.push_back(e);
+          }
+          eig_launch(et, NM);
+        } else {
+          // global-memory eigensolver on the n-side Gram while R > 160
+          const int ldg = (n + 3) / 4 * 4;
+          T* Gn = nside_gram(ldg);
+          for (size_t i = 0; i < modes.size(); ++i) {
+            const int k = modes[i];
+            EigTask<T> e = rule_task(Gn + i * size_t(ldg) * n, ldg, lam + size_t(k) * std::max(NM, n), k);
+            e.skip = skip_gm + k;
+            et.push_back(e);
+          }
+          eig_launch(et, n);
+        }
       }
     }
   }

@@ -83,6 +83,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
   // with alpha == 0 stages zeros (its operands are never read).
   int cur = -1;
   T alpha = T(0);
+  bool live_next = false;  // whether the fetched slab's term has a nonzero alpha (uniform)
   const T* Ap = nullptr;
   const T* Bp = nullptr;
   T ra[SA], rb[SB];
@@ -101,6 +102,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
       cur = t;
     }
     const bool live = alpha != T(0);
+    live_next = live;
 #pragma unroll
     for (int i = 0; i < SA; ++i) {
       const int gm = m0 + am[i], gk = k0 + ak[i];
@@ -118,6 +120,13 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
   };
   if (sb < se) fetch(sb);
   for (int slab = sb; slab < se; ++slab) {
+    // a slab of a zero-coefficient term (e.g. a disabled Gram block) adds
+    // nothing: it is neither staged nor multiplied (the branch is uniform)
+    const bool lv = live_next;
+    if (!lv) {
+      if (slab + 1 < se) fetch(slab + 1);
+      continue;
+    }
 #pragma unroll
     for (int i = 0; i < SA; ++i) As[ak[i]][am[i]] = ra[i];
 #pragma unroll

@@ -140,6 +140,7 @@ struct EigTask {
   T* lam;
   T* V;          // eigenvectors (ld = launch N); for rule kind 2 columns >= rank are zeroed
   const int* ndyn; // optional device size (< launch N); negative: skip, rank_out = -1
+  const int* skip; // optional device flag: nonzero = do nothing (another task of the launch pair decides)
   EigRule rule;
 };
 // Eigenvalues only: N <= 512; above kEigRegMax the matrix is reduced in place
@@ -151,7 +152,9 @@ void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipSt
 // Per mode k: R_k = sum_b rank_b[k]; enable[k] = (R_k <= rmax); nact[k] = R_k or -1.
 // Then the padded Gram (blocks of rc rows/cols) is compacted to its R_k x R_k
 // active part (ld = ldc) for every mode with enable[k] = 1.
-void gram_prep(const int* const* ranks, int nb, int d, int rmax, double* enable, int* nact, hipStream_t st);
+// skip_small[k] = (R_k > rmax), skip_big[k] = (R_k <= rmax) when non-null.
+void gram_prep(const int* const* ranks, int nb, int d, int rmax, double* enable, int* nact, hipStream_t st,
+               int* skip_small = nullptr, int* skip_big = nullptr);
 template <typename T>
 void gram_compact(const T* padded, int ldp, const int* const* ranks, int nb, int d, int rc, const int* nact,
                   T* compact, int ldc, size_t mode_stride_p, size_t mode_stride_c, hipStream_t st);

@@ -1,6 +1,8 @@
 // Small bookkeeping kernels: coefficient gathering, zero-sum fix-up,
 // accumulation, vector sums and the per-iteration status record.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <map>
 #include <mutex>
 
@@ -309,6 +311,25 @@ void iter_status(const double* sumsq2, const int* ls_flags, const double* res_k,
                  double* omega, IterStatus* out, hipStream_t st) {
   hipLaunchKernelGGL(iter_status_kernel, dim3(1), dim3(64), 0, st, sumsq2, ls_flags, res_k, rank, d, bd_tol, omega, out);
   TK_LAUNCH_CHECK();
+}
+
+// ---- launch counter and empty-kernel latency
+namespace {
+std::atomic<int64_t> g_launches{0};
+__global__ void empty_kernel() {}
+}  // namespace
+
+void count_launch() { g_launches.fetch_add(1, std::memory_order_relaxed); }
+int64_t launch_count() { return g_launches.load(std::memory_order_relaxed); }
+
+double empty_launch_us(int n, hipStream_t st) {
+  TK_HIP(hipStreamSynchronize(st));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < n; ++i) hipLaunchKernelGGL(empty_kernel, dim3(1), dim3(64), 0, st);
+  TK_HIP(hipGetLastError());
+  TK_HIP(hipStreamSynchronize(st));
+  const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  return n > 0 ? us / n : 0.0;
 }
 
 // ---- kernel-class timers

@@ -229,13 +229,16 @@ __global__ void sketch_width_kernel(const int* rt, int d, int p, int cap, int fo
   *s_out = est < cap + p ? est : cap + p;
 }
 
-__global__ void gram_prep_kernel(const int* const* ranks, int nb, int d, int rmax, double* enable, int* nact) {
+__global__ void gram_prep_kernel(const int* const* ranks, int nb, int d, int rmax, double* enable, int* nact,
+                                 int* skip_small, int* skip_big) {
   const int k = threadIdx.x;
   if (k >= d) return;
   int R = 0;
   for (int b = 0; b < nb; ++b) R += ranks[b][k];
   enable[k] = R <= rmax ? 1.0 : 0.0;
   nact[k] = R <= rmax ? R : -1;
+  if (skip_small) skip_small[k] = R > rmax;
+  if (skip_big) skip_big[k] = R <= rmax;
 }
 
 // Compacts the lower triangle of a padded block Gram: compact index i maps to
@@ -355,8 +358,10 @@ void mat_recap(const T* src, int ld_src, int rows_src, int cols_src, T* dst, int
   TK_LAUNCH_CHECK();
 }
 
-void gram_prep(const int* const* ranks, int nb, int d, int rmax, double* enable, int* nact, hipStream_t st) {
-  hipLaunchKernelGGL(gram_prep_kernel, dim3(1), dim3(64), 0, st, ranks, nb, d, rmax, enable, nact);
+void gram_prep(const int* const* ranks, int nb, int d, int rmax, double* enable, int* nact, hipStream_t st,
+               int* skip_small, int* skip_big) {
+  hipLaunchKernelGGL(gram_prep_kernel, dim3(1), dim3(64), 0, st, ranks, nb, d, rmax, enable, nact, skip_small,
+                     skip_big);
   TK_LAUNCH_CHECK();
 }
 

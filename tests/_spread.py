@@ -12,7 +12,10 @@ choices that are all valid:
     its basis; the GPU's FP64 form uses Cholesky-QR3 there);
   * for the FP32 form, every RoundSum operand, operator factor, sketch and
     the right-hand side rounded to FP32 (the FP32 form rounds its operands on
-    entry).
+    entry);
+  * the GPU's own spread: the same GPU solve on the right-hand side changed
+    by one unit roundoff of the form (2^-52, or 2^-24 for the FP32 form),
+    which measures how strongly the form's own arithmetic is amplified.
 The GPU may deviate from the oracle by at most ten times the largest of these
 spreads (running maximum along the trajectory), and always by the FP64
 parity bound 1e-10 (1e-4 for the FP32 form, its RoundSum bound).  The FP32
@@ -27,6 +30,25 @@ import oracle as O
 def perturbed_rhs(B: O.Tucker, seed: int = 99, rel: float = 2.0 ** -52) -> O.Tucker:
     rng = np.random.default_rng(seed)
     return O.Tucker(B.core * (1.0 + rel * rng.choice([-1.0, 1.0], size=B.core.shape)), B.U)
+
+
+def rel_spread(h_ref, h_pert):
+    """Relative difference of two histories over their common length."""
+    h_ref, h_pert = np.asarray(h_ref), np.asarray(h_pert)
+    m = min(len(h_ref), len(h_pert))
+    return np.abs(h_pert[:m] - h_ref[:m]) / np.abs(h_ref[:m])
+
+
+def bound_from_spreads(spreads, m, floor=1e-10):
+    """10x the running maximum (with one iteration of lookahead) of the
+    largest of the given spread arrays, over the first m iterations."""
+    sp = np.zeros(m)
+    for a in spreads:
+        a = np.asarray(a)[:m]
+        sp[:len(a)] = np.maximum(sp[:len(a)], a)
+    run = np.maximum.accumulate(sp)
+    ahead = np.concatenate([run[1:], run[-1:]])
+    return np.maximum(floor, 10.0 * ahead)
 
 
 def history_bound(h_ref, h_perts, floor=1e-10):

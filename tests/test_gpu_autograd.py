@@ -64,8 +64,8 @@ def test_autograd_gradients_against_oracle_dense_and_fd(tk):
     lo, xbar = O.loss_and_cotangent(x, Xt)
     lam, dalpha, _, _ = O.adjoint_gradients(terms, x, xbar, S, Om, oprm, want_dA=False)
     dcore = O.multi_ttm(lam.core, [B.U[k].T @ lam.U[k] for k in range(3)])
-    print("loss", float(loss), lo, "dalpha", ga, dalpha, flush=True)
-    assert abs(float(loss) / lo - 1.0) <= 1e-8
+    print("loss", float(loss.detach()), lo, "dalpha", ga, dalpha, flush=True)
+    assert abs(float(loss.detach()) / lo - 1.0) <= 1e-8
     assert np.allclose(ga, dalpha, rtol=1e-8, atol=0)
     assert np.linalg.norm(gb - dcore) <= 1e-8 * np.linalg.norm(dcore)
     # the dense FP64 gradient (N = 1000, row-major vec)

@@ -5,13 +5,15 @@ rank cap 32, k_trunc 3) in the FP32 form, each over one restart cycle against
 the FP64 oracle on identical seeded inputs.
 
 Bounds are measured (_spread.py).  FP64 form: every sketched residual, the
-cycle's true residual and its solution within ten times the oracle's own
-spread over a one-ulp change of the right-hand side and over the range-finder
-basis choice (at least 1e-10).  FP32 form: the iterations before the rank cap
-binds within the FP32 RoundSum bound 1e-4, a non-increasing sketched
-residual, and the cycle's
-true residual and solution within ten times the spread of the oracle runs
-above plus the run with every operand rounded to FP32 (at least 1e-4)."""
+cycle's true residual and its solution within ten times the largest spread of
+the oracle over a one-ulp change of the right-hand side and over the
+range-finder basis choice, and of the GPU's own solve under a one-ulp change
+(at least 1e-10).  FP32 form: the iterations before the rank cap binds
+within the FP32 RoundSum bound 1e-4, a non-increasing sketched residual, and
+the cycle's true residual and solution within ten times the largest spread of
+the oracle runs above, the oracle run with every operand rounded to FP32 and
+the GPU's own FP32 solve under an FP32-level change of the right-hand side
+(at least 1e-4)."""
 import dataclasses
 
 import numpy as np
@@ -20,12 +22,14 @@ import pytest
 import oracle as O
 from workloads import make_config
 
-from _spread import cholesky_qr3, first_divergence, fp32_operands, history_bound, perturbed_rhs
+from _spread import (bound_from_spreads, cholesky_qr3, first_divergence, fp32_operands, history_bound,
+                     perturbed_rhs, rel_spread)
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+U32 = 2.0 ** -24
 FP32_FLOOR = 1e-4
 
 
@@ -79,41 +83,44 @@ def convdiff():
     return w, _ensemble(w.terms, B, w.S, w.Omega, oprm, fp32=True)
 
 
-def _spreads(ens, keys):
-    Xo, oi, h_o, _ = ens["ref"]
-    hs = [ens[k][2] for k in keys]
-    sx = max(_dist(ens[k][0], Xo) for k in keys)
-    st = max(abs(ens[k][1]["true_relres"] / oi["true_relres"] - 1.0) for k in keys)
-    return hs, sx, st
-
-
 @pytest.mark.parametrize("form", [0, 1])
 def test_convdiff_cycle(tk, convdiff, form):
     w, ens = convdiff
     Xo, oi, h_o, ro = ens["ref"]
     prm = tk.SolveParams(form=form, tol=w.tol, eta=w.eta, maxiter=w.maxiter, max_restarts=1, k_trunc=w.k_trunc,
                          rank_cap=w.cap, oversample=w.p)
-    x, info = tk.solve(tk.KronOp.from_terms(w.terms), tk.Tucker.from_numpy(w.b_core, w.b_factors),
-                       [_cm(s) for s in w.S], [_cm(o) for o in w.Omega], prm)
+    op = tk.KronOp.from_terms(w.terms)
+    S, Om = [_cm(s) for s in w.S], [_cm(o) for o in w.Omega]
+    x, info = tk.solve(op, tk.Tucker.from_numpy(w.b_core, w.b_factors), S, Om, prm)
+    # the GPU's own spread: the same solve on the right-hand side changed by
+    # one unit roundoff of the form
+    Bp = perturbed_rhs(O.Tucker(w.b_core, w.b_factors), rel=2.0 ** -52 if form == 0 else U32)
+    xp, ip = tk.solve(op, tk.Tucker.from_numpy(Bp.core, Bp.U), S, Om, prm)
     h_g = np.array(info["hist"])
     m = min(len(h_g), len(h_o))
     dev = np.abs(h_g[:m] - h_o[:m]) / h_o[:m]
     X = _cpu(tk, x)
     dev_x = _dist(X, Xo)
     dev_t = abs(info["true_relres"] / oi["true_relres"] - 1.0)
-    hs64, sx64, st64 = _spreads(ens, ["ulp", "basis"])
-    b64 = history_bound(h_o, hs64)
+    g_h = rel_spread(h_g, ip["hist"])
+    g_x = _dist(_cpu(tk, xp), X)
+    g_t = abs(ip["true_relres"] / info["true_relres"] - 1.0)
+    keys = ["ulp", "basis"] if form == 0 else ["ulp", "basis", "fp32"]
+    sx = max(_dist(ens[k][0], Xo) for k in keys)
+    st = max(abs(ens[k][1]["true_relres"] / oi["true_relres"] - 1.0) for k in keys)
+    sx, st = max(sx, g_x), max(st, g_t)
+    spreads = [rel_spread(h_o, ens[k][2]) for k in keys] + [g_h]
     if form == 0:
-        bound, sx, st, floor = b64, sx64, st64, 1e-10
+        floor = 1e-10
+        bound = bound_from_spreads(spreads, m, floor)
     else:
         # FP32: per iteration only before the rank cap binds (no truncation
         # inside a singular-value continuum yet, nothing amplified); after
         # that, the end of the cycle
-        hs, sx, st = _spreads(ens, ["ulp", "basis", "fp32"])
         calm = np.array([max(r) < w.cap for r in ro])
         assert calm[:3].all()
-        bound = np.where(calm, FP32_FLOOR, np.inf)
         floor = FP32_FLOOR
+        bound = np.where(calm[:m], FP32_FLOOR, np.inf)
         assert np.all(np.diff(h_g) <= 1e-6 * h_g[:-1])    # the sketched residual never increases
     print(f"convdiff n=256 form {form}: iters gpu {info['iters']} oracle {oi['iters']}; first divergence above "
           f"{floor:g} at {first_divergence(h_g, h_o, floor)}; sketched dev max {dev.max():.2e} (worst ratio to the "

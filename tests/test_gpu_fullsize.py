@@ -18,7 +18,7 @@ import pytest
 import oracle as O
 from workloads import laplacian_eigenpairs
 
-from _spread import cholesky_qr3, first_divergence, history_bound, perturbed_rhs
+from _spread import bound_from_spreads, cholesky_qr3, first_divergence, perturbed_rhs, rel_spread
 
 pytestmark = pytest.mark.gpu
 
@@ -125,19 +125,22 @@ def test_fullsize_deblur_first_cycle_fp64(tk):
     # inside the core's singular-value continuum, where the kept subspace is
     # not determined beyond rounding and the short recurrence amplifies
     # rounding-level differences.  There the bound is measured (_spread.py):
-    # ten times the oracle's own spread over a one-ulp change of the
-    # right-hand side and over the range-finder basis choice, per iteration
-    # (running maximum), for the sketched residuals, the true residual and the
-    # solution.
+    # ten times the largest spread of the oracle over a one-ulp change of the
+    # right-hand side and over the range-finder basis choice, and of the GPU's
+    # own solve under a one-ulp change, per iteration (running maximum), for
+    # the sketched residuals, the true residual and the solution.
     w = _workload(3)
     op = tk.KronOp.from_terms(w.terms)
     b = tk.Tucker.from_numpy(w.b_core, w.b_factors)
     prm = tk.SolveParams(form=0, tol=w.tol, eta=w.eta, maxiter=w.maxiter, max_restarts=1, k_trunc=w.k_trunc,
                          rank_cap=w.cap, oversample=w.p)
-    x, info = tk.solve(op, b, [_cm(s) for s in w.S], [_cm(o) for o in w.Omega], prm)
+    S, Om = [_cm(s) for s in w.S], [_cm(o) for o in w.Omega]
+    x, info = tk.solve(op, b, S, Om, prm)
     oprm = O.SGMRESParams(tol=w.tol, eta=w.eta, maxiter=w.maxiter, max_restarts=1, k_trunc=w.k_trunc, cap=w.cap,
                           p=w.p)
     B = O.Tucker(w.b_core, w.b_factors)
+    Bp = perturbed_rhs(B)
+    xp, ip = tk.solve(op, tk.Tucker.from_numpy(Bp.core, Bp.U), S, Om, prm)   # the GPU's own spread
     log, logp, logc = [], [], []
     Xo, oinfo = O.solve(w.terms, B, w.S, w.Omega, oprm, log=log)
     Xp, pinfo = O.solve(w.terms, perturbed_rhs(B), w.S, w.Omega, oprm, log=logp)
@@ -154,12 +157,13 @@ def test_fullsize_deblur_first_cycle_fp64(tk):
     nb = (max(below) + 1) if below else 0
     assert np.max(np.abs(h_g[:nb] - h_o[:nb]), initial=0.0) <= 1e-10
     assert np.all(np.diff(h_g) <= 1e-12 * h_g[:-1])
-    bound = history_bound(h_o, [h_p, h_q])
+    bound = bound_from_spreads([rel_spread(h_o, h_p), rel_spread(h_o, h_q), rel_spread(h_g, ip["hist"])], len(h_o))
     dev = np.abs(h_g - h_o) / h_o
-    spread_t = max(abs(i["true_relres"] / oinfo["true_relres"] - 1.0) for i in (pinfo, qinfo))
+    spread_t = max([abs(i["true_relres"] / oinfo["true_relres"] - 1.0) for i in (pinfo, qinfo)] +
+                   [abs(ip["true_relres"] / info["true_relres"] - 1.0)])
     dev_t = abs(info["true_relres"] / oinfo["true_relres"] - 1.0)
     X = _cpu(tk, x)
-    spread_x, dev_x = max(_dist(Xp, Xo), _dist(Xq, Xo)), _dist(X, Xo)
+    spread_x, dev_x = max(_dist(Xp, Xo), _dist(Xq, Xo), _dist(_cpu(tk, xp), X)), _dist(X, Xo)
     print(f"deblur n=512 cycle: cap binds from iteration {nb}; first divergence above 1e-10 at "
           f"{first_divergence(h_g, h_o)}; sketched residuals max dev {dev.max():.2e} (oracle spread x10 "
           f"{bound.max():.2e}); true residual dev {dev_t:.2e} (spread {spread_t:.2e}); solution dev {dev_x:.2e} "
@@ -325,7 +329,8 @@ def test_fullsize_regularised_deblur_cycle(tk):
     # Projected Tikhonov + GCV on the benchmark's regularised deblurring
     # workload (n = 256, rank cap 48, sketch size 120), one cycle of 24
     # iterations: lambda_k, the sketched residuals and the solution within
-    # 1e-6 or ten times the oracle's own spread under 1e-15 input changes.
+    # 1e-6 or ten times the largest of the oracle's own spread under 1e-15
+    # input changes and the GPU's under the same change of the right-hand side.
     from test_gpu_tikhonov import _oracle_spread
     from workloads import deblur_gcv_problem, draw_sketches
     n, cap, p, it = 256, 48, 5, 24
@@ -346,11 +351,19 @@ def test_fullsize_regularised_deblur_cycle(tk):
     (lo, ho, rre_o, Xo), lam_s, hist_s, rre_s, x_s = _oracle_spread(run, B)
     prm = tk.SolveParams(form=0, tol=1e-14, maxiter=it, k_trunc=2, rank_cap=cap, oversample=p, max_restarts=1,
                          tikhonov=True)
-    x, info = tk.solve(tk.KronOp.from_terms(terms), _gpu(tk, B, rcap=(cap,) * 3), [_cm(s) for s in S],
-                       [_cm(o) for o in Om], prm)
+    opg, Sg, Omg = tk.KronOp.from_terms(terms), [_cm(s) for s in S], [_cm(o) for o in Om]
+    x, info = tk.solve(opg, _gpu(tk, B, rcap=(cap,) * 3), Sg, Omg, prm)
+    Bp = perturbed_rhs(B, rel=1e-15)
+    xp, ip = tk.solve(opg, _gpu(tk, Bp, rcap=(cap,) * 3), Sg, Omg, prm)   # the GPU's own spread
     Xg = _cpu(tk, x)
     rre_g = O.exact_norm([(1.0, Xg), (-1.0, xt)]) / nxt
     dist = np.linalg.norm(O.to_dense(Xg) - Xo) / np.linalg.norm(Xo)
+    lam_g = np.array(info["lam"][:it])
+    lam_s = np.maximum(lam_s, np.abs(np.array(ip["lam"][:it]) / lam_g - 1))
+    hist_s = np.maximum(hist_s, np.abs(np.array(ip["hist"][:it]) / np.array(info["hist"][:it]) - 1))
+    Xgp = _cpu(tk, xp)
+    rre_s = max(rre_s, abs((O.exact_norm([(1.0, Xgp), (-1.0, xt)]) / nxt) / rre_g - 1))
+    x_s = max(x_s, np.linalg.norm(O.to_dense(Xgp) - O.to_dense(Xg)) / np.linalg.norm(O.to_dense(Xg)))
     print(f"full-size regularised cycle: gpu rre {rre_g:.6f} lam[-1] {info['lam'][it - 1]:.6e}; oracle rre "
           f"{rre_o:.6f} lam[-1] {lo[-1]:.6e}; spread lam {lam_s.max():.1e} rre {rre_s:.1e}; dist {dist:.2e}",
           flush=True)

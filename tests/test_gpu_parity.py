@@ -13,7 +13,7 @@ import pytest
 
 import oracle as O
 
-from _spread import cholesky_qr3, first_divergence, history_bound, perturbed_rhs
+from _spread import bound_from_spreads, cholesky_qr3, first_divergence, perturbed_rhs, rel_spread
 
 pytestmark = pytest.mark.gpu
 
@@ -215,6 +215,8 @@ def test_solve_config1_parity_fp64(tk):
     op, b, S, Om = _workload_gpu(tk, w)
     prm = tk.SolveParams(form=0, tol=1e-8, eta=w.eta, maxiter=60, k_trunc=2, rank_cap=16, oversample=5)
     x, info = tk.solve(op, b, S, Om, prm)
+    Bp = perturbed_rhs(O.Tucker(w.b_core, w.b_factors))
+    xp, ip = tk.solve(op, tk.Tucker.from_numpy(Bp.core, Bp.U), S, Om, prm)   # the GPU's own spread
     oprm = O.SGMRESParams(tol=1e-8, eta=w.eta, maxiter=60, k_trunc=2, cap=16, p=5)
     log = []
     Xo, oinfo = O.solve(w.terms, O.Tucker(w.b_core, w.b_factors), w.S, w.Omega, oprm, log=log)
@@ -228,9 +230,10 @@ def test_solve_config1_parity_fp64(tk):
     # histories are fractions of ||b_s||: absolute differences are residual
     # differences relative to ||b||, held to the FP64 parity bound 1e-10
     assert np.max(np.abs(h_g[:n1] - h_o[:n1])) <= 1e-10
-    # later cycles: 10x the oracle's own spread over a one-ulp change of the
-    # right-hand side and over the range-finder basis choice (running maximum
-    # per iteration and per cycle; _spread.py)
+    # later cycles: 10x the largest spread of the oracle over a one-ulp change
+    # of the right-hand side and over the range-finder basis choice, and of the
+    # GPU's own solve under the one-ulp change (running maximum per iteration
+    # and per cycle; _spread.py)
     logp, logq = [], []
     Xp, pinfo = O.solve(w.terms, perturbed_rhs(O.Tucker(w.b_core, w.b_factors)), w.S, w.Omega, oprm, log=logp)
     Xq, qinfo = O.solve(w.terms, O.Tucker(w.b_core, w.b_factors), w.S, w.Omega,
@@ -238,9 +241,11 @@ def test_solve_config1_parity_fp64(tk):
     h_p = np.array([e["res"] for e in logp if "k" in e])
     h_q = np.array([e["res"] for e in logq if "k" in e])
     assert len(h_p) == len(h_o) == len(h_q)
-    bound = history_bound(h_o, [h_p, h_q])
+    bound = bound_from_spreads([rel_spread(h_o, h_p), rel_spread(h_o, h_q), rel_spread(h_g, ip["hist"])], len(h_o))
     dev = np.abs(h_g - h_o) / h_o
-    tb = history_bound(oinfo["true_hist"], [pinfo["true_hist"], qinfo["true_hist"]])
+    tb = bound_from_spreads([rel_spread(oinfo["true_hist"], pinfo["true_hist"]),
+                             rel_spread(oinfo["true_hist"], qinfo["true_hist"]),
+                             rel_spread(info["true_hist"], ip["true_hist"])], len(oinfo["true_hist"]))
     tdev = np.abs(np.array(info["true_hist"]) - np.array(oinfo["true_hist"])) / np.array(oinfo["true_hist"])
     print(f"config 1 cap 16: first divergence above 1e-10 at iteration {first_divergence(h_g, h_o)}; "
           f"later-cycle max dev {dev[n1:].max(initial=0):.2e} (bound {bound[n1:].max(initial=0):.2e}); "
