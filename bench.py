@@ -63,12 +63,12 @@ NOTE = {
 # for a plain copy of known size), valid only for the kernel sources it was
 # measured on: reported as null once any of them changes.
 TRAFFIC = {
-    "jacobi": dict(bytes_per_launch=48153.0,
+    "jacobi": dict(bytes_per_launch=63264.0,
                    sources={"paper_2608_11091_amd/csrc/eig.hip":
-                            "ed3dda42d480fa733f8f2c2b4fd0c8cfcaa07a08b9e2074312b6510f2b47fe84",
+                            "b4ad3c4c476652b35d550bd153857935a0fdc7a245fdfc8ac96884b89caba3ab",
                             "paper_2608_11091_amd/csrc/common.hpp":
-                            "af5e847ac6721fe9377fb2e2d663dbfa81b5ba58d44b4087ccc09f43dc299c71"},
-                   profile="profiles/jacobi_vec_traffic_deblur3d_n512.md"),
+                            "a72a951f0c6374c30ec565058a937f7bb8014779678f6d341fc5b73470946bd8"},
+                   profile="profiles/jacobi_blk_traffic_deblur3d_n512.md"),
 }
 
 

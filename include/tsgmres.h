@@ -327,6 +327,12 @@ int tk_launch_count(int64_t* count);
  * The floor a sequence of k dependent launches cannot go below is about
  * k * *us_per_launch. */
 int tk_launch_latency(int32_t n, void* stream, double* us_per_launch);
+/* Rank certificates of RoundSum's effective-rank rule (Sec. 3.1) on the
+ * current device since the library was loaded: *tried counts the per-mode
+ * checks, *passed those that settled r~_k >= rank cap without the Gram's
+ * spectrum (the sketch width is then cap + p, as the rule gives).  Waits for
+ * the device.  Diagnostics for tests and profiles. */
+int tk_rank_cert_count(int64_t* tried, int64_t* passed);
 
 /* Message of the last error on this thread ("" if none). */
 const char* tk_last_error(void);
@@ -334,8 +340,8 @@ const char* tk_last_error(void);
  * tikhonov and method, tk_mln_params gained tikhonov, tk_sgmres_info gained
  * hist_lambda (all appended), and tsgmres_projected_tikhonov was added.
  * 2.1 (201): tucker_sketch_noalloc was added.  2.2 (202): tk_launch_count and
- * tk_launch_latency were added. */
-#define TK_ABI_VERSION 202
+ * tk_launch_latency were added.  2.3 (203): tk_rank_cert_count was added. */
+#define TK_ABI_VERSION 203
 int tk_version(void);
 
 #ifdef __cplusplus

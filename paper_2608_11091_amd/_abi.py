@@ -18,7 +18,7 @@ ERRORS = {-1: "invalid argument", -2: "shape", -3: "capacity", -4: "workspace", 
           -6: "non-finite", -7: "unsupported"}
 
 # the structures below mirror include/tsgmres.h at this ABI version
-ABI_VERSION = 202
+ABI_VERSION = 203
 
 EXPORTS = [
     "tucker_apply_op", "tucker_apply_op_workspace", "tucker_sketch", "tucker_sketch_workspace",
@@ -28,7 +28,8 @@ EXPORTS = [
     "tucker_mln_sketch", "tucker_mln_sketch_workspace", "tucker_mln_recover", "tucker_mln_recover_workspace",
     "tsgmres_mln_solve", "tsgmres_mln_solve_workspace",
     "tsgmres_projected_tikhonov", "tsgmres_projected_tikhonov_workspace",
-    "tk_kernel_timer", "tk_kernel_timer_read", "tk_launch_count", "tk_launch_latency", "tk_last_error", "tk_version",
+    "tk_kernel_timer", "tk_kernel_timer_read", "tk_launch_count", "tk_launch_latency", "tk_rank_cert_count",
+    "tk_last_error", "tk_version",
 ]
 
 
@@ -116,6 +117,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.tk_kernel_timer_read.argtypes = [C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.tk_launch_count.argtypes = [C.POINTER(C.c_int64)]
     lib.tk_launch_latency.argtypes = [C.c_int32, C.c_void_p, C.POINTER(C.c_double)]
+    lib.tk_rank_cert_count.argtypes = [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.tk_last_error.restype = C.c_char_p
     lib.tk_version.restype = C.c_int
     for name in EXPORTS:

@@ -500,6 +500,15 @@ def launch_latency(n: int = 2000) -> float:
     return float(us.value)
 
 
+def rank_cert_count() -> tuple:
+    """(tried, passed): per-mode rank certificates of the effective-rank rule
+    on the current device since the library was loaded (waits for the
+    device)."""
+    tried, passed = C.c_int64(), C.c_int64()
+    check(_abi.load().tk_rank_cert_count(C.byref(tried), C.byref(passed)))
+    return int(tried.value), int(passed.value)
+
+
 def storage_floats(n: Sequence[int], ranks: Sequence[int]) -> int:
     """Floats stored by a Tucker tensor: sum_k n_k r_k + prod_k r_k."""
     return int(sum(a * b for a, b in zip(n, ranks)) + np.prod(ranks))

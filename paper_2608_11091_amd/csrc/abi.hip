@@ -1068,6 +1068,14 @@ int tk_launch_latency(int32_t n, void* stream, double* us_per_launch) {
   });
 }
 
+int tk_rank_cert_count(int64_t* tried, int64_t* passed) {
+  return guarded([&] {
+    TK_CHECK(tried != nullptr && passed != nullptr, kErrInvalidArg, "count pointer is NULL");
+    rank_cert_counts(tried, passed);
+    return 0;
+  });
+}
+
 const char* tk_last_error(void) { return tk::last_error(); }
 int tk_version(void) { return TK_ABI_VERSION; }
 

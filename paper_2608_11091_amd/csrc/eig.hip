@@ -42,6 +42,15 @@ template <> struct Lim<float> {
   static __device__ constexpr float tiny() { return 1e-37f; }
 };
 
+// A task does nothing when its pair flag or any rank certificate is set.
+template <typename T>
+__device__ __forceinline__ bool task_skipped(const EigTask<T>& t) {
+  if (t.skip != nullptr && *t.skip != 0) return true;
+  bool c = false;
+  for (int i = 0; i < t.ncert; ++i) c |= t.cert[i] != 0;
+  return c;
+}
+
 // Rank rules on a descending spectrum; returns the rank (run by one thread).
 template <typename T>
 __device__ int apply_rule(const EigRule& ru, const T* lam_desc, int N) {
@@ -190,7 +199,7 @@ __global__ __launch_bounds__(TRG_NT) void tridiag_reg_kernel(const EigTask<T>* _
   constexpr int TRG_NW = TRG_NT / kWave;                   // waves
   constexpr int TRG_RC = (VAL_NMAX + TRG_NW - 1) / TRG_NW;  // columns per thread
   const EigTask<T> tk_ = tasks[blockIdx.x];
-  if (tk_.skip != nullptr && *tk_.skip != 0) return;  // the other task of the pair decides
+  if (task_skipped(tk_)) return;
   int N = NL;
   if (tk_.ndyn != nullptr) {
     const int nd = *tk_.ndyn;
@@ -370,7 +379,7 @@ __global__ __launch_bounds__(1024) void tridiag_gm_kernel(const EigTask<T>* __re
   constexpr int NW = NT / kWave;          // 16 waves
   constexpr int RCH = GM_NMAX / kWave;    // row chunks of 64
   const EigTask<T> tk_ = tasks[blockIdx.x];
-  if (tk_.skip != nullptr && *tk_.skip != 0) return;  // the other task of the pair decides
+  if (task_skipped(tk_)) return;
   int N = NL;
   if (tk_.ndyn != nullptr) {
     const int nd = *tk_.ndyn;
@@ -618,7 +627,7 @@ __global__ __launch_bounds__(1024) void jacobi_blk_kernel(const EigTask<T>* __re
   __shared__ int posv[NPM];
   __shared__ T lam_s[NPM];
   const EigTask<T> tk_ = tasks[blockIdx.x];
-  if (tk_.skip != nullptr && *tk_.skip != 0) return;
+  if (task_skipped(tk_)) return;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -632,11 +641,15 @@ __global__ __launch_bounds__(1024) void jacobi_blk_kernel(const EigTask<T>* __re
     const int p = a < b ? a : b, q = a < b ? b : a;
     sch[t][k] = (unsigned short)(p | (q << 8));
   }
-  for (int e = tid; e < NP * LD; e += NT) {
-    const int c = e / LD, r = e % LD;
-    T a = T(0);
-    if (r < N && c < N) a = (r >= c) ? tk_.A[r + (size_t)c * tk_.lda] : tk_.A[c + (size_t)r * tk_.lda];
-    A[e] = a;
+  // the lower triangle, column by column (contiguous reads of whole cache
+  // lines), mirrored into the upper one in LDS; the padding row and column
+  // of an odd order are zero
+  for (int e = tid; e < NP * NP; e += NT) {
+    const int c = e / NP, r = e % NP;
+    if (r < c) continue;
+    const T a = r < N ? tk_.A[r + (size_t)c * tk_.lda] : T(0);
+    A[c * LD + r] = a;
+    A[r * LD + c] = a;
   }
   for (int e = tid; e < NP * LDV; e += NT) {
     const int c = e / LDV, r = e % LDV;
@@ -795,6 +808,66 @@ __global__ __launch_bounds__(1024) void jacobi_blk_kernel(const EigTask<T>* __re
     }
 }
 
+// Rank certificate of the effective-rank rule, one workgroup per mode (the
+// statement is next to its declaration).  The Cholesky factorisation of
+// H - theta I follows the right-looking form of the Cholesky-QR kernel: every
+// thread reads the pivot after the step's barrier, so all threads stop at the
+// same failed pivot; lane j owns column j of the trailing update and the
+// waves stride over its rows.
+constexpr int CERT_NT = 256;
+constexpr int CERT_MAX = 64;
+
+// certificates tried and passed since the library was loaded (per device)
+__device__ unsigned long long g_cert_count[2];
+
+template <typename T>
+__global__ __launch_bounds__(CERT_NT) void rank_cert_kernel(const T* __restrict__ H, const double* __restrict__ w,
+                                                            const double* __restrict__ fro, int nb_act,
+                                                            const double* __restrict__ tau_dev, CertParams cp,
+                                                            int* __restrict__ cert, int* __restrict__ rt) {
+  constexpr int NW = CERT_NT / kWave;
+  __shared__ double G[CERT_MAX][CERT_MAX + 1];
+  __shared__ double red[NW];
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int m = cp.cap;
+  const int nb = min(cp.nb, nb_act);
+  double part = 0.0;
+  for (int b = tid; b < nb; b += CERT_NT) part += w[b] * w[b] * fro[(size_t)k * cp.nb + b];
+  const double tr = block_sum(part, red);
+  const double tau = *tau_dev;
+  const double theta = (4.0 * fmax(cp.delta, tau * tau) + cp.rnd[k]) * tr;
+  const T* Hk = H + (size_t)k * m * m;
+  for (int e = tid; e < m * m; e += CERT_NT) {
+    const int i = e % m, j = e / m;
+    G[i][j] = double(Hk[i + (size_t)j * m]) - (i == j ? theta : 0.0);
+  }
+  __syncthreads();
+  bool ok = tr > 0.0 && tr < INFINITY;  // the same in every thread
+  const int j = lane;
+  for (int kk = 0; kk < m && ok; ++kk) {
+    const double pv = G[kk][kk];
+    if (!(pv > 0.0 && pv < INFINITY)) {
+      ok = false;
+      break;
+    }
+    if (j > kk && j < m) {
+      const double f = G[kk][j] / pv;
+      for (int i = kk + 1 + wave; i <= j; i += NW) G[i][j] -= G[kk][i] * f;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    cert[k] = ok ? 1 : 0;
+    if (ok)
+      for (int i = 0; i < cp.d; ++i) rt[i] = cp.cap;
+    atomicAdd(&g_cert_count[0], 1ull);
+    if (ok) atomicAdd(&g_cert_count[1], 1ull);
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -822,6 +895,30 @@ void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipSt
   TK_LAUNCH_CHECK();
   timer_end(kc, st);
 }
+
+template <typename T>
+void rank_certificate(const T* H, const double* w, const double* fro, int nb_active, const double* tau,
+                      const CertParams& cp, int* cert, int* rt, hipStream_t st) {
+  TK_CHECK(cp.cap >= 1 && cp.cap <= CERT_MAX && cp.d >= 1 && cp.d <= kMaxD && cp.nb >= 1 && nb_active >= 0,
+           kErrUnsupported, "rank certificate: sizes out of range");
+  timer_begin(kKcEigVals, st);
+  hipLaunchKernelGGL((rank_cert_kernel<T>), dim3(cp.d), dim3(CERT_NT), 0, st, H, w, fro, nb_active, tau, cp, cert,
+                     rt);
+  TK_LAUNCH_CHECK();
+  timer_end(kKcEigVals, st);
+}
+
+void rank_cert_counts(int64_t* tried, int64_t* passed) {
+  unsigned long long h[2] = {0, 0};
+  TK_HIP(hipMemcpyFromSymbol(h, HIP_SYMBOL(g_cert_count), sizeof(h), 0, hipMemcpyDeviceToHost));
+  *tried = int64_t(h[0]);
+  *passed = int64_t(h[1]);
+}
+
+template void rank_certificate<double>(const double*, const double*, const double*, int, const double*,
+                                       const CertParams&, int*, int*, hipStream_t);
+template void rank_certificate<float>(const float*, const double*, const double*, int, const double*,
+                                      const CertParams&, int*, int*, hipStream_t);
 
 template void jacobi_eig<double>(const EigTask<double>*, int, int, bool, hipStream_t);
 template void jacobi_eig<float>(const EigTask<float>*, int, int, bool, hipStream_t);

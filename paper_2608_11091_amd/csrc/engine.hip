@@ -511,6 +511,21 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
   const bool rule = cfg.force_s < 0;
   const bool overlap = rule && !cfg.householder;
   const size_t rule_from = q.steps.size();
+  // Where the spectrum is expensive (every FP64 Gram; in FP32 the Grams that
+  // can exceed the register eigensolver's order) the overlap becomes: Grams
+  // on the side stream, and the eigensolves wait on the main stream for the
+  // rank certificate after step 3; when it shows r~_k >= cap for some mode
+  // the width is cap + p and every eigensolve returns at once.  Elsewhere the
+  // eigensolves run on the side stream beside steps 2-3.
+  bool big_gram = false;
+  for (auto& modes : modes_by_n<T>(sh)) {
+    const int n = sh.n[modes[0]];
+    big_gram |= n > kEigRegMax && nb * rc > kEigRegMax;
+  }
+  const bool use_cert = overlap && (std::is_same<T, double>::value || big_gram);
+  int* cert_dev = use_cert ? ar.alloc<int>(kMaxD) : nullptr;
+  double* fro = use_cert ? ar.alloc<double>(size_t(nb) * d) : nullptr;
+  std::vector<std::function<void(hipStream_t)>> eig_steps;
   if (rule) {
     for (auto& modes : modes_by_n<T>(sh)) {
       const int n = sh.n[modes[0]];
@@ -523,6 +538,19 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       // global-memory one (order <= 512) above that, on the R-side Gram while
       // R <= n (capacity permitting) or else on the n-side Gram.
       const int Rp = nb * rc;
+      if (use_cert) {
+        // squared Frobenius norms of the factors: tr(G_k) for the certificate
+        for (int k : modes) {
+          std::vector<const T*> xs;
+          for (int b = 0; b < nb; ++b) xs.push_back(in.U[b][k]);
+          const size_t off = blob.add(xs);
+          const size_t len = size_t(n) * rc;
+          double* out = fro + size_t(k) * nb;
+          q.steps.push_back([=](hipStream_t st) {
+            dot_batched<T>(bl->at<const T*>(off), bl->at<const T*>(off), len, nbA(), 1.0, out, st);
+          });
+        }
+      }
       auto nside_gram = [&](int ldg) {
         T* Gn = ar.alloc<T>(size_t(ldg) * n * modes.size());
         GemmDesc<T> g;
@@ -548,13 +576,17 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       auto eig_launch = [&](std::vector<EigTask<T>> et, int NL) {
         const size_t off_et = blob.add(et);
         const int ne = int(et.size());
-        q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off_et), ne, NL, false, st); });
+        (use_cert ? eig_steps : q.steps).push_back([=](hipStream_t st) {
+          jacobi_eig<T>(bl->at<EigTask<T>>(off_et), ne, NL, false, st);
+        });
       };
       auto rule_task = [&](T* A, int lda, T* lam, int k) {
         EigTask<T> e{};
         e.A = A;
         e.lda = lda;
         e.lam = lam;
+        e.cert = cert_dev;
+        e.ncert = use_cert ? d : 0;
         e.rule.kind = 1;
         e.rule.tau = epsd + 1;
         e.rule.delta = cfg.delta;
@@ -752,7 +784,84 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
         }
     }
   }
-  if (overlap) {
+  if (use_cert) {
+    // Rank certificate (Courant-Fischer): for Q_k' = the first cap columns of
+    // the orthonormal range basis, lambda_cap(G_k) >= lambda_min(Q_k'^T G_k Q_k')
+    // for the rule's Gram G_k = sum_b w_b^2 U_bk U_bk^T, so a Cholesky
+    // factorisation of Q_k'^T G_k Q_k' - theta I settles r~_k >= cap without the
+    // spectrum (rank_certificate).  theta covers the rounding of
+    // P_bk = w_b Q_k'^T U_bk (inner dimension n) and of sum_b P_bk P_bk^T
+    // (inner dimension at most nb rc): 4 (n sqrt(cap) + nb rc) u tr(G_k).
+    const int cp_ = sh.cap;
+    T* Pm = ar.alloc<T>(size_t(nb) * d * cp_ * rc);
+    T* Hc = ar.alloc<T>(size_t(d) * cp_ * cp_);
+    for (auto& modes : modes_by_n<T>(sh)) {
+      const int n = sh.n[modes[0]];
+      {
+        // P_bk (cap x rc); groups ordered by block, so the active ones are a prefix
+        GemmDesc<T> g;
+        g.ta = true;
+        g.tb = false;
+        g.M = cp_;
+        g.N = rc;
+        g.K = n;
+        g.lda = n;
+        g.ldb = n;
+        g.ldc = cp_;
+        g.nb = nb_active;
+        const int nmod = int(modes.size());
+        g.ngroups_of = [nmod](int a) { return a * nmod; };
+        for (int b = 0; b < nb; ++b)
+          for (int k : modes) g.group1(Pm + (size_t(k) * nb + b) * cp_ * rc, Uh[k], in.U[b][k], w + b);
+        emit_gemm(q, pl, std::move(g));
+      }
+      {
+        // H_k = sum_b P_bk P_bk^T (cap x cap)
+        GemmDesc<T> g;
+        g.ta = false;
+        g.tb = true;
+        g.M = cp_;
+        g.N = cp_;
+        g.K = rc;
+        g.lda = cp_;
+        g.ldb = cp_;
+        g.ldc = cp_;
+        g.nb = nb_active;
+        g.terms_are_blocks = nb_active != nullptr;
+        for (int k : modes) {
+          std::vector<GemmTerm<T>> ts;
+          for (int b = 0; b < nb; ++b) {
+            const T* P = Pm + (size_t(k) * nb + b) * cp_ * rc;
+            ts.push_back(term<T>(P, P));
+          }
+          g.group(Hc + size_t(k) * cp_ * cp_, ts);
+        }
+        emit_gemm(q, pl, std::move(g));
+      }
+    }
+    CertParams cpar{};
+    cpar.d = d;
+    cpar.cap = cp_;
+    cpar.nb = nb;
+    cpar.delta = cfg.delta;
+    const double uT = std::is_same<T, double>::value ? 0x1p-53 : 0x1p-24;
+    for (int k = 0; k < d; ++k)
+      cpar.rnd[k] = 4.0 * (double(sh.n[k]) * std::sqrt(double(cp_)) + double(nb) * rc) * uT;
+    int* rt_ = rt;
+    // join the Grams and norms, certify, run the eigensolves that the
+    // certificate left, then keep the leading s columns of every basis
+    q.steps.push_back(join);
+    q.steps.push_back([=](hipStream_t st) {
+      rank_certificate<T>(Hc, w, fro, nbA(), epsd + 1, cpar, cert_dev, rt_, st);
+    });
+    for (auto& f : eig_steps) q.steps.push_back(f);
+    emit_width();
+    for (int k = 0; k < d; ++k) {
+      T* u = Uh[k];
+      const int n = sh.n[k];
+      q.steps.push_back([=](hipStream_t st) { zero_cols_from<T>(u, n, n, sc, s_dev, st); });
+    }
+  } else if (overlap) {
     // join the rule, then keep the leading s columns of every basis
     q.steps.push_back(join);
     emit_width();

@@ -141,6 +141,8 @@ struct EigTask {
   T* V;          // eigenvectors (ld = launch N); for rule kind 2 columns >= rank are zeroed
   const int* ndyn; // optional device size (< launch N); negative: skip, rank_out = -1
   const int* skip; // optional device flag: nonzero = do nothing (another task of the launch pair decides)
+  const int* cert; // optional device flags cert[0..ncert): any nonzero = do nothing (the rank certificate decided)
+  int ncert;
   EigRule rule;
 };
 // Eigenvalues only: N <= 512; above kEigRegMax the matrix is reduced in place
@@ -148,6 +150,29 @@ struct EigTask {
 constexpr int kEigRegMax = 160;
 template <typename T>
 void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipStream_t st);
+
+// Certificate for the effective-rank rule of RoundSum (Sec. 3.1), one task
+// per mode k.  H_k = Q_k^T G_k Q_k (cap x cap, ld cap, T) is the compression of
+// the rule's Gram G_k = sum_b w_b^2 U_bk U_bk^T onto the first cap columns of
+// the range-finder basis Q_k; tr(G_k) = sum_{b < nb_active} w_b^2 fro[k nb + b]
+// with fro the squared Frobenius norms of the factors (nb_active: the number
+// of live blocks, a host value).  If H_k - theta_k I has
+// a Cholesky factorisation, theta_k = (4 max(delta, tau^2) + rnd[k]) tr(G_k)
+// (rnd[k]: bound on the rounding of H_k relative to tr(G_k)), then the cap-th
+// eigenvalue of G_k exceeds both the zero clamp and the tail threshold, so
+// r~_k >= cap and the sketch width is cap + p: cert[k] = 1 and rt[0..d) = cap.
+// Otherwise cert[k] = 0 and rt is left alone.
+struct CertParams {
+  int d, cap, nb;
+  double delta;
+  double rnd[kMaxD];
+};
+// Certificates tried (one per mode) and passed on the current device since
+// the library was loaded (synchronises the device).
+void rank_cert_counts(int64_t* tried, int64_t* passed);
+template <typename T>
+void rank_certificate(const T* H, const double* w, const double* fro, int nb_active, const double* tau,
+                      const CertParams& cp, int* cert, int* rt, hipStream_t st);
 
 // Per mode k: R_k = sum_b rank_b[k]; enable[k] = (R_k <= rmax); nact[k] = R_k or -1.
 // Then the padded Gram (blocks of rc rows/cols) is compacted to its R_k x R_k

@@ -8,7 +8,23 @@ Cases (each built so that the rule, not the cap, sets s):
   * n = 512, twelve rank-48 blocks (R = 576 > n): the n-side 512 x 512 Gram;
   * n = 300, five rank-40 blocks (R = 200 < n): the R-side 200 x 200 Gram;
   * n = 512 with graded block weights and tau = 0.02: the tail rule itself
-    (not a numerical rank) decides, on the n-side Gram."""
+    (not a numerical rank) decides, on the n-side Gram.
+In all three the device's rank certificate (Courant-Fischer on the
+range-finder basis, which settles r~ >= cap without the spectrum) is tried
+and must decline: r~ < cap.  The last case guards its tau^2 term: with the
+zero clamp alone the certificate would pass there.
+
+The certificate is planned for every FP64 RoundSum and, in the FP32 form,
+for the sums whose Gram can exceed the register eigensolver's order 160
+(elsewhere the FP32 spectrum is cheaper than the certificate and runs beside
+the range sketch).  Cases where it must pass (r~ >= cap, s = cap + p), with s
+identical to the oracle's:
+  * the operator sum lambda V + (M x M x M) V at n = 512, cap 48 (factors
+    [U, M U]: the RoundSum of every sGMRES iteration), FP64; in FP32 (Gram
+    order 96) the spectrum path runs and no certificate is tried;
+  * a sixty-block sum (the final assembly of a 60-iteration cycle), where
+    the rule would otherwise need the 512 x 512 n-side spectrum, FP64 and
+    FP32."""
 import numpy as np
 import pytest
 
@@ -46,16 +62,20 @@ def _subspace_blocks(rng, n, nb, r, dim):
     return out
 
 
-def _run(tk, blocks, cap, p, eps, tau=None):
+def _run(tk, blocks, cap, p, eps, tau=None, form=0, expect_cert=False, expect_tried=True):
     n = blocks[0][1].n
     rng = np.random.default_rng(99)
     Om = [rng.standard_normal((nk, cap + p)) for nk in n]
     prm = O.RoundParams(eps=eps, cap=cap, p=p, tau=tau)
     Xo, info = O.roundsum(blocks, Om, prm)
     gb = [(c, tk.Tucker.from_numpy(X.core, X.U, rcap=(X.core.shape[0],) * len(n))) for c, X in blocks]
-    Xg, s = tk.rhosvd(gb, [_cm(o) for o in Om], eps=eps, cap=cap, p=p, tau=-1.0 if tau is None else tau)
+    t0, p0 = tk.rank_cert_count()
+    Xg, s = tk.rhosvd(gb, [_cm(o) for o in Om], eps=eps, cap=cap, p=p, tau=-1.0 if tau is None else tau, form=form)
+    t1, p1 = tk.rank_cert_count()
     print("oracle s", info["s"], "r~", info["rtilde"], "ranks", info["ranks"], "| gpu s", s, "ranks", Xg.ranks,
-          flush=True)
+          "| certificates tried", t1 - t0, "passed", p1 - p0, flush=True)
+    assert t1 - t0 == (len(n) if expect_tried else 0)   # one check per mode
+    assert (p1 - p0 > 0) == expect_cert
     return Xo, info, Xg, s
 
 
@@ -92,3 +112,42 @@ def test_rank_rule_tail_threshold_512(tk):
     assert s == info["s"]
     assert list(Xg.ranks) == list(info["ranks"])
     assert _dist(O.Tucker(*Xg.to_numpy()), Xo) <= 1e-10
+
+
+def _operator_sum(rng, n, cap, lam=1e-3):
+    U = [np.linalg.qr(rng.standard_normal((nk, cap)))[0] for nk in n]
+    M = []
+    for nk in n:
+        Q = np.linalg.qr(rng.standard_normal((nk, nk)))[0]
+        M.append((Q * np.linspace(1.0, 1e-4, nk)) @ Q.T)
+    core = rng.standard_normal((cap,) * len(n))
+    return [(lam, O.Tucker(core, U)), (1.0, O.Tucker(core, [Mk @ Uk for Mk, Uk in zip(M, U)]))]
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_rank_certificate_operator_sum_512(tk, form):
+    rng = np.random.default_rng(24)
+    blocks = _operator_sum(rng, (512, 512, 512), cap=48)
+    Xo, info, Xg, s = _run(tk, blocks, cap=48, p=5, eps=1e-10, form=form, expect_cert=form == 0,
+                           expect_tried=form == 0)
+    assert info["s"] == 53 and s == 53
+    assert list(Xg.ranks) == list(info["ranks"])
+    Xc = O.Tucker(*Xg.to_numpy())
+    assert _dist(Xc, Xo) <= (1e-10 if form == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_rank_certificate_sixty_blocks_512(tk, form):
+    # sixty orthonormal rank-48 blocks with decaying coefficients, as in the
+    # final assembly sum_i y_i V_i of a 60-iteration cycle (R = 2880 > n)
+    rng = np.random.default_rng(25)
+    n, cap = (512, 512, 512), 48
+    blocks = []
+    for i in range(60):
+        U = [np.linalg.qr(rng.standard_normal((nk, cap)))[0] for nk in n]
+        core = rng.standard_normal((cap,) * 3)
+        blocks.append((float(0.8 ** i * rng.choice([-1.0, 1.0])), O.Tucker(core / np.linalg.norm(core), U)))
+    Xo, info, Xg, s = _run(tk, blocks, cap=cap, p=5, eps=1e-10, form=form, expect_cert=True)
+    assert info["s"] == 53 and s == 53
+    assert list(Xg.ranks) == list(info["ranks"])
+    assert _dist(O.Tucker(*Xg.to_numpy()), Xo) <= (1e-10 if form == 0 else 1e-5)
