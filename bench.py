@@ -110,7 +110,8 @@ def host_cpu():
 def cpu_baseline(w, iters: int, iters_1thread: int):
     """The FP64 oracle on a bounded sample: the first `iters` sGMRES
     iterations of one cycle of the same workload, timed on the host cores
-    with every BLAS/OpenMP thread, and a shorter sample with one thread."""
+    with every BLAS/OpenMP thread and again with one thread (its small dense
+    products gain little from threads)."""
     import oracle as O
     from threadpoolctl import threadpool_info, threadpool_limits
     cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
@@ -400,7 +401,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-restarts", type=int, default=8)
     ap.add_argument("--cpu-iters", type=int, default=60)
-    ap.add_argument("--cpu-iters-1thread", type=int, default=10)
+    ap.add_argument("--cpu-iters-1thread", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mln", action="store_true", help="skip the MLN-Tucker sGMRES measurement")
