@@ -40,7 +40,8 @@ void dot_batched(const T* const* xs, const T* const* ys, size_t len, int n, doub
                  hipStream_t st);
 
 // ---- elementwise --------------------------------------------------------------
-// y = alpha * x with alpha = scale * (*num) / (*den) (num/den optional device scalars).
+// y = alpha * x with alpha = scale * (*num) / (*den) (num/den optional device
+// scalars; a denominator that is not positive and finite gives alpha = 0).
 template <typename T>
 void scale_copy(const T* x, T* y, size_t len, double scale, const double* num, const double* den,
                 hipStream_t st);
@@ -270,6 +271,7 @@ struct LsState {
   double beta_s_inv;   // not used when bs_norm is given
   const double* bs_norm; // device ||b_s||
   double* lam = nullptr; // regularisation parameter per column (kmax), when regularised
+  double* ysave = nullptr; // kmax x kmax: column k holds y after column k was added (optional)
 };
 void ls_add_column(const LsState& st_, int s, int kmax, int k, double conv_tol, double breakdown_tol,
                    hipStream_t st);

@@ -87,7 +87,10 @@ __global__ __launch_bounds__(LS_NT) void ls_add_kernel(LsState S, int s, int kma
       if (lane == r) b = yr;
       else if (lane < r) b -= S.R[lane + (size_t)r * kmax] * yr;
     }
-    if (lane <= k) S.y[lane] = b;
+    if (lane <= k) {
+      S.y[lane] = b;
+      if (S.ysave) S.ysave[(size_t)k * kmax + lane] = b;
+    }
   }
   if (i == 0) {
     const double nrm2 = *S.nrmM2 + cn;
@@ -309,6 +312,7 @@ __global__ __launch_bounds__(LS_NT) void ls_tikhonov_kernel(LsState S, int s, in
       if (den > 0.0) y = fma(X[tid + i * kTkLd], bh[i] / den, y);
     }
     S.y[tid] = y;
+    if (S.ysave) S.ysave[(size_t)k * kmax + tid] = y;
   }
   if (w == 0) {
     const double gi = lane < K ? gcv_g(sg2[lane], l2) : 0.0;

@@ -72,8 +72,10 @@ struct Cycle {
   double *Hv, *tau, *R, *qtb, *y, *res, *nrmM2, *lam;
   int* flags;
   IterStatus* st_dev;
-  IterStatus* st_host = nullptr;  // pinned
+  IterStatus* st_host = nullptr;  // pinned, two slots (iteration parity)
   double* lam_host = nullptr;     // pinned, maxiter
+  double* ysave = nullptr;        // maxiter x maxiter: y after each iteration
+  hipEvent_t st_ev[2] = {nullptr, nullptr};
   Seq setup, fin;
   std::vector<Seq> iter;
   int nb_final = 0;
@@ -84,6 +86,8 @@ struct Cycle {
   ~Cycle() {
     if (st_host) (void)hipHostFree(st_host);
     if (lam_host) (void)hipHostFree(lam_host);
+    for (auto& e : st_ev)
+      if (e) (void)hipEventDestroy(e);
   }
 
   void plan(Planner& pl, const OpDev<T>& op, bool transpose, const std::array<const T*, kMaxD>& S,
@@ -120,12 +124,14 @@ struct Cycle {
     res = ar.alloc<double>(maxiter);
     nrmM2 = ar.alloc<double>(1);
     lam = ar.alloc<double>(maxiter);
+    ysave = ar.alloc<double>(size_t(maxiter) * maxiter);
     flags = ar.alloc<int>(4);
     st_dev = ar.alloc<IterStatus>(1);
-    ls = LsState{Mcols, bs, Hv, tau, R, qtb, y, res, nrmM2, flags, 0.0, bsn, lam};
+    ls = LsState{Mcols, bs, Hv, tau, R, qtb, y, res, nrmM2, flags, 0.0, bsn, lam, ysave};
     if (!ar.measuring()) {
-      TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&st_host), sizeof(IterStatus), 0));
+      TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&st_host), 2 * sizeof(IterStatus), 0));
       TK_HIP(hipHostMalloc(reinterpret_cast<void**>(&lam_host), sizeof(double) * maxiter, 0));
+      for (auto& e : st_ev) TK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
 
     RoundCfg rcfg;
@@ -239,15 +245,34 @@ struct Cycle {
     conv_tol = (full ? 1.0 : eta) * tol_in;
     setup.run(st);
     int status = kNotConverged, kend = maxiter;
-    for (int k = 0; k < maxiter; ++k) {
+    // Iteration k + 1 is enqueued before the host reads iteration k's status,
+    // so the device does not drain while the host launches the next
+    // iteration.  If k ends the cycle, the extra iteration's results are
+    // never read: it writes V[k + 2] (Z[k + 1]), the next least-squares column
+    // and status, and the final assembly takes y as it was after iteration k.
+    // Near convergence (the last known residual within kSpecMargin of the
+    // cycle's tolerance) iterations are enqueued one at a time, so a
+    // converging cycle does not pay for an iteration it does not need.
+    constexpr double kSpecMargin = 1e6;
+    auto enqueue = [&](int k) {
       iter[k].run(st);
-      TK_HIP(hipMemcpyAsync(st_host, st_dev, sizeof(IterStatus), hipMemcpyDeviceToHost, st));
-      TK_HIP(hipStreamSynchronize(st));
-      const IterStatus s = *st_host;
+      TK_HIP(hipMemcpyAsync(st_host + (k & 1), st_dev, sizeof(IterStatus), hipMemcpyDeviceToHost, st));
+      TK_HIP(hipEventRecord(st_ev[k & 1], st));
+    };
+    double last_res = 1.0;  // relative residual of B before the first iteration
+    int queued = 0;         // iterations enqueued so far
+    for (int k = 0; k < maxiter; ++k) {
+      if (queued == k) enqueue(queued++);
+      if (queued == k + 1 && k + 1 < maxiter && last_res > kSpecMargin * conv_tol) enqueue(queued++);
+      TK_HIP(hipEventSynchronize(st_ev[k & 1]));
+      const IterStatus s = st_host[k & 1];
+      last_res = s.res;
       info.hist_sketched.push_back(s.res);
       for (int j = 0; j < sh.d; ++j) info.hist_ranks.push_back(s.rank[j]);
-      if (!std::isfinite(s.res) || !std::isfinite(s.omega))
+      if (!std::isfinite(s.res) || !std::isfinite(s.omega)) {
+        TK_HIP(hipStreamSynchronize(st));  // no enqueued iteration outlives the error
         throw Error{kErrNonFinite, "non-finite sketched residual or basis norm"};
+      }
       if (s.breakdown_ls || s.breakdown_w) {
         status = kBreakdown;
         kend = k + 1;
@@ -260,6 +285,8 @@ struct Cycle {
       }
     }
     nb_final = kend;
+    // the least-squares solution of the last iteration that counts
+    TK_HIP(hipMemcpyAsync(y, ysave + size_t(kend - 1) * maxiter, sizeof(double) * kend, hipMemcpyDeviceToDevice, st));
     fin.run(st);
     if (tikhonov) {
       TK_HIP(hipMemcpyAsync(lam_host, lam, sizeof(double) * kend, hipMemcpyDeviceToHost, st));

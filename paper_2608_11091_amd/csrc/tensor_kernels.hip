@@ -159,7 +159,12 @@ __global__ void scale_kernel(const T* __restrict__ x, T* __restrict__ y, size_t 
                              const double* den) {
   double a = scale;
   if (num) a *= *num;
-  if (den) a /= *den;
+  if (den) {
+    // a norm as denominator: zero (a breakdown) or non-finite gives a zero
+    // result instead of inf / NaN
+    const double dv = *den;
+    a = (dv > 0.0 && dv < INFINITY) ? a / dv : 0.0;
+  }
   const T at = T(a);
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
     y[e] = at * x[e];
