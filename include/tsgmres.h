@@ -37,6 +37,13 @@
  *     entry, products, Gram matrices, eigensolves and contractions run in
  *     FP32 (matrix cores with FP32 accumulation), the range-sketch QR of a
  *     RoundSum stays FP64, and results are widened to FP64 on exit.
+ *     TK_FORM_BF16 (tucker_apply_op, tucker_sketch, tucker_rhosvd only) is the
+ *     FP32 form with bfloat16 factors: every product with a Tucker factor
+ *     (operator factors times U, S_k^T U_k, U^T Omega, the range-sketch sum
+ *     and the core projection) rounds both operands to bfloat16 (round to
+ *     nearest even) and runs on the BF16 matrix cores with FP32 accumulation;
+ *     cores, Grams, QRs and eigensolves keep the FP32 form's arithmetic.  The
+ *     solver runs in FP64 or FP32 only.
  */
 #ifndef TSGMRES_H_
 #define TSGMRES_H_
@@ -65,7 +72,7 @@ extern "C" {
 #define TK_ERR_NONFINITE -6
 #define TK_ERR_UNSUPPORTED -7 /* outside the limits listed above */
 
-typedef enum { TK_FORM_FP64 = 0, TK_FORM_FP32 = 1 } tk_form;
+typedef enum { TK_FORM_FP64 = 0, TK_FORM_FP32 = 1, TK_FORM_BF16 = 2 } tk_form;
 
 /* Tucker tensor (Sec. 2.3, Tucker format equation). */
 typedef struct {
@@ -340,8 +347,9 @@ const char* tk_last_error(void);
  * tikhonov and method, tk_mln_params gained tikhonov, tk_sgmres_info gained
  * hist_lambda (all appended), and tsgmres_projected_tikhonov was added.
  * 2.1 (201): tucker_sketch_noalloc was added.  2.2 (202): tk_launch_count and
- * tk_launch_latency were added.  2.3 (203): tk_rank_cert_count was added. */
-#define TK_ABI_VERSION 203
+ * tk_launch_latency were added.  2.3 (203): tk_rank_cert_count was added.
+ * 2.4 (204): TK_FORM_BF16 for the per-call entry points. */
+#define TK_ABI_VERSION 204
 int tk_version(void);
 
 #ifdef __cplusplus

@@ -18,7 +18,7 @@ ERRORS = {-1: "invalid argument", -2: "shape", -3: "capacity", -4: "workspace", 
           -6: "non-finite", -7: "unsupported"}
 
 # the structures below mirror include/tsgmres.h at this ABI version
-ABI_VERSION = 203
+ABI_VERSION = 204
 
 EXPORTS = [
     "tucker_apply_op", "tucker_apply_op_workspace", "tucker_sketch", "tucker_sketch_workspace",

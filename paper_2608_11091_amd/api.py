@@ -158,7 +158,8 @@ def _ptr_array(ts: Sequence[Optional[torch.Tensor]]):
 
 def apply_op(op: KronOp, x: Tucker, transpose: bool = False, form: int = 0):
     """Factor products of ``L(x)``; returns the block list ``[(alpha_j, Tucker)]``.
-    ``form`` 1 computes them in FP32 (results widened to FP64)."""
+    ``form`` 1 computes them in FP32, 2 with bfloat16 operands on the BF16
+    matrix cores (FP32 accumulation); results are widened to FP64."""
     lib = _abi.load()
     d = x.d
     AU = []
@@ -181,7 +182,7 @@ def apply_op(op: KronOp, x: Tucker, transpose: bool = False, form: int = 0):
 
 def sketch(blocks, S: Sequence[torch.Tensor], form: int = 0) -> torch.Tensor:
     """Khatri-Rao sketch ``S^T vec(sum_b c_b X_b)`` (length s); ``form`` 1
-    computes it in FP32."""
+    computes it in FP32, 2 with bfloat16 factor products."""
     lib = _abi.load()
     bs, keep = _blocks_struct(blocks)
     s = int(S[0].shape[0])
@@ -213,7 +214,8 @@ def rhosvd(blocks, omega: Sequence[torch.Tensor], eps: float, cap: int, p: int =
            force_s: int = -1, force_ranks: Optional[Sequence[int]] = None, out_rcap: Optional[Sequence[int]] = None,
            form: int = 0):
     """RoundSum of a block sum; returns ``(Tucker, s)``.  ``form`` 1 runs it in
-    the FP32 form's arithmetic (FP64 range-sketch QR)."""
+    the FP32 form's arithmetic (FP64 range-sketch QR), 2 in the FP32 form
+    with bfloat16 factor products."""
     lib = _abi.load()
     bs, keep = _blocks_struct(blocks)
     x0 = blocks[0][1]

@@ -132,7 +132,7 @@ const float* emit_to_f32(Seq& q, Arena& ar, const double* src, size_t len) {
   return dst;
 }
 void check_form(int form) {
-  TK_CHECK(form == TK_FORM_FP64 || form == TK_FORM_FP32, kErrUnsupported, "unknown form");
+  TK_CHECK(form == TK_FORM_FP64 || form == TK_FORM_FP32 || form == TK_FORM_BF16, kErrUnsupported, "unknown form");
 }
 
 void finish_blob(Arena& ar, Blob& blob, hipStream_t st) {
@@ -162,9 +162,11 @@ int do_apply(const tk_kron_op* op, const tk_tucker* x, int transpose, int form, 
   const int d = x->d;
   Blob blob;
   Planner pl(ar, blob);
+  pl.bf16_factors = form == TK_FORM_BF16;
+  const bool f32 = form != TK_FORM_FP64;  // FP32 storage (FP32 and BF16-factor forms)
   Seq q;
   std::array<const float*, kMaxD> U32{};
-  if (form == TK_FORM_FP32)
+  if (f32)
     for (int k = 0; k < d; ++k) U32[k] = emit_to_f32(q, ar, x->U[k], size_t(x->n[k]) * x->rcap[k]);
   for (int j = 0; j < op->nterms; ++j)
     for (int k = 0; k < d; ++k) {
@@ -172,10 +174,10 @@ int do_apply(const tk_kron_op* op, const tk_tucker* x, int transpose, int form, 
       if (!A) continue;
       TK_CHECK(AU != nullptr && AU[j * d + k] != nullptr, kErrInvalidArg, "missing output buffer for a factor product");
       const int n = int(x->n[k]), rcap = int(x->rcap[k]);
-      if (form == TK_FORM_FP32) {
+      if (f32) {
         const float* A32 = emit_to_f32(q, ar, A, size_t(n) * n);
         float* P32 = ar.alloc<float>(size_t(n) * rcap);
-        plan_gemm<float>(q, pl, !transpose, false, n, rcap, n, A32, n, U32[k], n, P32, n, 1.0, 0.0);
+        plan_gemm<float>(q, pl, !transpose, false, n, rcap, n, A32, n, U32[k], n, P32, n, 1.0, 0.0, true);
         double* dst = AU[j * d + k];
         const size_t len = size_t(n) * rcap;
         q.steps.push_back([=](hipStream_t st) { cast_copy<float, double>(P32, dst, len, st); });
@@ -301,7 +303,8 @@ int do_sketch(const tk_block_sum* x, const double* const* S, int64_t s, int form
     TK_CHECK(S[k] != nullptr, kErrInvalidArg, "sketch factor is NULL");
     Sk[k] = S[k];
   }
-  if (form == TK_FORM_FP32) {
+  pl.bf16_factors = form == TK_FORM_BF16;
+  if (form != TK_FORM_FP64) {
     std::array<const float*, kMaxD> S32{};
     for (int k = 0; k < im.sh.d; ++k) S32[k] = emit_to_f32(q, ar, Sk[k], size_t(im.sh.n[k]) * s);
     Blocks<float> b32 = blocks_f32(q, ar, im);
@@ -344,7 +347,8 @@ int do_rhosvd(const tk_block_sum* in, const tk_round_params* prm, const double* 
   check_form(prm->form);
   TT<double> o = alloc_tt<double>(ar, sh);
   int* s_dev = nullptr;
-  if (prm->form == TK_FORM_FP32) {
+  pl.bf16_factors = prm->form == TK_FORM_BF16;
+  if (prm->form != TK_FORM_FP64) {
     std::array<const float*, kMaxD> om32{};
     for (int k = 0; k < sh.d; ++k) om32[k] = emit_to_f32(q, ar, om[k], size_t(sh.n[k]) * sh.sc());
     Blocks<float> b32 = blocks_f32(q, ar, im);

@@ -23,6 +23,7 @@ struct GemmDesc {
   const int* nb = nullptr;
   std::function<int(int)> ngroups_of;  // active groups as a function of *nb
   bool terms_are_blocks = false;       // clamp each group's terms to *nb
+  bool factor_product = false;         // a product with a Tucker factor (BF16 in the BF16-factor form)
 
   void group(T* C, const std::vector<GemmTerm<T>>& ts) {
     GemmGroup<T> g;
@@ -76,6 +77,7 @@ void emit_gemm(Seq& q, Planner& pl, GemmDesc<T>&& g) {
   L.beta = g.beta;
   L.splits = splits;
   L.partial = partial;
+  L.bf16 = std::is_same<T, float>::value && pl.bf16_factors && g.factor_product;
   L.ngroups = ng;
   const int* nb = g.nb;
   auto ngf = g.ngroups_of;
@@ -291,6 +293,7 @@ void plan_krp_range(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>& in, c
     g.ngroups_of = [nm](int a) { return a * nm; };
     for (int b = 0; b < nb; ++b)
       for (int j : modes) g.group1(Mp(b, j), in.U[b][j], L[j]);
+    g.factor_product = true;
     emit_gemm(q, pl, std::move(g));
   }
   T* Zl = ar.alloc<T>(size_t(nb) * P * w);
@@ -374,6 +377,7 @@ void plan_krp_range(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>& in, c
       for (int b = 0; b < nb; ++b) ts.push_back(term<T>(in.U[b][k], Tp(b, k), coef + b));
       g.group(Y[k], ts);
     }
+    g.factor_product = true;
     emit_gemm(q, pl, std::move(g));
   }
 }
@@ -406,6 +410,7 @@ void plan_core_projection(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>&
     g.ngroups_of = [nm](int a) { return a * nm; };
     for (int b = 0; b < nb; ++b)
       for (int k : modes) g.group1(Wp(b, k), Pm[k], in.U[b][k]);
+    g.factor_product = true;
     emit_gemm(q, pl, std::move(g));
   }
   // after the TTM of mode k (k = d-1 .. 1) the block tensor has dims
@@ -1030,6 +1035,7 @@ Blocks<T> plan_apply(Seq& q, Planner& pl, const Shape& sh, const OpDev<T>& op, c
     for (auto& key : order)
       if (std::find(modes.begin(), modes.end(), key.second) != modes.end())
         g.group1(prod[key], key.first, x.U[key.second]);
+    g.factor_product = true;
     emit_gemm(q, pl, std::move(g));
   }
   Blocks<T> out;
@@ -1069,6 +1075,7 @@ void plan_sketch(Seq& q, Planner& pl, const Shape& sh, const Blocks<T>& in, cons
     g.ldc = rc;
     for (int b = 0; b < nb; ++b)
       for (int k : modes) g.group1(Pp(b, k), in.U[b][k], S[k]);
+    g.factor_product = true;
     emit_gemm(q, pl, std::move(g));
   }
   T* Z = ar.alloc<T>(size_t(nb) * P * s);
@@ -1400,8 +1407,9 @@ void plan_unfold_gram(Seq& q, Planner& pl, int d, const int* dims, int k, const 
 
 template <typename T>
 void plan_gemm(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int K, const T* A, int lda, const T* B, int ldb,
-               T* C, int ldc, double alpha, double beta) {
+               T* C, int ldc, double alpha, double beta, bool factor_product) {
   GemmDesc<T> g;
+  g.factor_product = factor_product;
   g.ta = ta;
   g.tb = tb;
   g.M = M;
@@ -1512,7 +1520,7 @@ void plan_precond(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, c
   template void plan_ttm<T>(Seq&, Planner&, int, const int*, int, int, const T*, const T*, int, bool, T*);     \
   template void plan_unfold_gram<T>(Seq&, Planner&, int, const int*, int, const T*, const T*, T*, int, double); \
   template void plan_gemm<T>(Seq&, Planner&, bool, bool, int, int, int, const T*, int, const T*, int, T*, int,   \
-                             double, double);                                                                  \
+                             double, double, bool);                                                                  \
   template RoundSumOut<T> plan_roundsum<T>(Seq&, Planner&, const Shape&, const Blocks<T>&, const RoundCfg&,   \
                                            const std::array<const T*, kMaxD>&, const TT<T>&, const int*);      \
   template Blocks<T> plan_apply<T>(Seq&, Planner&, const Shape&, const OpDev<T>&, const TT<T>&, bool,         \

@@ -107,6 +107,12 @@ struct RoundCfg {
 struct Planner {
   Arena& ar;
   Blob& blob;
+  // BF16-factor form (FP32 plans only): the products that multiply a Tucker
+  // factor (operator factors times U, sketch factors, range-finder Omega and
+  // basis products) round their operands to bfloat16 and run on the BF16
+  // matrix cores with FP32 accumulation; cores, Grams, QRs and eigensolves
+  // keep FP32 / FP64.
+  bool bf16_factors = false;
   Planner(Arena& a, Blob& b) : ar(a), blob(b) {}
 };
 
@@ -154,10 +160,11 @@ void plan_ttm(Seq& q, Planner& pl, int d, const int* dims, int k, int newdim, co
 template <typename T>
 void plan_unfold_gram(Seq& q, Planner& pl, int d, const int* dims, int k, const T* X, const T* Y, T* G, int ldg,
                       double scale);
-// C = alpha * op(A) op(B) (+ beta C): a single plain GEMM.
+// C = alpha * op(A) op(B) (+ beta C): a single plain GEMM (`factor_product`:
+// one operand is a Tucker factor, BF16 operands in the BF16-factor form).
 template <typename T>
 void plan_gemm(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int K, const T* A, int lda, const T* B, int ldb,
-               T* C, int ldc, double alpha, double beta);
+               T* C, int ldc, double alpha, double beta, bool factor_product = false);
 
 // C_i = alpha op(A_i) op(B_i) for equally shaped problems, one launch.
 template <typename T>

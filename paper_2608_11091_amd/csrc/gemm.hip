@@ -26,6 +26,21 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 operand form (FP32 storage and accumulation): operands are rounded to
+// bfloat16 (round to nearest even; NaN kept quiet) as they are staged, and
+// multiplied on v_mfma_f32_16x16x16_bf16.  Lane l supplies rows / columns
+// l % 16 and the four consecutive k values 4 (l / 16) .. 4 (l / 16) + 3.
+typedef short s4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
 constexpr int SA = (BM * BK) / NT, SB = (BN * BK) / NT;  // staged elements per thread
 
@@ -34,13 +49,17 @@ constexpr int SA = (BM * BK) / NT, SB = (BN * BK) / NT;  // staged elements per 
 // second pass sums the partials in split order.  (Summing them in the last
 // workgroup to arrive at a tile needs device-scope fences, whose L2
 // write-back across the XCDs cost more than the second launch.)
-template <typename T, bool TA, bool TB>
+template <typename T, bool TA, bool TB, bool BF = false>
 __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, int ldb, int ldc,
                                                   const GemmTerm<T>* __restrict__ terms,
                                                   const GemmGroup<T>* __restrict__ groups, double beta,
                                                   int splits, T* __restrict__ partial, int max_terms) {
-  __shared__ T As[BK][BM + 1];
-  __shared__ T Bs[BK][BN + 1];
+  static_assert(!BF || sizeof(T) == 4, "bf16 operands with FP32 storage only");
+  constexpr int BKP = BK + 4;  // bf16 row: 16 k values + 4 pad (40 bytes: conflict-free 8-byte reads)
+  __shared__ T As[BF ? 1 : BK][BM + 1];
+  __shared__ T Bs[BF ? 1 : BK][BN + 1];
+  __shared__ __align__(8) unsigned short Asb[BF ? BM : 1][BKP];  // [m][k]
+  __shared__ __align__(8) unsigned short Bsb[BF ? BN : 1][BKP];  // [n][k]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
@@ -127,24 +146,45 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
       if (slab + 1 < se) fetch(slab + 1);
       continue;
     }
+    if constexpr (BF) {
 #pragma unroll
-    for (int i = 0; i < SA; ++i) As[ak[i]][am[i]] = ra[i];
+      for (int i = 0; i < SA; ++i) Asb[am[i]][ak[i]] = bf16_rne(float(ra[i]));
 #pragma unroll
-    for (int i = 0; i < SB; ++i) Bs[bk[i]][bn[i]] = rb[i];
+      for (int i = 0; i < SB; ++i) Bsb[bn[i]][bk[i]] = bf16_rne(float(rb[i]));
+    } else {
+#pragma unroll
+      for (int i = 0; i < SA; ++i) As[ak[i]][am[i]] = ra[i];
+#pragma unroll
+      for (int i = 0; i < SB; ++i) Bs[bk[i]][bn[i]] = rb[i];
+    }
     __syncthreads();
     if (slab + 1 < se) fetch(slab + 1);
+    if constexpr (BF) {
+      // the whole 16-deep slab in one MFMA per 16 x 16 output tile
+      const int kq = 4 * (lane >> 4);
+      s4 a[2], b[2];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      T a[2], b[2];
+      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const s4*>(&Asb[wm * 32 + i * 16 + (lane & 15)][kq]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kr][wm * 32 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn * 32 + j * 16 + (lane & 15)];
+      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const s4*>(&Bsb[wn * 32 + j * 16 + (lane & 15)][kq]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        T a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = As[kr][wm * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+      }
     }
     __syncthreads();
   }
@@ -194,14 +234,21 @@ void gemm_run(const GemmLaunch<T>& g, hipStream_t st) {
   dim3 grid(ceil_div(g.M, BM), ceil_div(g.N, BN), g.ngroups * g.splits);
   T* part = g.splits > 1 ? g.partial : nullptr;
   timer_begin(kKcGemm, st, g.flops);
-#define TK_GEMM_CASE(TA, TB)                                                                          \
-  if (g.ta == TA && g.tb == TB)                                                                       \
-    hipLaunchKernelGGL((gemm_kernel<T, TA, TB>), grid, dim3(NT), 0, st, g.M, g.N, g.K, g.lda, g.ldb, g.ldc, \
-                       g.terms, g.groups, g.beta, g.splits, part, g.max_terms);
-  TK_GEMM_CASE(false, false)
-  TK_GEMM_CASE(false, true)
-  TK_GEMM_CASE(true, false)
-  TK_GEMM_CASE(true, true)
+  TK_CHECK(!g.bf16 || sizeof(T) == 4, kErrUnsupported, "bf16 operands need FP32 storage");
+#define TK_GEMM_CASE(TA, TB, BF)                                                                          \
+  if (g.ta == TA && g.tb == TB && g.bf16 == BF)                                                            \
+    hipLaunchKernelGGL((gemm_kernel<T, TA, TB, BF && sizeof(T) == 4>), grid, dim3(NT), 0, st, g.M, g.N, g.K, \
+                       g.lda, g.ldb, g.ldc, g.terms, g.groups, g.beta, g.splits, part, g.max_terms);
+  TK_GEMM_CASE(false, false, false)
+  TK_GEMM_CASE(false, true, false)
+  TK_GEMM_CASE(true, false, false)
+  TK_GEMM_CASE(true, true, false)
+  if constexpr (sizeof(T) == 4) {
+    TK_GEMM_CASE(false, false, true)
+    TK_GEMM_CASE(false, true, true)
+    TK_GEMM_CASE(true, false, true)
+    TK_GEMM_CASE(true, true, true)
+  }
 #undef TK_GEMM_CASE
   TK_LAUNCH_CHECK();
   if (g.splits > 1) {

@@ -41,6 +41,7 @@ struct GemmLaunch {
   int splits = 1;          // split of the (term x K-slab) space (>1 uses `partial` + a reduction pass)
   T* partial = nullptr;    // ngroups * splits * M * N
   int max_terms = 1 << 30; // clamp every group to its first max_terms terms
+  bool bf16 = false;       // FP32 storage: round the operands to bfloat16, BF16 matrix cores, FP32 accumulation
   double flops = 0.0;      // algorithmic flops of this launch (for the kernel timer)
 };
 
