@@ -35,10 +35,12 @@ template <> struct Vec4<double> { using type = double __attribute__((ext_vector_
 template <typename T> struct Lim;
 template <> struct Lim<double> {
   static __device__ constexpr double eps() { return DBL_EPSILON; }
+  static __device__ constexpr double sqrt_eps() { return 1.4901161193847656e-08; }  // 2^-26
   static __device__ constexpr double tiny() { return 1e-300; }
 };
 template <> struct Lim<float> {
   static __device__ constexpr float eps() { return FLT_EPSILON; }
+  static __device__ constexpr float sqrt_eps() { return 3.4526698e-04f; }  // 2^-11.5
   static __device__ constexpr float tiny() { return 1e-37f; }
 };
 
@@ -623,6 +625,7 @@ __global__ __launch_bounds__(1024) void jacobi_blk_kernel(const EigTask<T>* __re
   __shared__ unsigned int rmask[2];      // pairs that rotate (bit k), by round parity
   __shared__ int skip_s[2];
   __shared__ int rotflag[3];
+  __shared__ int bigflag[3];             // a rotation of the sweep had a scaled off-diagonal above sqrt(eps)
   __shared__ int rank_s;
   __shared__ int posv[NPM];
   __shared__ T lam_s[NPM];
@@ -655,7 +658,10 @@ __global__ __launch_bounds__(1024) void jacobi_blk_kernel(const EigTask<T>* __re
     const int c = e / LDV, r = e % LDV;
     V[e] = (r == c) ? T(1) : T(0);
   }
-  if (tid < 3) rotflag[tid] = 0;
+  if (tid < 3) {
+    rotflag[tid] = 0;
+    bigflag[tid] = 0;
+  }
   // block task of this thread (pair I <= pair J), fixed for the whole kernel
   const int nblk = H * (H + 1) / 2;
   int bI = 0, bJ = 0;
@@ -697,13 +703,15 @@ __global__ __launch_bounds__(1024) void jacobi_blk_kernel(const EigTask<T>* __re
       // ---- phase 1
       if (wave == 0) {
         T c = T(1), sn = T(0), tt = T(0);
-        int flag = 0;
+        int flag = 0, big = 0;
         if (lane < H) {
           const unsigned pq = sch[t][lane];
           const int p = int(pq & 0xffu), q = int(pq >> 8);
           const T app = A[p * LD + p], aqq = A[q * LD + q], apq = A[q * LD + p];
           const T aa = fabs(apq);
-          flag = (q < N) && aa > Lim<T>::tiny() && aa > Lim<T>::eps() * jac_sqrt(fabs(app * aqq));
+          const T sc = jac_sqrt(fabs(app * aqq));
+          flag = (q < N) && aa > Lim<T>::tiny() && aa > Lim<T>::eps() * sc;
+          big = flag && aa > Lim<T>::sqrt_eps() * sc;
           T tr, cr;
           jac_rot(app, aqq, flag ? apq : T(1), tr, cr);
           if (flag) {
@@ -716,11 +724,16 @@ __global__ __launch_bounds__(1024) void jacobi_blk_kernel(const EigTask<T>* __re
           tnb[cur][lane] = tt;
         }
         const unsigned long long fm = __ballot(flag);
+        const unsigned long long bm = __ballot(big);
         if (lane == 0) {
           skip_s[cur] = fm == 0;
           rmask[cur] = (unsigned int)fm;
           if (fm != 0) rotflag[sweep % 3] = 1;
-          if (t == 0) rotflag[(sweep + 1) % 3] = 0;
+          if (bm != 0) bigflag[sweep % 3] = 1;
+          if (t == 0) {
+            rotflag[(sweep + 1) % 3] = 0;
+            bigflag[(sweep + 1) % 3] = 0;
+          }
         }
       } else if (prev_t >= 0) {
         if (vtask) v_rot(prev_t, prev_buf, vi, vJ);
@@ -772,7 +785,12 @@ __global__ __launch_bounds__(1024) void jacobi_blk_kernel(const EigTask<T>* __re
       prev_buf = cur;
       __syncthreads();
     }
-    if (rotflag[sweep % 3] == 0) break;  // read after the round's last barrier: same value everywhere
+    // Read after the sweep's last barrier: the same values in every thread.
+    // Stop after a sweep without rotations, or after one whose rotations all
+    // had scaled off-diagonals |a_pq| / sqrt(a_pp a_qq) <= sqrt(eps): cyclic
+    // Jacobi converges quadratically, so the off-diagonal it leaves is
+    // O(eps) relative to the diagonal, and another sweep would only confirm.
+    if (rotflag[sweep % 3] == 0 || bigflag[sweep % 3] == 0) break;
   }
   if (prev_t >= 0) {
     if (vtask) v_rot(prev_t, prev_buf, vi, vJ);
