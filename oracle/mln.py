@@ -37,11 +37,15 @@ Readings where the paper leaves a choice (both sides use them):
     sketched core and the leading r_sol columns of its factor sketches; the
     final recovery then uses the leading r~_sol columns of Psi_k.  The paper
     notes this equals sketching with those leading columns from the start.
+  * Flexible preconditioning: Z_k is the MLN truncation of M(V_k), i.e.
+    MLN_Recovery(MLN_Sketch of the 2q + 1 exponential-sum terms) with the
+    same Psi and target rank r as every other sketch; the operator acts on
+    that recovered Z_k, and its sketch (not V_k's) enters the final sum.
 """
 from __future__ import annotations
 
 import dataclasses
-from typing import List, Optional, Sequence
+from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
@@ -118,9 +122,16 @@ class MLNParams:
 
 
 def mln_sgmres(terms, B: Tucker, Psi: Sequence[np.ndarray], prm: MLNParams, transpose: bool = False,
-               log: Optional[list] = None):
+               log: Optional[list] = None, precond: Optional[Callable[[Tucker], list]] = None):
     """MLN-Tucker sGMRES on ``L(X) = B``; returns (X, info).  ``Psi`` are the
-    n_k x (r + p) sketches."""
+    n_k x (r + p) sketches.
+
+    ``precond`` (optional) maps a basis tensor V to the block list of M(V)
+    (Sec. 3.4).  The method is then flexible: the truncated preconditioned
+    tensor is Z_k = MLN_Recovery(MLN_Sketch(M(V_k))), the operator acts on
+    Z_k, only the sketches of the Z_k are kept for the solution (truncated to
+    the solution sketch size in the memory-efficient variant), and the
+    solution is recovered from sum_i y_i sketch(Z_i)."""
     r = prm.r
     beta = exact_norm([(1.0, B)])
     V = [scale(B, 1.0 / beta)]
@@ -132,11 +143,18 @@ def mln_sgmres(terms, B: Tucker, Psi: Sequence[np.ndarray], prm: MLNParams, tran
     cols: List[np.ndarray] = []
     hist: List[float] = []
     lams: List[float] = []
+    zsk: List[MLNSketch] = []
     status = NOT_CONVERGED
     y = np.zeros(0)
     i = 0
     for i in range(1, prm.maxiter + 1):
-        LV = apply_op(terms, V[-1], transpose=transpose)
+        if precond is not None:
+            skZ, _ = mln_sketch(precond(V[-1]), Psi, r)
+            Z = mln_recovery(skZ, Psi)
+            zsk.append(truncate_sketch(skZ, rt_sol, prm.r_sol) if prm.save_memory else skZ)
+            LV = apply_op(terms, Z, transpose=transpose)
+        else:
+            LV = apply_op(terms, V[-1], transpose=transpose)
         skW, sW = mln_sketch(LV, Psi, r)
         cols.append(sW)
         W = mln_recovery(skW, Psi)
@@ -169,7 +187,7 @@ def mln_sgmres(terms, B: Tucker, Psi: Sequence[np.ndarray], prm: MLNParams, tran
             status = OK
             break
     n_used = len(y)
-    final_sk = stored[:n_used]
+    final_sk = (zsk if precond is not None else stored)[:n_used]
     Psi_rec = Psi
     if prm.save_memory:
         final_sk = [s if s.core.shape[0] == rt_sol else truncate_sketch(s, rt_sol, prm.r_sol) for s in final_sk]

@@ -63,6 +63,16 @@ def expsum_blocks(X: Tucker, eig: Sequence[Tuple[np.ndarray, np.ndarray]], q: in
             for th, ch in zip(t, c)]
 
 
+def precond_blocks(X: Tucker, eig, q: int):
+    """The 2q + 1 terms of M(X) in the basis of X,
+    c_h G x_k (V_k exp(-t_h Lambda_k) V_k^T U_k), with the coefficients of
+    ``expsum_blocks``.  The flexible MLN method sketches these terms (Sec. 3.4):
+    the sketch of Z_k is stored and summed with the same Psi as every other
+    sketch, so it is taken of the tensor itself, not of its spectral-basis
+    image."""
+    return [(c, Tucker(T.core, [V @ U for (V, _), U in zip(eig, T.U)])) for c, T in expsum_blocks(X, eig, q)]
+
+
 def precond_apply(X: Tucker, eig, q: int, round_fn: Callable[[list], Tucker]) -> Tucker:
     """T(M(X)): round the spectral-basis terms with ``round_fn`` (a RoundSum of a
     block list) and map the factors back with V_k."""
