@@ -255,6 +255,17 @@ typedef struct {
                             the truncated sketches with Psi_k[:, :r_sol + p_sol] */
   int32_t r_sol, p_sol;  /* save_memory: 1 <= r_sol <= r, r_sol + p_sol <= r + p */
   int32_t tikhonov;      /* 1: projected Tikhonov with GCV, as in tk_sgmres_params */
+  /* Optional exponential-sum preconditioner M (Sec. 3.4), given as in
+   * tk_sgmres_params.  The method is then flexible: Z_i is the MLN recovery of
+   * the MLN sketch of M(V_i) (its 2q + 1 terms sketched with the same Psi_k
+   * and target rank r), L is applied to Z_i, and the solution is recovered
+   * from sum_i y_i sketch(Z_i); with save_memory the sketches of the Z_i are
+   * kept truncated to (r_sol + p_sol)^d cores and r_sol factor columns.  The
+   * pointer arrays and the device data they name are read during the call
+   * only.  precond_q = 0 (zero-initialised struct): no preconditioner. */
+  int32_t precond_q;                   /* 0: none; 1..400: 2q + 1 terms */
+  const double* const* precond_V;      /* host array of d device pointers: orthogonal V_k, n_k x n_k column-major */
+  const double* const* precond_lambda; /* host array of d device pointers: eigenvalues lambda_k, length n_k */
 } tk_mln_params;
 
 /* MLN sketch of a block sum x = sum_b coef_b X_b (the sketch of every block
@@ -348,8 +359,9 @@ const char* tk_last_error(void);
  * hist_lambda (all appended), and tsgmres_projected_tikhonov was added.
  * 2.1 (201): tucker_sketch_noalloc was added.  2.2 (202): tk_launch_count and
  * tk_launch_latency were added.  2.3 (203): tk_rank_cert_count was added.
- * 2.4 (204): TK_FORM_BF16 for the per-call entry points. */
-#define TK_ABI_VERSION 204
+ * 2.4 (204): TK_FORM_BF16 for the per-call entry points.  2.5 (205):
+ * tk_mln_params gained the preconditioner fields (appended). */
+#define TK_ABI_VERSION 205
 int tk_version(void);
 
 #ifdef __cplusplus

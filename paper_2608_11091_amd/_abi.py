@@ -18,7 +18,7 @@ ERRORS = {-1: "invalid argument", -2: "shape", -3: "capacity", -4: "workspace", 
           -6: "non-finite", -7: "unsupported"}
 
 # the structures below mirror include/tsgmres.h at this ABI version
-ABI_VERSION = 204
+ABI_VERSION = 205
 
 EXPORTS = [
     "tucker_apply_op", "tucker_apply_op_workspace", "tucker_sketch", "tucker_sketch_workspace",
@@ -65,7 +65,8 @@ class TkMlnParams(C.Structure):
     _fields_ = [("r", C.c_int32), ("p", C.c_int32), ("tol", C.c_double), ("eta", C.c_double),
                 ("maxiter", C.c_int32), ("k_trunc", C.c_int32), ("breakdown_tol", C.c_double),
                 ("save_memory", C.c_int32), ("r_sol", C.c_int32), ("p_sol", C.c_int32),
-                ("tikhonov", C.c_int32)]
+                ("tikhonov", C.c_int32), ("precond_q", C.c_int32), ("precond_V", C.POINTER(C.c_void_p)),
+                ("precond_lambda", C.POINTER(C.c_void_p))]
 
 
 class TkSgmresInfo(C.Structure):

@@ -530,14 +530,29 @@ class MlnParams:
     r_sol: int = 0
     p_sol: int = 0
     tikhonov: bool = False   # projected Tikhonov with GCV (Sec. 4.3)
+    # exponential-sum preconditioner (Sec. 3.4), as in ``SolveParams``: the
+    # method is then flexible and keeps the sketches of Z_i = recover(sketch(M(V_i)))
+    precond_q: int = 0
+    precond: Optional[Tuple[list, list]] = None
 
-    def struct(self) -> TkMlnParams:
+    def struct(self):
+        """The C struct and the objects it points into (keep them alive for the call)."""
         p = TkMlnParams()
         p.r, p.p, p.tol, p.eta, p.maxiter, p.k_trunc = self.r, self.p, self.tol, self.eta, self.maxiter, self.k_trunc
         p.breakdown_tol, p.save_memory, p.r_sol, p.p_sol = self.breakdown_tol, int(self.save_memory), self.r_sol, \
             self.p_sol
         p.tikhonov = int(self.tikhonov)
-        return p
+        keep = []
+        p.precond_q = int(self.precond_q)
+        if self.precond_q > 0:
+            if self.precond is None:
+                raise ValueError("precond_q > 0 needs the eigenpairs in `precond`")
+            Vs, lams = self.precond
+            va, la = _ptr_array(Vs), _ptr_array(lams)
+            keep += [va, la]
+            p.precond_V = va
+            p.precond_lambda = la
+        return p, keep
 
 
 def mln_sketch(blocks, Psi: Sequence[torch.Tensor], r: int):
@@ -583,7 +598,7 @@ def mln_solve_workspace_bytes(op: KronOp, b: Tucker, prm: MlnParams) -> int:
     lib = _abi.load()
     ops, k1 = op.struct(b.n)
     bst = b.struct()
-    ps = prm.struct()
+    ps, kp = prm.struct()
     nb = C.c_size_t()
     check(lib.tsgmres_mln_solve_workspace(C.byref(ops), C.byref(bst), C.byref(ps), C.byref(nb)))
     return int(nb.value)
@@ -594,7 +609,7 @@ def mln_solve(op: KronOp, b: Tucker, Psi: Sequence[torch.Tensor], prm: MlnParams
     lib = _abi.load()
     ops, k1 = op.struct(b.n)
     bst = b.struct()
-    ps = prm.struct()
+    ps, kp = prm.struct()
     nb = C.c_size_t()
     check(lib.tsgmres_mln_solve_workspace(C.byref(ops), C.byref(bst), C.byref(ps), C.byref(nb)))
     # a caller's workspace is used as given: one that is too small makes the

@@ -702,6 +702,9 @@ void check_mln_params(const tk_mln_params* prm) {
   if (prm->save_memory)
     TK_CHECK(prm->r_sol >= 1 && prm->r_sol <= prm->r && prm->p_sol >= 0 && prm->r_sol + prm->p_sol <= prm->r + prm->p,
              kErrInvalidArg, "save_memory needs 1 <= r_sol <= r and r_sol + p_sol <= r + p");
+  TK_CHECK(prm->precond_q >= 0 && prm->precond_q <= 400, kErrInvalidArg, "precond_q must be in [0, 400]");
+  TK_CHECK(prm->precond_q == 0 || (prm->precond_V != nullptr && prm->precond_lambda != nullptr), kErrInvalidArg,
+           "preconditioner eigenpairs missing");
 }
 
 int do_mln_solve(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* prm, const double* const* Psi,
@@ -730,7 +733,16 @@ int do_mln_solve(const tk_kron_op* op, const tk_tucker* b, const tk_mln_params* 
   cfg.r_sol = prm->r_sol;
   cfg.p_sol = prm->p_sol;
   cfg.tikhonov = prm->tikhonov != 0;
-  auto solver = make_mln_solver(ar, sh, op_dev(op), bi, cfg, ps, st);
+  PrecondT<double> pc;
+  pc.q = prm->precond_q;
+  if (pc.q > 0)
+    for (int k = 0; k < d; ++k) {
+      pc.V[k] = prm->precond_V[k];
+      pc.lam[k] = prm->precond_lambda[k];
+      TK_CHECK(ar.measuring() || (pc.V[k] != nullptr && pc.lam[k] != nullptr), kErrInvalidArg,
+               "preconditioner eigenpairs missing");
+    }
+  auto solver = make_mln_solver(ar, sh, op_dev(op), bi, cfg, ps, st, pc);
   if (ar.measuring()) return 0;
   TK_CHECK(x != nullptr, kErrInvalidArg, "x is NULL");
   for (int k = 0; k < d; ++k) TK_CHECK(ps[k] != nullptr, kErrInvalidArg, "Psi factor is NULL");

@@ -1443,8 +1443,7 @@ void plan_gemm_batched(Seq& q, Planner& pl, bool ta, bool tb, int M, int N, int 
 
 // ====================================================================== preconditioner
 template <typename T>
-void plan_precond(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, const TT<T>& x, const TT<T>& z,
-                  const RoundCfg& rcfg, const std::array<const T*, kMaxD>& omega) {
+Blocks<T> plan_precond_terms(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, const TT<T>& x) {
   const int d = sh.d, rc = sh.rc, qn = pc.q, nh = 2 * qn + 1;
   TK_CHECK(qn >= 1, kErrInvalidArg, "preconditioner: q must be >= 1");
   Arena& ar = pl.ar;
@@ -1494,6 +1493,15 @@ void plan_precond(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, c
   }
   Blocks<T> terms;
   for (int h = 0; h < nh; ++h) terms.add(x.core, fac[h], x.rank, coef + h, 1.0);
+  return terms;
+}
+
+template <typename T>
+void plan_precond(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, const TT<T>& x, const TT<T>& z,
+                  const RoundCfg& rcfg, const std::array<const T*, kMaxD>& omega) {
+  const int d = sh.d, rc = sh.rc;
+  Arena& ar = pl.ar;
+  Blocks<T> terms = plan_precond_terms<T>(q, pl, sh, pc, x);
   // rounding in the spectral basis at the full sketch width; the core goes
   // straight into z, the factors into temporaries that are mapped back
   RoundCfg cfg = rcfg;
@@ -1537,7 +1545,8 @@ void plan_precond(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, c
   template void plan_core_projection<T>(Seq&, Planner&, const Shape&, const Blocks<T>&, const double*,        \
                                         const std::array<const T*, kMaxD>&, int, T*, const int*);         \
   template void plan_precond<T>(Seq&, Planner&, const Shape&, const PrecondT<T>&, const TT<T>&, const TT<T>&,  \
-                                const RoundCfg&, const std::array<const T*, kMaxD>&);
+                                const RoundCfg&, const std::array<const T*, kMaxD>&);                         \
+  template Blocks<T> plan_precond_terms<T>(Seq&, Planner&, const Shape&, const PrecondT<T>&, const TT<T>&);
 TK_INST(double)
 TK_INST(float)
 #undef TK_INST

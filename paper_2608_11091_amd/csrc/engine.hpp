@@ -209,6 +209,27 @@ void plan_mln_sketch(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>&
 void plan_mln_recovery(Seq& q, Planner& pl, const Shape& sh, const MlnSk& sk,
                        const std::array<const double*, kMaxD>& Psi, int r, int rt, const TT<double>& out);
 
+// Separable spectral preconditioner (Sec. 3.4): per mode an orthogonal V_k
+// (n_k x n_k, column-major) and eigenvalues lambda_k of the 1D operator;
+// M = sum_{h=-q..q} c_h (x)_k V_k exp(-t_h Lambda_k) V_k^T with t_h = exp(h eta),
+// c_h = eta t_h, eta = pi / sqrt(q).  q = 0: no preconditioner.
+template <typename T>
+struct PrecondT {
+  int q = 0;
+  std::array<const T*, kMaxD> V{};
+  std::array<const T*, kMaxD> lam{};
+};
+// The 2q + 1 terms of M(x) in the spectral basis: core of x, factors
+// exp(-t_h (Lambda_k - lambda_min,k)) V_k^T U_k (n_k x rc, allocated from the
+// planner's arena) and device coefficients c_h exp(-t_h sum_k lambda_min,k).
+template <typename T>
+Blocks<T> plan_precond_terms(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, const TT<T>& x);
+// z = RoundSum of the 2q + 1 terms of M(x) in the spectral basis (full sketch
+// width), factors mapped back by V_k.
+template <typename T>
+void plan_precond(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, const TT<T>& x, const TT<T>& z,
+                  const RoundCfg& rcfg, const std::array<const T*, kMaxD>& omega);
+
 struct MlnCfg {
   int r = 32, p = 32;
   double tol = 1e-8, eta = 0.4;
@@ -230,26 +251,14 @@ struct MlnSolverDel {
   void operator()(MlnSolver* s) const;
 };
 using MlnSolverPtr = std::unique_ptr<MlnSolver, MlnSolverDel>;
-// MLN-Tucker sGMRES on L(X) = b, planned once (b's ranks <= cfg.r).
+// MLN-Tucker sGMRES on L(X) = b, planned once (b's ranks <= cfg.r).  With
+// precond.q > 0 the method is flexible (Sec. 3.4): Z_k = MLN recovery of the
+// MLN sketch of M(V_k), L acts on Z_k and the stored sketches of the Z_k give
+// the solution.
 MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const TT<double>& b,
-                             const MlnCfg& cfg, const std::array<const double*, kMaxD>& Psi, hipStream_t st);
+                             const MlnCfg& cfg, const std::array<const double*, kMaxD>& Psi, hipStream_t st,
+                             const PrecondT<double>& precond = PrecondT<double>{});
 void mln_solver_run(MlnSolver& s, TT<double>& x_out, MlnInfo& info, hipStream_t st);
-
-// Separable spectral preconditioner (Sec. 3.4): per mode an orthogonal V_k
-// (n_k x n_k, column-major) and eigenvalues lambda_k of the 1D operator;
-// M = sum_{h=-q..q} c_h (x)_k V_k exp(-t_h Lambda_k) V_k^T with t_h = exp(h eta),
-// c_h = eta t_h, eta = pi / sqrt(q).  q = 0: no preconditioner.
-template <typename T>
-struct PrecondT {
-  int q = 0;
-  std::array<const T*, kMaxD> V{};
-  std::array<const T*, kMaxD> lam{};
-};
-// z = RoundSum of the 2q + 1 terms of M(x) in the spectral basis (full sketch
-// width), factors mapped back by V_k.
-template <typename T>
-void plan_precond(Seq& q, Planner& pl, const Shape& sh, const PrecondT<T>& pc, const TT<T>& x, const TT<T>& z,
-                  const RoundCfg& rcfg, const std::array<const T*, kMaxD>& omega);
 
 // ------------------------------------------------------------------ solver
 struct SolveCfg {

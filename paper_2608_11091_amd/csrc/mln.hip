@@ -240,6 +240,15 @@ void plan_mln_recovery(Seq& q, Planner& pl, const Shape& sh, const MlnSk& sk,
 // solution is the recovery of sum_i y_i sketch(V_i).  Every iteration replays
 // the plan built for its index; the temporaries of one iteration are reused
 // by the next.
+//
+// Flexible preconditioning (Sec. 3.4): Z_i = recover(sketch(M(V_i))) and L
+// acts on Z_i; the sketches of the Z_i (truncated at once in the
+// memory-efficient variant) replace those of the V_i in the solution.  The
+// 2q + 1 terms of M(V_i) are built in the spectral basis (V_k^T U_k with row
+// scalings), where the sketch with Psi_k of a term with factors V_k W_k
+// equals the sketch with Psi'_k = V_k^T Psi_k of the term with factors W_k,
+// except for the factor sketches, which come out as V_k^T F_k: one GEMM with
+// V_k maps them back.  Psi'_k is formed once per solve.
 class MlnSolver {
  public:
   Shape sh;
@@ -252,6 +261,11 @@ class MlnSolver {
   std::vector<MlnSk> Sfull;  // full sketches (a ring of kt + 2 with save_memory)
   std::vector<MlnSk> Strunc; // truncated copies of every stored sketch (save_memory)
   MlnSk Wsk, Fsk;
+  PrecondT<double> pc;
+  std::vector<MlnSk> Zsk;    // sketches of Z_i (truncated with save_memory)
+  MlnSk Zfull;               // save_memory: the full sketch of the current Z_i
+  TT<double> Z;              // recovered Z_i
+  std::array<double*, kMaxD> Psip{};  // V_k^T Psi_k
   double *bnorm2, *beta, *d0, *bs, *bsn2, *bsn, *Mcols, *h, *s2, *omega, *rnorm2;
   double *Hv, *tau, *R, *qtb, *y, *res, *nrmM2, *lam;
   int* flags;
@@ -276,7 +290,8 @@ class MlnSolver {
 void MlnSolverDel::operator()(MlnSolver* s) const { delete s; }
 
 MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op, const TT<double>& b,
-                             const MlnCfg& cfg, const std::array<const double*, kMaxD>& Psi, hipStream_t st) {
+                             const MlnCfg& cfg, const std::array<const double*, kMaxD>& Psi, hipStream_t st,
+                             const PrecondT<double>& precond) {
   MlnSolverPtr sp(new MlnSolver());
   MlnSolver& s = *sp;
   s.sh = sh;
@@ -298,6 +313,8 @@ MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op
     TK_CHECK(s.rs >= 1 && s.rs <= r && s.rts >= s.rs && s.rts <= rt, kErrInvalidArg,
              "save_memory needs 1 <= r_sol <= r and r_sol <= r_sol + p_sol <= r + p");
   }
+  s.pc = precond;
+  const bool flex = precond.q > 0;
   Planner pl(ar, s.blob);
   Blob* bl = &s.blob;
 
@@ -306,8 +323,15 @@ MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op
   s.X = alloc_tt<double>(ar, sh);
   const int nfull = cfg.save_memory ? std::min(kt + 2, mx + 1) : mx + 1;
   for (int i = 0; i < nfull; ++i) s.Sfull.push_back(alloc_mln(ar, sh, r, rt));
-  if (cfg.save_memory)
+  if (cfg.save_memory && !flex)
     for (int i = 0; i <= mx; ++i) s.Strunc.push_back(alloc_mln(ar, sh, s.rs, s.rts));
+  if (flex) {
+    for (int i = 0; i < mx; ++i)
+      s.Zsk.push_back(cfg.save_memory ? alloc_mln(ar, sh, s.rs, s.rts) : alloc_mln(ar, sh, r, rt));
+    if (cfg.save_memory) s.Zfull = alloc_mln(ar, sh, r, rt);
+    s.Z = alloc_tt<double>(ar, sh);
+    for (int k = 0; k < d; ++k) s.Psip[k] = ar.alloc<double>(size_t(sh.n[k]) * rt);
+  }
   s.Wsk = alloc_mln(ar, sh, r, rt);
   s.Fsk = cfg.save_memory ? alloc_mln(ar, sh, s.rs, s.rts) : alloc_mln(ar, sh, r, rt);
   s.bnorm2 = ar.alloc<double>(1);
@@ -343,8 +367,23 @@ MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op
     Blocks<double> vb;
     vb.add(s.V[i], nullptr, 1.0);
     plan_mln_sketch(q, pl, sh, vb, Psi, r, rt, s.full(i), i == 0 ? s.d0 : nullptr);
-    if (cfg.save_memory) emit_mln_truncate(q, sh, rt, r, s.full(i), s.rts, s.rs, s.Strunc[i]);
+    if (cfg.save_memory && !flex) emit_mln_truncate(q, sh, rt, r, s.full(i), s.rts, s.rs, s.Strunc[i]);
   };
+  // Psi'_k = V_k^T Psi_k, one GEMM launch per group of equal mode size
+  std::array<const double*, kMaxD> Psip{};
+  for (int k = 0; k < d; ++k) Psip[k] = s.Psip[k];
+  if (flex)
+    for (auto& modes : group_modes(sh)) {
+      const int n = sh.n[modes[0]];
+      std::vector<const double*> a, bb;
+      std::vector<double*> c;
+      for (int k : modes) {
+        a.push_back(precond.V[k]);
+        bb.push_back(Psi[k]);
+        c.push_back(s.Psip[k]);
+      }
+      plan_gemm_batched<double>(s.setup, pl, true, false, n, rt, n, a, n, bb, n, c, n, 1.0);
+    }
 
   // ---- setup: beta = ||b|| (exact), V_1 = b / beta, stored sketch of V_1,
   //      b_s = beta diag(G_Psi(V_1))
@@ -387,7 +426,32 @@ MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op
     const size_t mk = ar.mark();
     Seq q;
     const TT<double> vn = s.V[k + 1];
-    Blocks<double> LV = plan_apply<double>(q, pl, sh, op, s.V[k], false);
+    const TT<double>* opnd = &s.V[k];
+    if (flex) {
+      // sketch of M(V_k): core straight into its slot, factor sketches V_k^T F_k
+      // into temporaries mapped back by V_k; then Z_k = recover(sketch)
+      const MlnSk zf = cfg.save_memory ? s.Zfull : s.Zsk[k];
+      MlnSk zt;
+      zt.core = zf.core;
+      for (int j = 0; j < d; ++j) zt.F[j] = ar.alloc<double>(size_t(sh.n[j]) * r);
+      Blocks<double> mt = plan_precond_terms<double>(q, pl, sh, precond, s.V[k]);
+      plan_mln_sketch(q, pl, sh, mt, Psip, r, rt, zt, nullptr);
+      for (auto& modes : group_modes(sh)) {
+        const int n = sh.n[modes[0]];
+        std::vector<const double*> a, bb;
+        std::vector<double*> c;
+        for (int j : modes) {
+          a.push_back(precond.V[j]);
+          bb.push_back(zt.F[j]);
+          c.push_back(zf.F[j]);
+        }
+        plan_gemm_batched<double>(q, pl, false, false, n, r, n, a, n, bb, n, c, n, 1.0);
+      }
+      plan_mln_recovery(q, pl, sh, zf, Psi, r, rt, s.Z);
+      if (cfg.save_memory) emit_mln_truncate(q, sh, rt, r, zf, s.rts, s.rs, s.Zsk[k]);
+      opnd = &s.Z;
+    }
+    Blocks<double> LV = plan_apply<double>(q, pl, sh, op, *opnd, false);
     plan_mln_sketch(q, pl, sh, LV, Psi, r, rt, s.Wsk, s.Mcols + size_t(k) * rt);
     plan_mln_recovery(q, pl, sh, s.Wsk, Psi, r, rt, vn);
     Blocks<double> wb;
@@ -441,7 +505,7 @@ MlnSolverPtr make_mln_solver(Arena& ar, const Shape& sh, const OpDev<double>& op
     std::vector<const double*> cs;
     std::vector<double> ss;
     for (int i = 0; i < mx; ++i) {
-      xs.push_back(cfg.save_memory ? s.Strunc[i] : s.Sfull[i]);
+      xs.push_back(flex ? s.Zsk[i] : cfg.save_memory ? s.Strunc[i] : s.Sfull[i]);
       cs.push_back(s.y + i);
       ss.push_back(1.0);
     }

@@ -99,3 +99,34 @@ def test_mln_sketch_and_recover_workspace_queries():
     # at least the (r + p)^(d-1) r ping-pong buffers of the core contraction
     assert nb.value >= 2 * 8 * 32 * 32 * 20
     assert lib.tucker_mln_recover_workspace(3, nn, 65, 0, C.byref(nb)) == -7
+
+
+def test_flexible_mln_workspace_and_checks():
+    # The flexible method (Sec. 3.4) keeps one sketch of every Z_i besides the
+    # basis sketches: maxiter more full sketches, or maxiter truncated ones
+    # plus one full sketch with save_memory.  q outside [0, 400] and a
+    # missing eigenpair list are rejected before anything is planned.
+    tk, op, b = _problem()
+    from paper_2608_11091_amd._abi import TkError
+    from workloads import laplacian_eigenpairs
+    n, d, r, p, mx, kt, rs, ps = 64, 3, 16, 16, 30, 2, 4, 4
+    pc = tk.precond_tensors(*laplacian_eigenpairs((n,) * d), device="cpu")
+    big, small = _sketch_bytes(n, d, r, r + p), _sketch_bytes(n, d, rs, rs + ps)
+    plain = tk.mln_solve_workspace_bytes(op, b, tk.MlnParams(r=r, p=p, maxiter=mx, k_trunc=kt))
+    flex = tk.mln_solve_workspace_bytes(op, b, tk.MlnParams(r=r, p=p, maxiter=mx, k_trunc=kt, precond_q=16,
+                                                            precond=pc))
+    assert flex - plain >= mx * big
+    kw = dict(r=r, p=p, maxiter=mx, k_trunc=kt, save_memory=True, r_sol=rs, p_sol=ps)
+    plain_s = tk.mln_solve_workspace_bytes(op, b, tk.MlnParams(**kw))
+    flex_s = tk.mln_solve_workspace_bytes(op, b, tk.MlnParams(**kw, precond_q=16, precond=pc))
+    # save_memory stores maxiter truncated Z sketches and one full one (and
+    # drops the truncated copies of the basis sketches, which the flexible
+    # solution does not use): about maxiter - 1 full sketches fewer, less a
+    # difference in the arena's peak of temporaries below one full sketch
+    assert (flex - plain) - (flex_s - plain_s) >= (mx - 3) * big
+    with pytest.raises(ValueError):
+        tk.MlnParams(r=4, p=4, precond_q=8).struct()
+    for q in (-1, 401):
+        with pytest.raises(TkError) as e:
+            tk.mln_solve_workspace_bytes(op, b, tk.MlnParams(r=4, p=4, precond_q=q, precond=pc))
+        assert e.value.code == -1
