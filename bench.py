@@ -242,7 +242,8 @@ def precond_bench(tk, torch, args):
     """Preconditioned flexible RHOSVD-Tucker sGMRES (Sec. 3.4) on the Laplacian
     experiment's problem at n = 512: 3D Poisson, right-hand side
     ones/||ones|| x e_1 x e_1, k_trunc = 1, p = 5, exponential sum with 2q + 1
-    terms; both forms, time to 1e-8 and iterations/s."""
+    terms; both forms, time to 1e-8 and iterations/s.  Then the flexible
+    MLN-Tucker sGMRES on the same problem (r = p = 32, q = 36, k_trunc = 3)."""
     import numpy as np
 
     from workloads import draw_sketches, laplacian_1d, laplacian_eigenpairs
@@ -274,6 +275,40 @@ def precond_bench(tk, torch, args):
                          true_relres=inf["true_relres"], true_hist=inf["true_hist"],
                          seconds_per_solve=dt / args.steps,
                          iters_per_s=sum(i["iters"] for i in infos) / dt, workspace_bytes=ws.numel())
+    # flexible MLN-Tucker sGMRES on the same problem: the stored sketches are
+    # those of Z_i = recover(sketch(M(V_i))) (Sec. 3.4)
+    from workloads import draw_mln_sketches
+    mr, mp, mq = 32, 32, 36
+    Psi_h = draw_mln_sketches((n,) * 3, mr, mp)
+    Psi = [_cm(torch, a) for a in Psi_h]
+    bm = tk.Tucker.from_numpy(np.ones((1, 1, 1)), [np.ones((n, 1)) / np.sqrt(n), e1, e1], rcap=(mr,) * 3)
+    mprm = tk.MlnParams(r=mr, p=mp, tol=args.tol, eta=0.4, maxiter=30, k_trunc=3, precond_q=mq, precond=pre)
+    mws = torch.empty(tk.mln_solve_workspace_bytes(op, bm, mprm), dtype=torch.uint8, device="cuda")
+    tk.mln_solve(op, bm, Psi, mprm, workspace=mws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    minfos = [tk.mln_solve(op, bm, Psi, mprm, workspace=mws)[1] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mi = minfos[-1]
+    out["mln_flexible"] = dict(method="flexible MLN-Tucker sGMRES (Sec. 3.4)", r=mr, p=mp, q=mq, k_trunc=3,
+                               iters=mi["iters"], status=mi["status_name"], true_relres=mi["true_relres"],
+                               seconds_per_solve=dt / args.steps, iters_per_s=sum(i["iters"] for i in minfos) / dt,
+                               workspace_bytes=mws.numel())
+    if not args.no_cpu_baseline:
+        import oracle as O
+        from oracle import mln as OM
+        from oracle import precond as P
+        eig = [P.laplacian_eig(n)] * 3
+        t2 = time.perf_counter()
+        _, moi = OM.mln_sgmres(terms, O.Tucker(np.ones((1, 1, 1)), [np.ones((n, 1)) / np.sqrt(n), e1, e1]), Psi_h,
+                               OM.MLNParams(r=mr, p=mp, tol=args.tol, eta=0.4, maxiter=30, k_trunc=3),
+                               precond=lambda V: P.precond_blocks(V, eig, mq))
+        dto = time.perf_counter() - t2
+        out["mln_flexible"]["cpu_baseline"] = dict(
+            value=moi["iters"] / dto, unit="MLN iterations/s", kind="oracle", seconds_per_solve=dto,
+            true_relres=moi["true_relres"],
+            sample=f"the whole flexible MLN solve ({moi['iters']} iterations), {dto:.1f} s")
     if not args.no_cpu_baseline:
         # the oracle's whole FP64 solve to the same tolerance (a few iterations)
         import oracle as O
