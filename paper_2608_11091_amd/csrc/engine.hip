@@ -1298,13 +1298,29 @@ void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>
       // and are cut; what is cut is below the rounding of the core sum itself
       // the basis of a mode's last block is needed only when it is re-orthogonalised
       // (blocks after the first) or projected out of later blocks
+      // A mode with a single distinct factor needs only R, and with no earlier
+      // block there is nothing to cut against: the R of a plain Householder
+      // QR gives the same core norm (a column the cut would drop contributes
+      // at the 64 u level), at a fraction of the pivoted kernel's cost.
       std::vector<QrPivTask> qt;
+      std::vector<QrTask> qs;
       for (int k : act) {
         const bool need_q = i > 0 || int(fac[k].size()) > 1;
-        qt.push_back(QrPivTask{Xt[k], fac[k][i], need_q ? Qi(k) : nullptr, Rt[k], facr[k][i]});
+        if (need_q)
+          qt.push_back(QrPivTask{Xt[k], fac[k][i], Qi(k), Rt[k], facr[k][i]});
+        else
+          qs.push_back(QrTask{Xt[k], nullptr, Rt[k], facr[k][i]});
       }
-      const size_t off = pl.blob.add(qt);
-      q.steps.push_back([=](hipStream_t st) { qr_piv_batched(bl->at<QrPivTask>(off), na, n, rc, kCutTol, st); });
+      if (!qs.empty()) {
+        const size_t off = pl.blob.add(qs);
+        const int ns = int(qs.size());
+        q.steps.push_back([=](hipStream_t st) { qr_batched(bl->at<QrTask>(off), ns, n, rc, nullptr, st); });
+      }
+      if (!qt.empty()) {
+        const size_t off = pl.blob.add(qt);
+        const int np = int(qt.size());
+        q.steps.push_back([=](hipStream_t st) { qr_piv_batched(bl->at<QrPivTask>(off), np, n, rc, kCutTol, st); });
+      }
       if (i == 0) {
         std::vector<const double*> rts;
         std::vector<double*> rds;

@@ -13,17 +13,20 @@ namespace {
 
 // ---------------------------------------------------------------- Householder QR
 // Column-distributed layout: lane c of every wave owns column c (c < 64) and
-// wave w holds rows [32w, 32w + 32) of it in registers, so a block of
-// ceil(n / 32) waves covers n <= 512 rows.  Sums over rows are in-thread
+// wave w holds rows [RS w, RS w + RS) of it in registers (RS = 32 up to 256
+// rows, 64 above), so a block of at most 8 waves covers n <= 512 rows.  Sums over rows are in-thread
 // over the 32 rows plus one pass over the waves' partials in LDS (fixed
 // order).  Every wave derives the pivot of a step from the same LDS partials,
 // and the pivot column's lane of each wave hands the reflector of that
 // wave's rows to the other lanes through a per-wave LDS slot (in-order LDS
 // within a wave, no block barrier), so a factorisation step needs two
 // barriers and a Q step one.
-constexpr int QC_RS = 32;
+constexpr int QC_RS = 32;              // rows per wave up to 256 rows
 constexpr int QC_MAXW = 16;
-constexpr int QC_NT = QC_MAXW * kWave;
+constexpr int QC_MAXROWS = 512;
+constexpr int QC_NT_SMALL = 4 * kWave;
+constexpr int QC_NT = 8 * kWave;
+constexpr int QC_NT_BIG = 16 * kWave;
 
 struct QrJob {
   const double* Y;
@@ -65,9 +68,17 @@ __device__ __forceinline__ double tree8(const double* s) {
 // column when the task has no reference) and a stop once that ratio is at or
 // below drop_tol; R[j][c] is then the coefficient of input column c on basis
 // column j.
-template <bool PIV, typename Task>
-__global__ __launch_bounds__(QC_NT) void qr_cols_kernel(const Task* __restrict__ tasks, int n, int cap,
-                                                        double drop_tol, const int* __restrict__ m_dev) {
+//
+// NTB is the largest block the instantiation is launched with and RS the
+// rows each wave holds: at most 8 waves leave each thread at least 256
+// registers (16 waves cap it at 128), so n <= 128 runs on up to 4 waves of
+// 32 rows, n <= 256 on up to 8, and n <= 512 on 8 waves of 64 rows, except
+// the pivoted form, whose extra state spills there: it takes 16 waves of 32
+// rows with one select per row (the form with the smallest register need).
+template <bool PIV, typename Task, int NTB, int RS>
+__global__ __launch_bounds__(NTB) void qr_cols_kernel(const Task* __restrict__ tasks, int n, int cap,
+                                                      double drop_tol, const int* __restrict__ m_dev) {
+  static_assert(NTB / kWave * RS <= QC_MAXROWS && NTB / kWave <= QC_MAXW, "row blocks within the LDS arrays");
   __shared__ double pn1[QC_MAXW][kWave];  // per-wave sums of squares over rows >= j
   __shared__ double rowj[kWave];          // row j of every column
   __shared__ double pw[2][QC_MAXW][kWave];  // per-wave partials of v^T A
@@ -75,13 +86,18 @@ __global__ __launch_bounds__(QC_NT) void qr_cols_kernel(const Task* __restrict__
   __shared__ double tau_s[kWave];
   __shared__ int piv_s[kWave];
   __shared__ int step_of[kWave];
-  __shared__ double vsh[QC_MAXW][QC_RS];  // reflector on each wave's rows
+  __shared__ double vsh_all[QC_MAXROWS];  // reflector on each wave's rows
+  // rows per chunk; a 16-wave block (n > 256 in the pivoted form) keeps one
+  // select per row, the form whose register need is the smallest
+  constexpr bool CHUNKED = NTB <= QC_NT;
+  constexpr int QC_CH = 8;
   const QrJob jb = job_of(tasks[blockIdx.x], cap, m_dev);
   const int tid = threadIdx.x;
   const int c = tid & (kWave - 1);
   const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform: row tests stay scalar
   const int nw = blockDim.x / kWave;
-  const int r0 = w * QC_RS;
+  const int r0 = w * RS;
+  double* const vsh = vsh_all + w * RS;  // this wave's rows
   const int m = max(0, min(jb.m, cap));
   const int kmax = min(m, n);
 
@@ -89,27 +105,63 @@ __global__ __launch_bounds__(QC_NT) void qr_cols_kernel(const Task* __restrict__
   // masked afterwards: no per-row branches whose conditions stay live
   const int cl = min(c, cap - 1);
   const bool colin = c < m;
-  const double* refp = jb.ref ? jb.ref : jb.Y;  // reference columns (the input itself for the global cut)
-  double a[QC_RS];
+  double a[RS];
   double sref = 0.0;  // this thread's share of the squared reference norm
 #pragma unroll
-  for (int i = 0; i < QC_RS; ++i) {
+  for (int i = 0; i < RS; ++i) {
     const int r = r0 + i;
     const size_t at = (size_t)min(r, n - 1) + (size_t)cl * n;
     const bool in = colin && r < n;
     const double y = jb.Y[at];
     a[i] = in ? y : 0.0;
-    if (PIV) {
-      const double v = in ? refp[at] : 0.0;
-      sref += v * v;
+  }
+  if (PIV) {
+    if (jb.ref == nullptr) {
+      // global cut: the reference columns are the input itself
+#pragma unroll
+      for (int i = 0; i < RS; ++i) sref += a[i] * a[i];
+    } else {
+      // reference columns read a chunk at a time, so that their loads do not
+      // all hold registers beside the input's
+#pragma unroll
+      for (int q = 0; q < RS; q += QC_CH) {
+#pragma unroll
+        for (int i = q; i < q + QC_CH; ++i) {
+          const int r = r0 + i;
+          const size_t at = (size_t)min(r, n - 1) + (size_t)cl * n;
+          const double v = (colin && r < n) ? jb.ref[at] : 0.0;
+          sref += v * v;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
   // the pivot column's lane stores v on this wave's rows; the other lanes of
   // the wave read it back after a wave-scope fence
+  // Rows are handled in chunks of QC_CH: the step's diagonal row t0 (relative
+  // to the wave) is uniform, so a chunk lies wholly below it, wholly above
+  // it, or holds it, and only that one chunk of the wave takes per-row
+  // selects (uniform branches choose the case).
   auto publish = [&](bool own, int t0, double scale, double diag) {
-    if (own) {
+    if constexpr (!CHUNKED) {
+      if (own) {
 #pragma unroll
-      for (int i = 0; i < QC_RS; ++i) vsh[w][i] = (i < t0) ? 0.0 : (i == t0 ? diag : a[i] * scale);
+        for (int i = 0; i < RS; ++i) vsh[i] = (i < t0) ? 0.0 : (i == t0 ? diag : a[i] * scale);
+      }
+    } else if (own) {
+#pragma unroll
+      for (int q = 0; q < RS; q += QC_CH) {
+        if (t0 < q) {
+#pragma unroll
+          for (int i = q; i < q + QC_CH; ++i) vsh[i] = a[i] * scale;
+        } else if (t0 >= q + QC_CH) {
+#pragma unroll
+          for (int i = q; i < q + QC_CH; ++i) vsh[i] = 0.0;
+        } else {
+#pragma unroll
+          for (int i = q; i < q + QC_CH; ++i) vsh[i] = (i < t0) ? 0.0 : (i == t0 ? diag : a[i] * scale);
+        }
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -120,15 +172,34 @@ __global__ __launch_bounds__(QC_NT) void qr_cols_kernel(const Task* __restrict__
   auto norm_partials = [&](int j) {
     const int t0 = j - r0;
     double s1[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (!CHUNKED) {
 #pragma unroll
-    for (int i = 0; i < QC_RS; ++i) s1[i & 7] += (i >= t0) ? a[i] * a[i] : 0.0;
-    pn1[w][c] = tree8(s1);
-    if (t0 >= 0 && t0 < QC_RS) {
-      double x = 0.0;
+      for (int i = 0; i < RS; ++i) s1[i & 7] += (i >= t0) ? a[i] * a[i] : 0.0;
+      pn1[w][c] = tree8(s1);
+      if (t0 >= 0 && t0 < RS) {
+        double x = 0.0;
 #pragma unroll
-      for (int i = 0; i < QC_RS; ++i) x = (i == t0) ? a[i] : x;
-      rowj[c] = x;
+        for (int i = 0; i < RS; ++i) x = (i == t0) ? a[i] : x;
+        rowj[c] = x;
+      }
+      return;
     }
+#pragma unroll
+    for (int q = 0; q < RS; q += QC_CH) {
+      if (t0 < q) {
+#pragma unroll
+        for (int i = q; i < q + QC_CH; ++i) s1[i & 7] += a[i] * a[i];
+      } else if (t0 < q + QC_CH) {  // the chunk holding row j
+        double x = 0.0;
+#pragma unroll
+        for (int i = q; i < q + QC_CH; ++i) {
+          s1[i & 7] += (i >= t0) ? a[i] * a[i] : 0.0;
+          x = (i == t0) ? a[i] : x;
+        }
+        rowj[c] = x;
+      }
+    }
+    pn1[w][c] = tree8(s1);
   };
   if (PIV) pw[0][w][c] = sref;
   if (tid < kWave) step_of[tid] = -1;
@@ -185,17 +256,45 @@ __global__ __launch_bounds__(QC_NT) void qr_cols_kernel(const Task* __restrict__
     const bool upd = tau != 0.0 && alive;
     publish(c == p, t0, scal, 1.0);
     double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (!CHUNKED) {
 #pragma unroll
-    for (int i = 0; i < QC_RS; ++i) s[i & 7] += vsh[w][i] * a[i];
+      for (int i = 0; i < RS; ++i) s[i & 7] += vsh[i] * a[i];
+    } else
+#pragma unroll
+    for (int q = 0; q < RS; q += QC_CH)
+      if (t0 < q + QC_CH) {  // rows above the diagonal row carry v = 0
+#pragma unroll
+        for (int i = q; i < q + QC_CH; ++i) s[i & 7] += vsh[i] * a[i];
+      }
     pw[0][w][c] = upd ? tree8(s) : 0.0;
     __syncthreads();
     const double wc = wave_partials_sum(pw[0], nw, c);
     const double tw = upd ? tau * wc : 0.0;
+    // column p keeps its rows above j, takes beta at row j and the reflector
+    // below; the other columns take a - tw v (a no-op above row j)
+    const double keep = (c == p) ? 0.0 : 1.0;
+    const double twp = (c == p) ? -1.0 : tw;
+    if constexpr (!CHUNKED) {
 #pragma unroll
-    for (int i = 0; i < QC_RS; ++i) {
-      const double v = vsh[w][i];
-      const double own = (i < t0) ? a[i] : (i == t0 ? beta : v);  // column p: beta, then the reflector
-      a[i] = (c == p) ? own : a[i] - tw * v;
+      for (int i = 0; i < RS; ++i) {
+        const double v = vsh[i];
+        const double own = (i < t0) ? a[i] : (i == t0 ? beta : v);
+        a[i] = (c == p) ? own : a[i] - tw * v;
+      }
+    } else
+#pragma unroll
+    for (int q = 0; q < RS; q += QC_CH) {
+      if (t0 < q) {
+#pragma unroll
+        for (int i = q; i < q + QC_CH; ++i) a[i] = fma(-twp, vsh[i], keep * a[i]);
+      } else if (t0 < q + QC_CH) {
+#pragma unroll
+        for (int i = q; i < q + QC_CH; ++i) {
+          const double v = vsh[i];
+          const double own = (i < t0) ? a[i] : (i == t0 ? beta : v);
+          a[i] = (c == p) ? own : a[i] - tw * v;
+        }
+      }
     }
     nlive = j + 1;
     norm_partials(j + 1);
@@ -207,7 +306,7 @@ __global__ __launch_bounds__(QC_NT) void qr_cols_kernel(const Task* __restrict__
   // ---------------- R (and its transpose): row jj of every column
   if (jb.R != nullptr || jb.Rt != nullptr) {
 #pragma unroll
-    for (int i = 0; i < QC_RS; ++i) {
+    for (int i = 0; i < RS; ++i) {
       const int row = r0 + i;
       if (row < cap && c < cap) {
         const int sc = step_of[c];
@@ -231,23 +330,54 @@ __global__ __launch_bounds__(QC_NT) void qr_cols_kernel(const Task* __restrict__
     const bool upd = later && tau != 0.0;
     publish(c == p, t0, 1.0, 1.0);
     double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if constexpr (!CHUNKED) {
 #pragma unroll
-    for (int i = 0; i < QC_RS; ++i) s[i & 7] += vsh[w][i] * a[i];
+      for (int i = 0; i < RS; ++i) s[i & 7] += vsh[i] * a[i];
+    } else
+#pragma unroll
+    for (int q = 0; q < RS; q += QC_CH)
+      if (t0 < q + QC_CH) {
+#pragma unroll
+        for (int i = q; i < q + QC_CH; ++i) s[i & 7] += vsh[i] * a[i];
+      }
     pw[b][w][c] = upd ? tree8(s) : 0.0;
     __syncthreads();
     const double wc = wave_partials_sum(pw[b], nw, c);
     const double tw = upd ? tau * wc : 0.0;
+    // column p becomes basis column j: 0 above row j, 1 - tau at row j,
+    // -tau v below; the other columns take a - tw v
+    const double keep = (c == p) ? 0.0 : 1.0;
+    const double twp = (c == p) ? tau : tw;
+    if constexpr (!CHUNKED) {
 #pragma unroll
-    for (int i = 0; i < QC_RS; ++i) {
-      const double v = vsh[w][i];
-      const double own = (i < t0) ? 0.0 : (i == t0 ? 1.0 - tau : -tau * v);
-      a[i] = (c == p) ? own : a[i] - tw * v;
+      for (int i = 0; i < RS; ++i) {
+        const double v = vsh[i];
+        const double own = (i < t0) ? 0.0 : (i == t0 ? 1.0 - tau : -tau * v);
+        a[i] = (c == p) ? own : a[i] - tw * v;
+      }
+    } else
+#pragma unroll
+    for (int q = 0; q < RS; q += QC_CH) {
+      if (t0 < q) {
+#pragma unroll
+        for (int i = q; i < q + QC_CH; ++i) a[i] = fma(-twp, vsh[i], keep * a[i]);
+      } else if (t0 >= q + QC_CH) {
+#pragma unroll
+        for (int i = q; i < q + QC_CH; ++i) a[i] = keep * a[i];
+      } else {
+#pragma unroll
+        for (int i = q; i < q + QC_CH; ++i) {
+          const double v = vsh[i];
+          const double own = (i < t0) ? 0.0 : (i == t0 ? 1.0 - tau : -tau * v);
+          a[i] = (c == p) ? own : a[i] - tw * v;
+        }
+      }
     }
     later = later || c == p;
   }
   const int jj = step_of[c];
 #pragma unroll
-  for (int i = 0; i < QC_RS; ++i) {
+  for (int i = 0; i < RS; ++i) {
     const int row = r0 + i;
     if (row < n) {
       if (jj >= 0) jb.Q[row + (size_t)jj * n] = a[i];
@@ -380,22 +510,36 @@ static double qr_flops(int ntasks, int n, int cap, bool with_q) {
 
 void qr_batched(const QrTask* tasks_d, int ntasks, int n, int cap, const int* m_dev, hipStream_t st) {
   if (ntasks <= 0) return;
-  TK_CHECK(n >= 1 && n <= QC_MAXW * QC_RS, kErrUnsupported, "Householder QR: more than 512 rows");
+  TK_CHECK(n >= 1 && n <= QC_MAXROWS, kErrUnsupported, "Householder QR: more than 512 rows");
   TK_CHECK(cap <= kWave, kErrUnsupported, "Householder QR: more than 64 columns");
   timer_begin(kKcQr, st, qr_flops(ntasks, n, cap, true));
-  hipLaunchKernelGGL((qr_cols_kernel<false, QrTask>), dim3(ntasks), dim3(kWave * ceil_div(n, QC_RS)), 0, st,
-                     tasks_d, n, cap, 0.0, m_dev);
+  if (n <= 4 * QC_RS)
+    hipLaunchKernelGGL((qr_cols_kernel<false, QrTask, QC_NT_SMALL, QC_RS>), dim3(ntasks),
+                       dim3(kWave * ceil_div(n, QC_RS)), 0, st, tasks_d, n, cap, 0.0, m_dev);
+  else if (n <= 8 * QC_RS)
+    hipLaunchKernelGGL((qr_cols_kernel<false, QrTask, QC_NT, QC_RS>), dim3(ntasks), dim3(kWave * ceil_div(n, QC_RS)),
+                       0, st, tasks_d, n, cap, 0.0, m_dev);
+  else
+    hipLaunchKernelGGL((qr_cols_kernel<false, QrTask, QC_NT, 2 * QC_RS>), dim3(ntasks),
+                       dim3(kWave * ceil_div(n, 2 * QC_RS)), 0, st, tasks_d, n, cap, 0.0, m_dev);
   TK_LAUNCH_CHECK();
   timer_end(kKcQr, st);
 }
 
 void qr_piv_batched(const QrPivTask* tasks_d, int ntasks, int n, int cap, double drop_tol, hipStream_t st) {
   if (ntasks <= 0) return;
-  TK_CHECK(n >= 1 && n <= QC_MAXW * QC_RS && cap <= kWave, kErrUnsupported,
+  TK_CHECK(n >= 1 && n <= QC_MAXROWS && cap <= kWave, kErrUnsupported,
            "pivoted QR: more than 512 rows or 64 columns");
   timer_begin(kKcQr, st, qr_flops(ntasks, n, cap, true));
-  hipLaunchKernelGGL((qr_cols_kernel<true, QrPivTask>), dim3(ntasks), dim3(kWave * ceil_div(n, QC_RS)), 0, st,
-                     tasks_d, n, cap, drop_tol, nullptr);
+  if (n <= 4 * QC_RS)
+    hipLaunchKernelGGL((qr_cols_kernel<true, QrPivTask, QC_NT_SMALL, QC_RS>), dim3(ntasks),
+                       dim3(kWave * ceil_div(n, QC_RS)), 0, st, tasks_d, n, cap, drop_tol, nullptr);
+  else if (n <= 8 * QC_RS)
+    hipLaunchKernelGGL((qr_cols_kernel<true, QrPivTask, QC_NT, QC_RS>), dim3(ntasks), dim3(kWave * ceil_div(n, QC_RS)),
+                       0, st, tasks_d, n, cap, drop_tol, nullptr);
+  else  // the pivoted form would spill with 64 rows per wave: 16 waves of 32
+    hipLaunchKernelGGL((qr_cols_kernel<true, QrPivTask, QC_NT_BIG, QC_RS>), dim3(ntasks),
+                       dim3(kWave * ceil_div(n, QC_RS)), 0, st, tasks_d, n, cap, drop_tol, nullptr);
   TK_LAUNCH_CHECK();
   timer_end(kKcQr, st);
 }
