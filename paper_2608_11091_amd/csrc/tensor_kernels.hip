@@ -24,8 +24,9 @@ __global__ __launch_bounds__(KRP_NT) void krp_kernel(const KrpTask<T>* __restric
   const KrpTask<T> tk_ = tasks[blockIdx.y];
   const int f = tk_.f, ldo = tk_.ldo;
   const int tid = threadIdx.x;
-  for (int j = 0; j < m; ++j) {
-    if (j == f) continue;
+#pragma unroll
+  for (int j = 0; j < kMaxD; ++j) {
+    if (j >= m || j == f) continue;
     for (int i = tid; i < z.v[j]; i += KRP_NT) mv[j][i] = tk_.Mj[j][i + (size_t)l * tk_.ldm[j]];
   }
   __syncthreads();
@@ -38,15 +39,21 @@ __global__ __launch_bounds__(KRP_NT) void krp_kernel(const KrpTask<T>* __restric
     const int O = P / zf;
     T acc = T(0);
     if (pp < nparts) {
-      // strides of the row-major multi-index
+      // strides of the row-major multi-index (loops over the fixed kMaxD
+      // modes, unrolled, so that the index arrays stay in registers)
       int stride[kMaxD];
-      stride[m - 1] = 1;
-      for (int j = m - 2; j >= 0; --j) stride[j] = stride[j + 1] * z.v[j + 1];
+#pragma unroll
+      for (int j = kMaxD - 1; j >= 0; --j) stride[j] = (j >= m - 1) ? 1 : stride[j + 1 < kMaxD ? j + 1 : j] * z.v[j + 1 < kMaxD ? j + 1 : j];
+      int sf = 1;
+#pragma unroll
+      for (int j = 0; j < kMaxD; ++j)
+        if (j == f) sf = stride[j];
       for (int o = pp; o < O; o += nparts) {
-        int rem = o, row = a * stride[f];
+        int rem = o, row = a * sf;
         T prod = T(1);
-        for (int j = m - 1; j >= 0; --j) {
-          if (j == f) continue;
+#pragma unroll
+        for (int j = kMaxD - 1; j >= 0; --j) {
+          if (j >= m || j == f) continue;
           const int ij = rem % z.v[j];
           rem /= z.v[j];
           row += ij * stride[j];
@@ -69,7 +76,9 @@ __global__ __launch_bounds__(KRP_NT) void krp_kernel(const KrpTask<T>* __restric
     for (int e = tid; e < P; e += KRP_NT) {
       int rem = e;
       T prod = T(1);
-      for (int j = m - 1; j >= 0; --j) {
+#pragma unroll
+      for (int j = kMaxD - 1; j >= 0; --j) {
+        if (j >= m) continue;
         const int ij = rem % z.v[j];
         rem /= z.v[j];
         prod *= mv[j][ij];
