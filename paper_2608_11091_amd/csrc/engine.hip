@@ -870,15 +870,6 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       const int n = sh.n[k];
       q.steps.push_back([=](hipStream_t st) { zero_cols_from<T>(u, n, n, sc, s_dev, st); });
     }
-  } else if (overlap) {
-    // join the rule, then keep the leading s columns of every basis
-    q.steps.push_back(join);
-    emit_width();
-    for (int k = 0; k < d; ++k) {
-      T* u = Uh[k];
-      const int n = sh.n[k];
-      q.steps.push_back([=](hipStream_t st) { zero_cols_from<T>(u, n, n, sc, s_dev, st); });
-    }
   }
   // --- 4. core projection C^ = sum_b c_b G_b x_k (U^_k^T U_bk)
   T* Cb[2] = {ar.alloc<T>(sclen), ar.alloc<T>(sclen)};
@@ -887,6 +878,22 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     std::array<const T*, kMaxD> Uc{};
     for (int k = 0; k < d; ++k) Uc[k] = Uh[k];
     plan_core_projection<T>(q, pl, sh, in, coef, Uc, sc, Cb[0], nb_active);
+  }
+  if (!use_cert && overlap) {
+    // The rule's eigensolves ran beside steps 2-4: join them, then keep the
+    // leading s columns of every basis and the leading s indices of every
+    // core mode.  The projection was formed at the full width sc; basis
+    // column i only meets core index i of its mode, so zeroing both after
+    // the fact gives the same core as projecting onto the zeroed basis.
+    q.steps.push_back(join);
+    emit_width();
+    WidthZero<T> wz{};
+    for (int k = 0; k < d; ++k) {
+      wz.U[k] = Uh[k];
+      wz.n[k] = sh.n[k];
+    }
+    wz.core = Cb[0];
+    q.steps.push_back([=](hipStream_t st) { zero_beyond_width<T>(wz, d, sc, s_dev, st); });
   }
   // --- 5. ST-HOSVD of C^, modes 1..d in order.  Per mode the truncation is
   //        decided by a Jacobi eigen-solve of the Gram of the ROTATED unfolding

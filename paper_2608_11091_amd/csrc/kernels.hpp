@@ -61,6 +61,16 @@ void core_recap(const T* src, const int* sd, const int* sv, T* dst, const int* d
 // Zero columns [*from_dev, cols) of a column-major rows x cols matrix.
 template <typename T>
 void zero_cols_from(T* A, int ld, int rows, int cols, const int* from_dev, hipStream_t st);
+// One launch: columns >= s of the d factors U[k] (n[k] x sc, ld n[k]) and
+// every entry of the dense sc^d core (row-major) with an index >= s.
+template <typename T>
+struct WidthZero {
+  T* U[kMaxD];
+  int n[kMaxD];
+  T* core;
+};
+template <typename T>
+void zero_beyond_width(const WidthZero<T>& a, int d, int sc, const int* s_dev, hipStream_t st);
 // Side stream of the current device (created on first use: non-blocking,
 // default priority) for work that a plan runs beside the caller's stream.
 hipStream_t side_stream();

@@ -70,6 +70,39 @@ __global__ void zero_cols_from_kernel(T* A, int ld, int rows, int cols, const in
 }
 
 template <typename T>
+__global__ void zero_beyond_width_kernel(WidthZero<T> a, int d, int sc, const int* s_dev) {
+  const int s = max(*s_dev, 0);
+  const int part = blockIdx.y;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  const size_t e0 = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (part < d) {
+    T* U = nullptr;
+    int n = 1;
+#pragma unroll
+    for (int k = 0; k < kMaxD; ++k)
+      if (k == part) {
+        U = a.U[k];
+        n = a.n[k];
+      }
+    const size_t len = size_t(n) * sc;
+    for (size_t e = e0; e < len; e += stride)
+      if (int(e / n) >= s) U[e] = T(0);
+  } else {
+    size_t len = 1;
+    for (int k = 0; k < d; ++k) len *= size_t(sc);
+    for (size_t e = e0; e < len; e += stride) {
+      size_t rem = e;
+      bool out = false;
+      for (int k = 0; k < d; ++k) {
+        out = out || int(rem % sc) >= s;
+        rem /= sc;
+      }
+      if (out) a.core[e] = T(0);
+    }
+  }
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void lincomb_kernel(T* const* y, const T* const* x, const double* const* c,
                                                       const double* s, const size_t* len, int ldx, int nx,
                                                       int accumulate) {
@@ -223,6 +256,16 @@ void zero_cols_from(T* A, int ld, int rows, int cols, const int* from_dev, hipSt
   if (rows <= 0 || cols <= 0) return;
   hipLaunchKernelGGL((zero_cols_from_kernel<T>), dim3(gsz(size_t(rows) * cols)), dim3(256), 0, st, A, ld, rows, cols,
                      from_dev);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
+void zero_beyond_width(const WidthZero<T>& a, int d, int sc, const int* s_dev, hipStream_t st) {
+  size_t mx = 1;
+  for (int k = 0; k < d; ++k) mx *= size_t(sc);
+  for (int k = 0; k < d; ++k) mx = std::max(mx, size_t(a.n[k]) * sc);
+  const unsigned gx = unsigned(std::min<size_t>((mx + 255) / 256, 1024));
+  hipLaunchKernelGGL((zero_beyond_width_kernel<T>), dim3(gx, d + 1), dim3(256), 0, st, a, d, sc, s_dev);
   TK_LAUNCH_CHECK();
 }
 
@@ -393,6 +436,8 @@ template void zero_sum_fixup<double>(const double*, const double*, int, const in
 template void zero_sum_fixup<float>(const double*, const double*, int, const int*, int, float* const*, float*, size_t,
                                     int*, hipStream_t);
 template void zero_cols_from<double>(double*, int, int, int, const int*, hipStream_t);
+template void zero_beyond_width<double>(const WidthZero<double>&, int, int, const int*, hipStream_t);
+template void zero_beyond_width<float>(const WidthZero<float>&, int, int, const int*, hipStream_t);
 template void zero_cols_from<float>(float*, int, int, int, const int*, hipStream_t);
 template void mat_axpy<double>(const double*, int, double*, int, int, int, hipStream_t);
 template void mat_axpy<float>(const float*, int, float*, int, int, int, hipStream_t);
