@@ -749,7 +749,16 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     double* Rq = ar.alloc<double>(size_t(d) * sc * sc);
     for (auto& modes : modes_by_n<T>(sh)) {
       const int n = sh.n[modes[0]];
-      for (int k : modes) emit_cast<T>(q, Y[k], Y64[k], size_t(n) * sc);
+      if constexpr (!std::is_same<T, double>::value) {
+        // the FP32 range sketches of these modes to FP64, one launch
+        CastSet<T, double> cs;
+        for (int k : modes) {
+          cs.x[cs.count] = Y[k];
+          cs.y[cs.count] = Y64[k];
+          cs.len[cs.count++] = size_t(n) * sc;
+        }
+        q.steps.push_back([=](hipStream_t st) { cast_multi<T, double>(cs, st); });
+      }
       std::vector<CholTask> ct;
       for (int k : modes) ct.push_back(CholTask{Gq + size_t(k) * sc * sc, Rq + size_t(k) * sc * sc});
       const size_t coff = blob.add(ct);
@@ -784,13 +793,15 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
         const size_t toff = blob.add(tt);
         q.steps.push_back([=](hipStream_t st) { trsm_rows(bl->at<TrsmTask>(toff), nt, n, sc, mq, st); });
       }
-      if (!std::is_same<T, double>::value)
+      if constexpr (!std::is_same<T, double>::value) {
+        CastSet<double, T> cs;
         for (int k : modes) {
-          double* src = Q64[k];
-          T* dst = Uh[k];
-          const size_t len = size_t(n) * sc;
-          q.steps.push_back([=](hipStream_t st) { cast_copy<double, T>(src, dst, len, st); });
+          cs.x[cs.count] = Q64[k];
+          cs.y[cs.count] = Uh[k];
+          cs.len[cs.count++] = size_t(n) * sc;
         }
+        q.steps.push_back([=](hipStream_t st) { cast_multi<double, T>(cs, st); });
+      }
     }
   }
   if (use_cert) {
@@ -865,11 +876,12 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     });
     for (auto& f : eig_steps) q.steps.push_back(f);
     emit_width();
+    WidthZero<T> wz{};
     for (int k = 0; k < d; ++k) {
-      T* u = Uh[k];
-      const int n = sh.n[k];
-      q.steps.push_back([=](hipStream_t st) { zero_cols_from<T>(u, n, n, sc, s_dev, st); });
+      wz.U[k] = Uh[k];
+      wz.n[k] = sh.n[k];
     }
+    q.steps.push_back([=](hipStream_t st) { zero_beyond_width<T>(wz, d, sc, s_dev, st); });
   }
   // --- 4. core projection C^ = sum_b c_b G_b x_k (U^_k^T U_bk)
   T* Cb[2] = {ar.alloc<T>(sclen), ar.alloc<T>(sclen)};
@@ -1276,9 +1288,12 @@ void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>
         xs.push_back(Xt[k]);
         fs.push_back(fac[k][i]);
       }
-      q.steps.push_back([=](hipStream_t st) {
-        for (int a2 = 0; a2 < na; ++a2) mat_recap<double>(fs[a2], n, n, rc, xs[a2], n, n, rc, st);
-      });
+      // the first block's QR reads the factors in place (it does not write
+      // its input); later blocks are orthogonalised in a working copy
+      if (i > 0)
+        q.steps.push_back([=](hipStream_t st) {
+          for (int a2 = 0; a2 < na; ++a2) mat_recap<double>(fs[a2], n, n, rc, xs[a2], n, n, rc, st);
+        });
       if (i > 0) {
         const int Kq = i * rc;
         // C1 = Q^T F -> R[0:Kq, block i];  X -= Q C1;  C2 = Q^T X;  X -= Q C2
@@ -1309,14 +1324,19 @@ void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>
       // block there is nothing to cut against: the R of a plain Householder
       // QR gives the same core norm (a column the cut would drop contributes
       // at the 64 u level), at a fraction of the pivoted kernel's cost.
+      // With one factor per mode (Md = rc) the first block's R goes straight
+      // into its place in R_k.
+      const bool direct_r = i == 0 && Md == rc;
       std::vector<QrPivTask> qt;
       std::vector<QrTask> qs;
       for (int k : act) {
         const bool need_q = i > 0 || int(fac[k].size()) > 1;
+        const double* y = i == 0 ? fac[k][0] : Xt[k];
+        double* r = direct_r ? Rk[k] : Rt[k];
         if (need_q)
-          qt.push_back(QrPivTask{Xt[k], fac[k][i], Qi(k), Rt[k], facr[k][i]});
+          qt.push_back(QrPivTask{y, fac[k][i], Qi(k), r, facr[k][i]});
         else
-          qs.push_back(QrTask{Xt[k], nullptr, Rt[k], facr[k][i]});
+          qs.push_back(QrTask{y, nullptr, r, facr[k][i]});
       }
       if (!qs.empty()) {
         const size_t off = pl.blob.add(qs);
@@ -1329,15 +1349,17 @@ void plan_exact_norm2(Seq& q, Planner& pl, const Shape& sh, const Blocks<double>
         q.steps.push_back([=](hipStream_t st) { qr_piv_batched(bl->at<QrPivTask>(off), np, n, rc, kCutTol, st); });
       }
       if (i == 0) {
-        std::vector<const double*> rts;
-        std::vector<double*> rds;
-        for (int k : act) {
-          rts.push_back(Rt[k]);
-          rds.push_back(Rdiag(k));
+        if (!direct_r) {
+          std::vector<const double*> rts;
+          std::vector<double*> rds;
+          for (int k : act) {
+            rts.push_back(Rt[k]);
+            rds.push_back(Rdiag(k));
+          }
+          q.steps.push_back([=](hipStream_t st) {
+            for (int a2 = 0; a2 < na; ++a2) mat_recap<double>(rts[a2], rc, rc, rc, rds[a2], Md, rc, rc, st);
+          });
         }
-        q.steps.push_back([=](hipStream_t st) {
-          for (int a2 = 0; a2 < na; ++a2) mat_recap<double>(rts[a2], rc, rc, rc, rds[a2], Md, rc, rc, st);
-        });
         continue;
       }
       // Re-orthogonalise the new block's basis against the previous blocks: a

@@ -53,6 +53,16 @@ void count_nonfinite(const double* const* xs, const size_t* lens, int ntasks, si
                      hipStream_t st);
 template <typename A, typename B>
 void cast_copy(const A* x, B* y, size_t len, hipStream_t st);
+// Up to kMaxD conversions y[i] = B(x[i]) of lengths len[i] in one launch.
+template <typename A, typename B>
+struct CastSet {
+  const A* x[kMaxD];
+  B* y[kMaxD];
+  size_t len[kMaxD];
+  int count = 0;
+};
+template <typename A, typename B>
+void cast_multi(const CastSet<A, B>& set, hipStream_t st);
 // Copy a d-way core between capacity layouts: src has layout dims sd[] of
 // which the leading sv[] are valid, dst has layout dims dd[]; dst entries
 // outside the valid region are zero.
@@ -61,8 +71,9 @@ void core_recap(const T* src, const int* sd, const int* sv, T* dst, const int* d
 // Zero columns [*from_dev, cols) of a column-major rows x cols matrix.
 template <typename T>
 void zero_cols_from(T* A, int ld, int rows, int cols, const int* from_dev, hipStream_t st);
-// One launch: columns >= s of the d factors U[k] (n[k] x sc, ld n[k]) and
-// every entry of the dense sc^d core (row-major) with an index >= s.
+// One launch: columns >= s of the d factors U[k] (n[k] x sc, ld n[k]) and,
+// unless core is null, every entry of the dense sc^d core (row-major) with an
+// index >= s.
 template <typename T>
 struct WidthZero {
   T* U[kMaxD];

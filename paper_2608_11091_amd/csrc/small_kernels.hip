@@ -265,7 +265,8 @@ void zero_beyond_width(const WidthZero<T>& a, int d, int sc, const int* s_dev, h
   for (int k = 0; k < d; ++k) mx *= size_t(sc);
   for (int k = 0; k < d; ++k) mx = std::max(mx, size_t(a.n[k]) * sc);
   const unsigned gx = unsigned(std::min<size_t>((mx + 255) / 256, 1024));
-  hipLaunchKernelGGL((zero_beyond_width_kernel<T>), dim3(gx, d + 1), dim3(256), 0, st, a, d, sc, s_dev);
+  const unsigned parts = a.core ? d + 1 : d;
+  hipLaunchKernelGGL((zero_beyond_width_kernel<T>), dim3(gx, parts), dim3(256), 0, st, a, d, sc, s_dev);
   TK_LAUNCH_CHECK();
 }
 

@@ -202,6 +202,22 @@ __global__ void cast_kernel(const A* __restrict__ x, B* __restrict__ y, size_t l
     y[e] = B(x[e]);
 }
 
+template <typename A, typename B>
+__global__ void cast_multi_kernel(CastSet<A, B> set) {
+  const A* x = nullptr;
+  B* y = nullptr;
+  size_t len = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxD; ++k)
+    if (k == int(blockIdx.y)) {
+      x = set.x[k];
+      y = set.y[k];
+      len = set.len[k];
+    }
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < len; e += (size_t)gridDim.x * blockDim.x)
+    y[e] = B(x[e]);
+}
+
 template <typename T>
 __global__ void core_recap_kernel(const T* __restrict__ src, Dims4 sd, Dims4 sv, T* __restrict__ dst, Dims4 dd,
                                   int d, size_t total) {
@@ -342,6 +358,16 @@ void fill(T* y, size_t len, T v, hipStream_t st) {
 }
 
 template <typename A, typename B>
+void cast_multi(const CastSet<A, B>& set, hipStream_t st) {
+  TK_CHECK(set.count >= 0 && set.count <= kMaxD, kErrInvalidArg, "cast_multi: too many buffers");
+  size_t mx = 0;
+  for (int k = 0; k < set.count; ++k) mx = std::max(mx, set.len[k]);
+  if (mx == 0) return;
+  hipLaunchKernelGGL((cast_multi_kernel<A, B>), dim3(grid_for(mx), set.count), dim3(256), 0, st, set);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename A, typename B>
 void cast_copy(const A* x, B* y, size_t len, hipStream_t st) {
   if (len == 0) return;
   hipLaunchKernelGGL((cast_kernel<A, B>), dim3(grid_for(len)), dim3(256), 0, st, x, y, len);
@@ -406,6 +432,8 @@ TK_INST(double)
 TK_INST(float)
 #undef TK_INST
 template void cast_copy<double, float>(const double*, float*, size_t, hipStream_t);
+template void cast_multi<double, float>(const CastSet<double, float>&, hipStream_t);
+template void cast_multi<float, double>(const CastSet<float, double>&, hipStream_t);
 template void cast_copy<float, double>(const float*, double*, size_t, hipStream_t);
 template void fill<int>(int*, size_t, int, hipStream_t);
 
