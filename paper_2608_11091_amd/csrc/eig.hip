@@ -650,7 +650,25 @@ __global__ __launch_bounds__(1024) void jacobi_blk_kernel(const EigTask<T>* __re
   for (int e = tid; e < NP * NP; e += NT) {
     const int c = e / NP, r = e % NP;
     if (r < c) continue;
-    const T a = r < N ? tk_.A[r + (size_t)c * tk_.lda] : T(0);
+    T a = T(0);
+    if (r < N) {
+      const size_t at = r + (size_t)c * tk_.lda;
+      if (tk_.part) {  // the matrix's split-K partials, summed in split order
+        // (eight loads in flight at a time; the additions keep their order)
+        const T* pp = tk_.part + at;
+        int sp = 0;
+        for (; sp + 8 <= tk_.splits; sp += 8) {
+          T v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = pp[(sp + u) * tk_.pstride];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a += v[u];
+        }
+        for (; sp < tk_.splits; ++sp) a += pp[sp * tk_.pstride];
+      } else {
+        a = tk_.A[at];
+      }
+    }
     A[c * LD + r] = a;
     A[r * LD + c] = a;
   }

@@ -12,6 +12,16 @@ namespace tk {
 namespace {
 
 // ---------------------------------------------------------------- helpers
+// Where a product's split-K partials were left for its consumer to sum
+// (part = nullptr: the product ran whole and wrote C).  Group g's partials
+// start at part + g * splits * stride.
+template <typename T>
+struct SplitOut {
+  const T* part = nullptr;
+  int splits = 1;
+  size_t stride = 0;  // M * N, one partial
+};
+
 template <typename T>
 struct GemmDesc {
   bool ta = false, tb = false;
@@ -24,6 +34,10 @@ struct GemmDesc {
   std::function<int(int)> ngroups_of;  // active groups as a function of *nb
   bool terms_are_blocks = false;       // clamp each group's terms to *nb
   bool factor_product = false;         // a product with a Tucker factor (BF16 in the BF16-factor form)
+  // optional: the only consumer of C sums the split-K partials itself, which
+  // saves the reduction launch (C is then not written); needs beta = 0,
+  // ldc = M and a fixed group count
+  SplitOut<T>* split_out = nullptr;
 
   void group(T* C, const std::vector<GemmTerm<T>>& ts) {
     GemmGroup<T> g;
@@ -79,6 +93,15 @@ void emit_gemm(Seq& q, Planner& pl, GemmDesc<T>&& g) {
   L.partial = partial;
   L.bf16 = std::is_same<T, float>::value && pl.bf16_factors && g.factor_product;
   L.ngroups = ng;
+  if (g.split_out) {
+    TK_CHECK(g.beta == 0.0 && g.ldc == g.M && g.nb == nullptr, kErrUnsupported,
+             "internal: deferred split-K reduction needs beta = 0, ldc = M and fixed groups");
+    *g.split_out = SplitOut<T>{};
+    if (splits > 1) {
+      L.defer_reduce = true;
+      *g.split_out = SplitOut<T>{partial, splits, size_t(g.M) * g.N};
+    }
+  }
   const int* nb = g.nb;
   auto ngf = g.ngroups_of;
   const bool tb = g.terms_are_blocks;
@@ -175,7 +198,7 @@ void emit_ttm(Seq& q, Planner& pl, int d, const int* dims, int k, int newdim, co
 // G = X_(k) Y_(k)^T (mid x mid, ld ldg) for two tensors of dims `dims`.
 template <typename T>
 void emit_unfold_gram(Seq& q, Planner& pl, int d, const int* dims, int k, const T* X, const T* Y, T* G, int ldg,
-                      double scale = 1.0) {
+                      double scale = 1.0, SplitOut<T>* split_out = nullptr) {
   long pre = 1, post = 1;
   for (int j = 0; j < k; ++j) pre *= dims[j];
   for (int j = k + 1; j < d; ++j) post *= dims[j];
@@ -202,6 +225,7 @@ void emit_unfold_gram(Seq& q, Planner& pl, int d, const int* dims, int k, const 
       ts.push_back(term<T>(X + size_t(p) * post * mid, Y + size_t(p) * post * mid, nullptr, nullptr, nullptr, scale));
     g.group(G, ts);
   }
+  g.split_out = split_out;
   emit_gemm(q, pl, std::move(g));
 }
 
@@ -761,7 +785,6 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       }
       std::vector<CholTask> ct;
       for (int k : modes) ct.push_back(CholTask{Gq + size_t(k) * sc * sc, Rq + size_t(k) * sc * sc});
-      const size_t coff = blob.add(ct);
       const int nt = int(ct.size());
       const double shift1 = 11.0 * (double(n) * sc + double(sc) * (sc + 1)) * 0x1p-53;
       for (int pass = 0; pass < 3; ++pass) {
@@ -781,12 +804,23 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
         g.ldb = n;
         g.ldc = sc;
         for (size_t i = 0; i < modes.size(); ++i) g.group1(Gq + size_t(modes[i]) * sc * sc, src[i], src[i]);
+        // the Cholesky kernel sums the Gram's split-K partials itself
+        SplitOut<double> so;
+        g.split_out = &so;
         emit_gemm(q, pl, std::move(g));
+        std::vector<CholTask> ctp = ct;
+        for (size_t i = 0; i < ctp.size(); ++i)
+          if (so.part) {
+            ctp[i].part = so.part + i * size_t(so.splits) * so.stride;
+            ctp[i].splits = so.splits;
+            ctp[i].pstride = so.stride;
+          }
+        const size_t cpo = blob.add(ctp);
         const double sh_p = pass == 0 ? shift1 : 0.0;
         const double drel = pass == 1 ? 1e-30 : 0.0, dabs = pass == 2 ? 0.25 : 0.0;
         const int* mq = overlap ? nullptr : s_dev;
         q.steps.push_back(
-            [=](hipStream_t st) { chol_batched(bl->at<CholTask>(coff), nt, sc, mq, sh_p, drel, dabs, st); });
+            [=](hipStream_t st) { chol_batched(bl->at<CholTask>(cpo), nt, sc, mq, sh_p, drel, dabs, st); });
         std::vector<TrsmTask> tt;
         for (size_t i = 0; i < modes.size(); ++i)
           tt.push_back(TrsmTask{src[i], Rq + size_t(modes[i]) * sc * sc, dst[i]});
@@ -937,12 +971,17 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       V1[k] = ar.alloc<T>(size_t(sc) * sc);
       V2[k] = ar.alloc<T>(size_t(sc) * sc);
       U12[k] = ar.alloc<T>(size_t(sc) * sc);
-      emit_unfold_gram<T>(q, pl, d, dims, k, Cb[0], Cb[0], G1 + size_t(k) * sc * sc, sc);
+      // the eigensolver sums the Gram's split-K partials itself
+      SplitOut<T> so;
+      emit_unfold_gram<T>(q, pl, d, dims, k, Cb[0], Cb[0], G1 + size_t(k) * sc * sc, sc, 1.0, &so);
       et[k] = EigTask<T>{};
       et[k].A = G1 + size_t(k) * sc * sc;
       et[k].lda = sc;
       et[k].lam = lam1 + size_t(k) * sc;
       et[k].V = V1[k];
+      et[k].part = so.part;
+      et[k].splits = so.splits;
+      et[k].pstride = so.stride;
     }
     const size_t off = blob.add(et);
     q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off), d, sc, true, st); });
@@ -950,12 +989,16 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
   int cb = 0;
   for (int k = 0; k < d; ++k) {
     emit_ttm<T>(q, pl, d, dims, k, sc, {Cb[cb]}, {V1[k]}, sc, true, {Bt});
-    emit_unfold_gram<T>(q, pl, d, dims, k, Bt, Bt, G2, sc);
+    SplitOut<T> so;
+    emit_unfold_gram<T>(q, pl, d, dims, k, Bt, Bt, G2, sc, 1.0, &so);
     {
       std::vector<EigTask<T>> et(1);
       et[0] = EigTask<T>{};
       et[0].A = G2;
       et[0].lda = sc;
+      et[0].part = so.part;
+      et[0].splits = so.splits;
+      et[0].pstride = so.stride;
       et[0].lam = lam2;
       et[0].V = V2[k];
       et[0].rule.kind = 2;

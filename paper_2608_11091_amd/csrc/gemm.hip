@@ -251,7 +251,7 @@ void gemm_run(const GemmLaunch<T>& g, hipStream_t st) {
   }
 #undef TK_GEMM_CASE
   TK_LAUNCH_CHECK();
-  if (g.splits > 1) {
+  if (g.splits > 1 && !g.defer_reduce) {
     const size_t MN = (size_t)g.M * g.N;
     dim3 rg((unsigned)std::min<size_t>((MN + 255) / 256, 64), g.ngroups);
     hipLaunchKernelGGL((splitk_reduce<T>), rg, dim3(256), 0, st, g.M, g.N, g.ldc, g.groups, g.beta, g.splits, part);

@@ -42,6 +42,7 @@ struct GemmLaunch {
   T* partial = nullptr;    // ngroups * splits * M * N
   int max_terms = 1 << 30; // clamp every group to its first max_terms terms
   bool bf16 = false;       // FP32 storage: round the operands to bfloat16, BF16 matrix cores, FP32 accumulation
+  bool defer_reduce = false;  // splits > 1: leave the partials for the consumer to sum (C is not written)
   double flops = 0.0;      // algorithmic flops of this launch (for the kernel timer)
 };
 

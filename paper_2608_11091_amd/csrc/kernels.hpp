@@ -127,6 +127,11 @@ void qr_piv_batched(const QrPivTask* tasks_d, int ntasks, int n, int cap, double
 struct CholTask {
   const double* G;  // cap x cap, col-major
   double* R;        // cap x cap, col-major (upper triangle)
+  // optional: G is not formed; its entries are the sums, in order, of
+  // part[sp * pstride + i + j * cap] over sp < splits (split-K partials)
+  const double* part = nullptr;
+  int splits = 0;
+  size_t pstride = 0;
 };
 void chol_batched(const CholTask* tasks_d, int ntasks, int cap, const int* m_dev, double shift, double dead_rel,
                   double dead_abs, hipStream_t st);
@@ -166,6 +171,12 @@ struct EigTask {
   const int* cert; // optional device flags cert[0..ncert): any nonzero = do nothing (the rank certificate decided)
   int ncert;
   EigRule rule;
+  // optional (eigensolver with vectors): A is not formed; its entries are the
+  // sums, in order sp = 0..splits-1, of part[sp * pstride + r + c * lda]
+  // (the split-K partials of the product that would have written A)
+  const T* part;
+  int splits;
+  size_t pstride;
 };
 // Eigenvalues only: N <= 512; above kEigRegMax the matrix is reduced in place
 // (A must then be writable scratch).  With vectors: N <= 64.

@@ -411,7 +411,25 @@ __global__ __launch_bounds__(CH_NT) void chol_kernel(const CholTask* __restrict_
   m = min(m, cap);
   for (int e = tid; e < cap * cap; e += CH_NT) {
     const int i = e % cap, j = e / cap;
-    G[i][j] = (i < m && j < m) ? tk_.G[i + (size_t)j * cap] : 0.0;
+    double g = 0.0;
+    if (i < m && j < m) {
+      if (tk_.part) {  // the Gram's split-K partials, summed in split order
+        // (eight loads in flight at a time; the additions keep their order)
+        const double* pp = tk_.part + i + (size_t)j * cap;
+        int sp = 0;
+        for (; sp + 8 <= tk_.splits; sp += 8) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = pp[(sp + u) * tk_.pstride];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) g += v[u];
+        }
+        for (; sp < tk_.splits; ++sp) g += pp[sp * tk_.pstride];
+      } else {
+        g = tk_.G[i + (size_t)j * cap];
+      }
+    }
+    G[i][j] = g;
   }
   __syncthreads();
   const double tr = block_sum(tid < m ? G[tid][tid] : 0.0, red);
