@@ -907,15 +907,18 @@ __global__ __launch_bounds__(CERT_NT) void rank_cert_kernel(const T* __restrict_
 }  // namespace
 
 template <typename T>
-void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipStream_t st) {
+void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipStream_t st, int in_splits) {
   if (ntasks <= 0 || N <= 0) return;
   // algorithmic work of a symmetric eigendecomposition of order N: 9 N^3 with
   // eigenvectors (symmetric QR algorithm count), (4/3) N^3 for the tridiagonal
-  // reduction behind the eigenvalues-only path
+  // reduction behind the eigenvalues-only path.  Bytes: the lower triangle of
+  // every input slab (the matrix, or each split-K partial that the load sums),
+  // plus the eigenvalues and, with vectors, the N x N eigenvectors.
   const int kc = want_v ? kKcJacobi : kKcEigVals;
   const double nn = double(N);
+  const double in_b = (want_v ? double(in_splits) * nn * (nn + 1.0) / 2.0 : nn * nn);
   timer_begin(kc, st, double(ntasks) * (want_v ? 9.0 : 4.0 / 3.0) * nn * nn * nn,
-              double(ntasks) * sizeof(T) * ((want_v ? 2.0 : 1.0) * nn * nn + nn));
+              double(ntasks) * sizeof(T) * (in_b + (want_v ? nn * nn : 0.0) + nn));
   if (want_v) {
     TK_CHECK(N <= VEC_NMAX, kErrUnsupported, "symmetric eigensolver: eigenvectors above size 64");
     hipLaunchKernelGGL((jacobi_blk_kernel<T>), dim3(ntasks), dim3(1024), 0, st, tasks_d, N);
@@ -956,7 +959,7 @@ template void rank_certificate<double>(const double*, const double*, const doubl
 template void rank_certificate<float>(const float*, const double*, const double*, int, const double*,
                                       const CertParams&, int*, int*, hipStream_t);
 
-template void jacobi_eig<double>(const EigTask<double>*, int, int, bool, hipStream_t);
-template void jacobi_eig<float>(const EigTask<float>*, int, int, bool, hipStream_t);
+template void jacobi_eig<double>(const EigTask<double>*, int, int, bool, hipStream_t, int);
+template void jacobi_eig<float>(const EigTask<float>*, int, int, bool, hipStream_t, int);
 
 }  // namespace tk

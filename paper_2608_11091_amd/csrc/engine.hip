@@ -967,6 +967,7 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
   for (int j = 0; j < d; ++j) dims[j] = sc;
   {
     std::vector<EigTask<T>> et(d);
+    int in_splits = 1;
     for (int k = 0; k < d; ++k) {
       V1[k] = ar.alloc<T>(size_t(sc) * sc);
       V2[k] = ar.alloc<T>(size_t(sc) * sc);
@@ -982,9 +983,10 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       et[k].part = so.part;
       et[k].splits = so.splits;
       et[k].pstride = so.stride;
+      in_splits = std::max(in_splits, so.splits);  // equal for every mode (same K)
     }
     const size_t off = blob.add(et);
-    q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off), d, sc, true, st); });
+    q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off), d, sc, true, st, in_splits); });
   }
   int cb = 0;
   for (int k = 0; k < d; ++k) {
@@ -1010,7 +1012,8 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       et[0].rule.force = (cfg.force_r[k] >= 0) ? force_dev + k : nullptr;
       et[0].rule.rank_out = out.rank + k;
       const size_t off = blob.add(et);
-      q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off), 1, sc, true, st); });
+      const int in_splits = std::max(1, so.splits);
+      q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off), 1, sc, true, st, in_splits); });
     }
     emit_ttm<T>(q, pl, d, dims, k, sc, {Bt}, {V2[k]}, sc, true, {Cb[1 - cb]});
     {

@@ -179,10 +179,12 @@ struct EigTask {
   size_t pstride;
 };
 // Eigenvalues only: N <= 512; above kEigRegMax the matrix is reduced in place
-// (A must then be writable scratch).  With vectors: N <= 64.
+// (A must then be writable scratch).  With vectors: N <= 64.  in_splits is the
+// number of split-K partials the tasks' loads sum (1 when they read A); it
+// only enters the kernel timer's byte count.
 constexpr int kEigRegMax = 160;
 template <typename T>
-void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipStream_t st);
+void jacobi_eig(const EigTask<T>* tasks_d, int ntasks, int N, bool want_v, hipStream_t st, int in_splits = 1);
 
 // Certificate for the effective-rank rule of RoundSum (Sec. 3.1), one task
 // per mode k.  H_k = Q_k^T G_k Q_k (cap x cap, ld cap, T) is the compression of
