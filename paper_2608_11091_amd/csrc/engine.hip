@@ -66,11 +66,12 @@ void emit_gemm(Seq& q, Planner& pl, GemmDesc<T>&& g) {
   int maxt = 1;
   for (auto& gr : g.groups) maxt = std::max(maxt, gr.t1 - gr.t0);
   const long tiles = long(ceil_div(g.M, 64)) * ceil_div(g.N, 64) * ng;
-  const long slabs = long(maxt) * ceil_div(g.K, 16);
-  // Split-K for the path's small, long-K products: about four 16-deep K slabs
-  // per workgroup (measured on the path's shapes: a 48 x 53 x 512 product
-  // takes 44.9 / 16.4 / 12.1 / 11.5 us at 1 / 4 / 8 / 16 splits, kernel and
-  // reduction); products that already fill the chip or have few slabs run whole.
+  const long slabs = long(maxt) * ceil_div(g.K, 16);  // in units of 16 of K
+  // Split-K for the path's small, long-K products: about 64 of K (two of the
+  // kernel's 32-deep slabs) per workgroup (measured on the path's shapes: a
+  // 48 x 53 x 512 product took 44.9 / 16.4 / 12.1 / 11.5 us at 1 / 4 / 8 / 16
+  // splits, kernel and reduction); products that already fill the chip or
+  // have little K run whole.
   int splits = 1;
   if (tiles < 256 && slabs >= 16) {
     splits = int(std::min<long>(slabs / 4, std::max<long>(1, 512 / tiles)));

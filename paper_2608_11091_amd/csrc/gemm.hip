@@ -3,9 +3,9 @@
 // Tile: 64 x 64 outputs per workgroup of 256 threads (4 waves in a 2 x 2
 // arrangement), each wave owning a 32 x 32 sub-tile = 2 x 2 MFMA 16x16
 // accumulators so four independent MFMA chains hide the pipeline latency.
-// K is staged through LDS in slabs of 16 with global loads coalesced along
-// the contiguous dimension of each operand; the alpha of a term is folded
-// into the A slab while it is staged.
+// K is staged through LDS in slabs of 32 (16 in the bf16 form) with global
+// loads coalesced along the contiguous dimension of each operand; the alpha
+// of a term is folded into the A slab while it is staged.
 #include "gemm.hpp"
 
 namespace tk {
@@ -41,8 +41,13 @@ __device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
-constexpr int SA = (BM * BK) / NT, SB = (BN * BK) / NT;  // staged elements per thread
+constexpr int BM = 64, BN = 64, NT = 256;
+
+// Operand pointers come from the term table, so the compiler cannot tell
+// that they address global memory; loads through them in this address space
+// are global loads rather than flat ones.
+template <typename T>
+using GPtr = const __attribute__((address_space(1))) T*;
 
 // Split-K: the (term, K-slab) iteration space of a group is divided evenly
 // over `splits` workgroups per output tile; each writes its partial tile and a
@@ -55,9 +60,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
                                                   const GemmGroup<T>* __restrict__ groups, double beta,
                                                   int splits, T* __restrict__ partial, int max_terms) {
   static_assert(!BF || sizeof(T) == 4, "bf16 operands with FP32 storage only");
-  constexpr int BKP = BK + 4;  // bf16 row: 16 k values + 4 pad (40 bytes: conflict-free 8-byte reads)
-  __shared__ T As[BF ? 1 : BK][BM + 1];
-  __shared__ T Bs[BF ? 1 : BK][BN + 1];
+  // K depth of a slab: 32 (8 loads per operand and thread in flight at once,
+  // half the slab iterations of a 16-deep slab on the path's short-K
+  // workgroups); 16 for the bf16 form, one 16-deep MFMA per output tile
+  constexpr int KB = BF ? 16 : 32;
+  constexpr int SA = (BM * KB) / NT, SB = (BN * KB) / NT;  // staged elements per thread
+  constexpr int BKP = 16 + 4;  // bf16 row: 16 k values + 4 pad (40 bytes: conflict-free 8-byte reads)
+  __shared__ T As[BF ? 1 : KB][BM + 1];
+  __shared__ T Bs[BF ? 1 : KB][BN + 1];
   __shared__ __align__(8) unsigned short Asb[BF ? BM : 1][BKP];  // [m][k]
   __shared__ __align__(8) unsigned short Bsb[BF ? BN : 1][BKP];  // [n][k]
   const int tid = threadIdx.x;
@@ -80,7 +90,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
 
   const int t1 = min(grp.t1, grp.t0 + max_terms);
   const int nterm = max(0, t1 - grp.t0);
-  const int nks = (K + BK - 1) / BK;
+  const int nks = (K + KB - 1) / KB;
   const int total = nterm * nks;
   const int per = (total + splits - 1) / splits;
   const int sb = sp * per, se = min(total, sb + per);
@@ -90,25 +100,32 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
 #pragma unroll
   for (int i = 0; i < SA; ++i) {
     if (!TA) { am[i] = tid & 63; ak[i] = (tid >> 6) + 4 * i; }
-    else { ak[i] = tid & 15; am[i] = (tid >> 4) + 16 * i; }
+    else { ak[i] = tid % KB; am[i] = tid / KB + (NT / KB) * i; }
   }
 #pragma unroll
   for (int i = 0; i < SB; ++i) {
-    if (!TB) { bk[i] = tid & 15; bn[i] = (tid >> 4) + 16 * i; }
+    if (!TB) { bk[i] = tid % KB; bn[i] = tid / KB + (NT / KB) * i; }
     else { bn[i] = tid & 63; bk[i] = (tid >> 6) + 4 * i; }
   }
   // Slab s is fetched into registers one slab ahead of its use, so its global
-  // loads are in flight while the matrix cores work on slab s - 1.  A term
-  // with alpha == 0 stages zeros (its operands are never read).
+  // loads are in flight while the matrix cores work on slab s - 1.  The loads
+  // are unconditional (an out-of-range element reads element 0 of its live
+  // operand) and go through the global address space; the range test and the
+  // term's alpha are applied when the slab is staged into LDS: a select or a
+  // multiply right after a load, or a flat load (counted with the LDS
+  // operations that every barrier waits for), would make the thread wait for
+  // that load before issuing the next.  A term with alpha == 0 stages zeros
+  // and reads neither operand.
   int cur = -1;
   T alpha = T(0);
-  bool live_next = false;  // whether the fetched slab's term has a nonzero alpha (uniform)
+  T alpha_next = T(0);     // alpha of the fetched slab's term (uniform)
+  bool live_next = false;  // whether that alpha is nonzero (uniform)
   const T* Ap = nullptr;
   const T* Bp = nullptr;
   T ra[SA], rb[SB];
   auto fetch = [&](int slab) {
     const int t = grp.t0 + slab / nks;
-    const int k0 = (slab % nks) * BK;
+    const int k0 = (slab % nks) * KB;
     if (t != cur) {
       const GemmTerm<T> tm = terms[t];
       double al = tm.scale;
@@ -120,21 +137,22 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
       Bp = tm.B;
       cur = t;
     }
-    const bool live = alpha != T(0);
-    live_next = live;
+    alpha_next = alpha;
+    live_next = alpha != T(0);
+    if (!live_next) return;
+    const GPtr<T> ga = (GPtr<T>)Ap;
+    const GPtr<T> gb = (GPtr<T>)Bp;
 #pragma unroll
     for (int i = 0; i < SA; ++i) {
       const int gm = m0 + am[i], gk = k0 + ak[i];
-      T v = T(0);
-      if (live && gm < M && gk < K) v = (TA ? Ap[gk + (size_t)gm * lda] : Ap[gm + (size_t)gk * lda]) * alpha;
-      ra[i] = v;
+      const size_t at = (gm < M && gk < K) ? (TA ? gk + (size_t)gm * lda : gm + (size_t)gk * lda) : 0;
+      ra[i] = ga[at];
     }
 #pragma unroll
     for (int i = 0; i < SB; ++i) {
       const int gn = n0 + bn[i], gk = k0 + bk[i];
-      T v = T(0);
-      if (live && gn < N && gk < K) v = TB ? Bp[gn + (size_t)gk * ldb] : Bp[gk + (size_t)gn * ldb];
-      rb[i] = v;
+      const size_t at = (gn < N && gk < K) ? (TB ? gn + (size_t)gk * ldb : gk + (size_t)gn * ldb) : 0;
+      rb[i] = gb[at];
     }
   };
   if (sb < se) fetch(sb);
@@ -142,20 +160,27 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
     // a slab of a zero-coefficient term (e.g. a disabled Gram block) adds
     // nothing: it is neither staged nor multiplied (the branch is uniform)
     const bool lv = live_next;
+    const T al = alpha_next;
     if (!lv) {
       if (slab + 1 < se) fetch(slab + 1);
       continue;
     }
+    const int k0 = (slab % nks) * KB;
+    T va[SA], vb[SB];
+#pragma unroll
+    for (int i = 0; i < SA; ++i) va[i] = (m0 + am[i] < M && k0 + ak[i] < K) ? ra[i] * al : T(0);
+#pragma unroll
+    for (int i = 0; i < SB; ++i) vb[i] = (n0 + bn[i] < N && k0 + bk[i] < K) ? rb[i] : T(0);
     if constexpr (BF) {
 #pragma unroll
-      for (int i = 0; i < SA; ++i) Asb[am[i]][ak[i]] = bf16_rne(float(ra[i]));
+      for (int i = 0; i < SA; ++i) Asb[am[i]][ak[i]] = bf16_rne(float(va[i]));
 #pragma unroll
-      for (int i = 0; i < SB; ++i) Bsb[bn[i]][bk[i]] = bf16_rne(float(rb[i]));
+      for (int i = 0; i < SB; ++i) Bsb[bn[i]][bk[i]] = bf16_rne(float(vb[i]));
     } else {
 #pragma unroll
-      for (int i = 0; i < SA; ++i) As[ak[i]][am[i]] = ra[i];
+      for (int i = 0; i < SA; ++i) As[ak[i]][am[i]] = va[i];
 #pragma unroll
-      for (int i = 0; i < SB; ++i) Bs[bk[i]][bn[i]] = rb[i];
+      for (int i = 0; i < SB; ++i) Bs[bk[i]][bn[i]] = vb[i];
     }
     __syncthreads();
     if (slab + 1 < se) fetch(slab + 1);
@@ -173,7 +198,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, int lda, 
         for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16(a[i], b[j], acc[i][j]);
     } else {
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
+      for (int kk = 0; kk < KB; kk += 4) {
         const int kr = kk + (lane >> 4);
         T a[2], b[2];
 #pragma unroll
