@@ -7,6 +7,7 @@
 // loads coalesced along the contiguous dimension of each operand; the alpha
 // of a term is folded into the A slab while it is staged.
 #include "gemm.hpp"
+#include "kernels.hpp"
 
 namespace tk {
 
@@ -43,11 +44,6 @@ __device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c) {
 
 constexpr int BM = 64, BN = 64, NT = 256;
 
-// Operand pointers come from the term table, so the compiler cannot tell
-// that they address global memory; loads through them in this address space
-// are global loads rather than flat ones.
-template <typename T>
-using GPtr = const __attribute__((address_space(1))) T*;
 
 // Split-K: the (term, K-slab) iteration space of a group is divided evenly
 // over `splits` workgroups per output tile; each writes its partial tile and a

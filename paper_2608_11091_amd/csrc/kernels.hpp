@@ -5,6 +5,13 @@
 
 namespace tk {
 
+// Device pointers read from task tables are generic to the compiler; loads
+// through this global address space alias are global loads rather than flat
+// ones (a flat load also counts as an LDS operation, so every barrier's LDS
+// wait would wait for it, and prefetches would not stay in flight).
+template <typename T>
+using GPtr = const __attribute__((address_space(1))) T*;
+
 // ---- Khatri-Rao reductions (MTTKRP tail and Khatri-Rao sketch) -------------
 // Z is a P x S column-major matrix whose rows are a row-major multi-index over
 // m modes of sizes z[0..m-1].  For free position f (0 <= f < m) it computes

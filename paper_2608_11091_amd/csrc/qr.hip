@@ -473,16 +473,30 @@ __global__ __launch_bounds__(TR_NT) void trsm_rows_kernel(const TrsmTask* __rest
   const int tid = threadIdx.x;
   int m = m_dev ? *m_dev : cap;
   m = min(m, cap);
-  for (int e = tid; e < cap * cap; e += TR_NT) {
-    const int i = e % cap, j = e / cap;
-    R[i][j] = tk_.R[i + (size_t)j * cap];
+  {
+    // every load of R in flight at once, then the LDS writes
+    constexpr int RPT = CH_MAX * CH_MAX / TR_NT;
+    const GPtr<double> gr = (GPtr<double>)tk_.R;
+    const int cc = cap * cap;
+    double rv[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int e = tid + u * TR_NT;
+      rv[u] = gr[e < cc ? e : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int e = tid + u * TR_NT;
+      if (e < cc) R[e % cap][e / cap] = rv[u];
+    }
   }
   __syncthreads();
   const int row = blockIdx.x * TR_NT + tid;
   if (row >= n) return;
   double q[CH_MAX];
+  const GPtr<double> gy = (GPtr<double>)tk_.Y;
 #pragma unroll
-  for (int j = 0; j < CH_MAX; ++j) q[j] = (j < m) ? tk_.Y[row + (size_t)j * n] : 0.0;
+  for (int j = 0; j < CH_MAX; ++j) q[j] = (j < m) ? gy[row + (size_t)j * n] : 0.0;
 #pragma unroll
   for (int j = 0; j < CH_MAX; ++j) {
     if (j < m) {
