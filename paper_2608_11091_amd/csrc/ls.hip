@@ -16,6 +16,7 @@ namespace tk {
 namespace {
 
 constexpr int LS_NT = 256;
+constexpr int LS_KMAX = 64;  // columns per cycle (iterations per restart cycle)
 
 __global__ __launch_bounds__(LS_NT) void ls_init_kernel(LsState S, int s) {
   const int i = threadIdx.x;
@@ -34,12 +35,31 @@ __global__ __launch_bounds__(LS_NT) void ls_add_kernel(LsState S, int s, int kma
   const int i = threadIdx.x;
   const int lane = i & 63, w = i >> 6;
   double x = i < s ? S.Mcol[i + (size_t)k * s] : 0.0;
+  // this row of the k previous reflectors, staged in LDS with sixteen loads
+  // in flight at a time (a load inside the barrier-separated loop below
+  // would cost a full load latency per reflector); a row outside the sketch
+  // reads row s - 1 and never uses it
+  __shared__ double hvs[LS_KMAX * LS_NT];  // reflector j, row i at [j * LS_NT + i]
+  __shared__ double taus[LS_KMAX];
+  if (i < k) taus[i] = S.tau[i];  // read by all after block_sum's barriers
+  {
+    const size_t ic = (size_t)min(i, s - 1);
+    for (int jb = 0; jb < k; jb += 16) {
+      double t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (jb + u < k) t[u] = S.Hv[ic + (size_t)(jb + u) * s];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (jb + u < k) hvs[(jb + u) * LS_NT + i] = t[u];
+    }
+  }
   const double cn = block_sum(x * x, red);
-  // previous reflectors
+  // previous reflectors (each thread reads back only its own row)
   for (int j = 0; j < k; ++j) {
-    const double v = (i == j) ? 1.0 : (i > j && i < s ? S.Hv[i + (size_t)j * s] : 0.0);
+    const double v = (i == j) ? 1.0 : (i > j && i < s ? hvs[j * LS_NT + i] : 0.0);
     const double wsum = block_sum(v * x, red);
-    x -= S.tau[j] * v * wsum;
+    x -= taus[j] * v * wsum;
   }
   // new reflector on x[k:]
   double va = (i == k) ? x : 0.0;
@@ -78,14 +98,23 @@ __global__ __launch_bounds__(LS_NT) void ls_add_kernel(LsState S, int s, int kma
   if (i < s) S.qtb[i] = q;
   const double tail2 = block_sum(i > k ? q * q : 0.0, red);
   __syncthreads();
-  // back substitution on wave 0: lane r holds b_r
+  // back substitution on wave 0: lane r holds b_r and row r of R (columns
+  // below k loaded up front, column k is this thread's new entry)
   if (w == 0) {
-    double b = (lane <= k) ? S.qtb[lane] : 0.0;
-    for (int r = k; r >= 0; --r) {
-      const double rr = S.R[r + (size_t)r * kmax];
+    const double rk = (i < k) ? x : (i == k ? beta : 0.0);
+    double rrow[LS_KMAX];
+#pragma unroll
+    for (int r = 0; r < LS_KMAX; ++r)
+      if (r < k) rrow[r] = S.R[lane + (size_t)r * kmax];
+    double b = (lane <= k) ? q : 0.0;
+#pragma unroll
+    for (int r = LS_KMAX - 1; r >= 0; --r) {
+      if (r > k) continue;
+      const double rl = (r == k) ? rk : rrow[r];
+      const double rr = __shfl(rl, r, 64);
       const double yr = __shfl(b, r, 64) / rr;
       if (lane == r) b = yr;
-      else if (lane < r) b -= S.R[lane + (size_t)r * kmax] * yr;
+      else if (lane < r) b -= rl * yr;
     }
     if (lane <= k) {
       S.y[lane] = b;
