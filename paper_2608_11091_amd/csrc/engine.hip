@@ -530,10 +530,9 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
   q.steps.push_back([=](hipStream_t st) {
     if (own_eps) TK_HIP(hipMemcpyAsync(const_cast<double*>(epsd), hp->ev, sizeof(hp->ev), hipMemcpyHostToDevice, st));
     if (any_force) TK_HIP(hipMemcpyAsync(force_dev, hp->force, sizeof(hp->force), hipMemcpyHostToDevice, st));
-    gather_coef(bl->at<const double*>(off_cptr), bl->at<double>(off_cscale), nbA(), coef, st);
     dot_batched<T>(bl->at<const T*>(off_cores), bl->at<const T*>(off_cores), corelen, nbA(), 1.0, sumsq, st);
-    block_weights(coef, sumsq, nbA(), w, st);
-    zero_threshold(w, nbA(), zero_tol, zthr, st);
+    coef_weights_threshold(bl->at<const double*>(off_cptr), bl->at<double>(off_cscale), sumsq, nbA(), zero_tol, coef,
+                           w, zthr, st);
   });
 
   // --- 1. effective-rank heuristic (Gram eigenvalues) -> sketch width.  With
@@ -823,19 +822,14 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
         q.steps.push_back(
             [=](hipStream_t st) { chol_batched(bl->at<CholTask>(cpo), nt, sc, mq, sh_p, drel, dabs, st); });
         std::vector<TrsmTask> tt;
-        for (size_t i = 0; i < modes.size(); ++i)
+        for (size_t i = 0; i < modes.size(); ++i) {
           tt.push_back(TrsmTask{src[i], Rq + size_t(modes[i]) * sc * sc, dst[i]});
+          // the last pass also writes the FP32 basis of the FP32 form
+          if constexpr (!std::is_same<T, double>::value)
+            if (pass == 2) tt.back().Qf = Uh[modes[i]];
+        }
         const size_t toff = blob.add(tt);
         q.steps.push_back([=](hipStream_t st) { trsm_rows(bl->at<TrsmTask>(toff), nt, n, sc, mq, st); });
-      }
-      if constexpr (!std::is_same<T, double>::value) {
-        CastSet<double, T> cs;
-        for (int k : modes) {
-          cs.x[cs.count] = Q64[k];
-          cs.y[cs.count] = Uh[k];
-          cs.len[cs.count++] = size_t(n) * sc;
-        }
-        q.steps.push_back([=](hipStream_t st) { cast_multi<double, T>(cs, st); });
       }
     }
   }
@@ -910,13 +904,12 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       rank_certificate<T>(Hc, w, fro, nbA(), epsd + 1, cpar, cert_dev, rt_, st);
     });
     for (auto& f : eig_steps) q.steps.push_back(f);
-    emit_width();
     WidthZero<T> wz{};
     for (int k = 0; k < d; ++k) {
       wz.U[k] = Uh[k];
       wz.n[k] = sh.n[k];
     }
-    q.steps.push_back([=](hipStream_t st) { zero_beyond_width<T>(wz, d, sc, s_dev, st); });
+    q.steps.push_back([=](hipStream_t st) { width_and_zero<T>(wz, d, sc, rt_, p_, cap_, fs_, s_dev, st); });
   }
   // --- 4. core projection C^ = sum_b c_b G_b x_k (U^_k^T U_bk)
   T* Cb[2] = {ar.alloc<T>(sclen), ar.alloc<T>(sclen)};
@@ -933,14 +926,14 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     // column i only meets core index i of its mode, so zeroing both after
     // the fact gives the same core as projecting onto the zeroed basis.
     q.steps.push_back(join);
-    emit_width();
     WidthZero<T> wz{};
     for (int k = 0; k < d; ++k) {
       wz.U[k] = Uh[k];
       wz.n[k] = sh.n[k];
     }
     wz.core = Cb[0];
-    q.steps.push_back([=](hipStream_t st) { zero_beyond_width<T>(wz, d, sc, s_dev, st); });
+    int* rt_ = rt;
+    q.steps.push_back([=](hipStream_t st) { width_and_zero<T>(wz, d, sc, rt_, p_, cap_, fs_, s_dev, st); });
   }
   // --- 5. ST-HOSVD of C^, modes 1..d in order.  Per mode the truncation is
   //        decided by a Jacobi eigen-solve of the Gram of the ROTATED unfolding
@@ -1061,8 +1054,7 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     std::array<T*, kMaxD> U = {out.U[0], out.U[1], out.U[2], out.U[3]};
     int* rk = out.rank;
     q.steps.push_back([=](hipStream_t st) {
-      core_recap<T>(src, sd, nullptr, dst, dd, d, st);
-      zero_sum_fixup<T>(total, zthr, d, nn, rc, U.data(), dst, corelen, rk, st);
+      core_recap_fixup<T>(src, sd, dst, dd, d, total, zthr, nn, rc, U.data(), rk, st);
     });
   }
   RoundSumOut<T> o;

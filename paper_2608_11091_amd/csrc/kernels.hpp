@@ -89,6 +89,11 @@ struct WidthZero {
 };
 template <typename T>
 void zero_beyond_width(const WidthZero<T>& a, int d, int sc, const int* s_dev, hipStream_t st);
+// The same zeroing with the width computed in the kernel from the kept ranks,
+// as sketch_width does it, and written to *s_out.
+template <typename T>
+void width_and_zero(const WidthZero<T>& a, int d, int sc, const int* rt, int p, int cap, int force, int* s_out,
+                    hipStream_t st);
 // Side stream of the current device (created on first use: non-blocking,
 // default priority) for work that a plan runs beside the caller's stream.
 hipStream_t side_stream();
@@ -148,6 +153,7 @@ struct TrsmTask {
   const double* Y;
   const double* R;
   double* Q;
+  float* Qf = nullptr;  // optional FP32 copy of Q (same layout), rounded to nearest
 };
 void trsm_rows(const TrsmTask* tasks_d, int ntasks, int n, int cap, const int* m_dev, hipStream_t st);
 
@@ -238,6 +244,14 @@ void zero_sum_fixup(const double* total, const double* zthr, int d, const int* n
                     size_t core_len, int* rank, hipStream_t st);
 // zthr = (tol * sum_{b < nb} w[b])^2.
 void zero_threshold(const double* w, int nb, double tol, double* zthr, hipStream_t st);
+// gather_coef, block_weights and zero_threshold in one launch (one
+// workgroup): coef[b], w[b] = |coef[b]| sqrt(sumsq[b]) and zthr.
+void coef_weights_threshold(const double* const* cptr, const double* cscale, const double* sumsq, int nb, double tol,
+                            double* coef, double* w, double* zthr, hipStream_t st);
+// core_recap (no view limit) followed by zero_sum_fixup, in one launch.
+template <typename T>
+void core_recap_fixup(const T* src, const int* sd, T* dst, const int* dd, int d, const double* total,
+                      const double* zthr, const int* n, int rc, T* const* U, int* rank, hipStream_t st);
 // Y[:, :] += X[:, :] (rows x cols, col-major with their own leading dims).
 template <typename T>
 void mat_axpy(const T* X, int ldx, T* Y, int ldy, int rows, int cols, hipStream_t st);

@@ -509,7 +509,11 @@ __global__ __launch_bounds__(TR_NT) void trsm_rows_kernel(const TrsmTask* __rest
   }
 #pragma unroll
   for (int j = 0; j < CH_MAX; ++j)
-    if (j < cap) tk_.Q[row + (size_t)j * n] = (j < m) ? q[j] : 0.0;
+    if (j < cap) {
+      const double qv = (j < m) ? q[j] : 0.0;
+      tk_.Q[row + (size_t)j * n] = qv;
+      if (tk_.Qf) tk_.Qf[row + (size_t)j * n] = float(qv);
+    }
 }
 
 }  // namespace

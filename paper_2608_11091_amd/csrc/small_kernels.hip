@@ -25,6 +25,22 @@ __global__ void zero_threshold_kernel(const double* w, int nb, double tol, doubl
   *zthr = s * s;
 }
 
+__global__ __launch_bounds__(256) void coef_weights_threshold_kernel(const double* const* cptr, const double* cscale,
+                                                                     const double* sumsq, int nb, double tol,
+                                                                     double* coef, double* w, double* zthr) {
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const double c = cscale[b] * (cptr[b] ? *cptr[b] : 1.0);
+    coef[b] = c;
+    w[b] = fabs(c) * sqrt(sumsq[b]);
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += w[b];
+  s *= tol;
+  *zthr = s * s;
+}
+
 template <typename T>
 __global__ void zero_sum_fixup_kernel(const double* total, const double* zthr, int d, int n0, int n1, int n2, int n3, int rc, T* U0, T* U1,
                                       T* U2, T* U3, T* core, size_t core_len, int* rank) {
@@ -69,9 +85,32 @@ __global__ void zero_cols_from_kernel(T* A, int ld, int rows, int cols, const in
   if (c >= from) A[r + size_t(c) * ld] = T(0);
 }
 
+// The sketch width s = min(max_k (rt_k + p), cap + p), or force when force >= 0
+// (rt_k < 0: the mode's rule was skipped, counted as cap).
+__device__ inline int width_from_ranks(const int* rt, int d, int p, int cap, int force) {
+  if (force >= 0) return force;
+  int est = 0;
+  for (int k = 0; k < d; ++k) {
+    const int v = rt[k] < 0 ? cap + p : rt[k] + p;
+    est = v > est ? v : est;
+  }
+  return est < cap + p ? est : cap + p;
+}
+
+// Zeroes basis columns (part < d) and core indices (part == d) at or beyond
+// the width s; s comes from *s_dev, or from the ranks rt when rt is given (and
+// is then written to *s_out by one thread).
 template <typename T>
-__global__ void zero_beyond_width_kernel(WidthZero<T> a, int d, int sc, const int* s_dev) {
-  const int s = max(*s_dev, 0);
+__global__ void zero_beyond_width_kernel(WidthZero<T> a, int d, int sc, const int* s_dev, const int* rt, int p,
+                                         int cap, int force, int* s_out) {
+  int s;
+  if (rt) {
+    s = width_from_ranks(rt, d, p, cap, force);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *s_out = s;
+  } else {
+    s = *s_dev;
+  }
+  s = max(s, 0);
   const int part = blockIdx.y;
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   const size_t e0 = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -266,9 +305,31 @@ void zero_beyond_width(const WidthZero<T>& a, int d, int sc, const int* s_dev, h
   for (int k = 0; k < d; ++k) mx = std::max(mx, size_t(a.n[k]) * sc);
   const unsigned gx = unsigned(std::min<size_t>((mx + 255) / 256, 1024));
   const unsigned parts = a.core ? d + 1 : d;
-  hipLaunchKernelGGL((zero_beyond_width_kernel<T>), dim3(gx, parts), dim3(256), 0, st, a, d, sc, s_dev);
+  hipLaunchKernelGGL((zero_beyond_width_kernel<T>), dim3(gx, parts), dim3(256), 0, st, a, d, sc, s_dev, nullptr, 0,
+                     0, 0, nullptr);
   TK_LAUNCH_CHECK();
 }
+
+template <typename T>
+void width_and_zero(const WidthZero<T>& a, int d, int sc, const int* rt, int p, int cap, int force, int* s_out,
+                    hipStream_t st) {
+  size_t mx = 1;
+  for (int k = 0; k < d; ++k) mx *= size_t(sc);
+  for (int k = 0; k < d; ++k) mx = std::max(mx, size_t(a.n[k]) * sc);
+  const unsigned gx = unsigned(std::min<size_t>((mx + 255) / 256, 1024));
+  const unsigned parts = a.core ? d + 1 : d;
+  hipLaunchKernelGGL((zero_beyond_width_kernel<T>), dim3(gx, parts), dim3(256), 0, st, a, d, sc, nullptr, rt, p, cap,
+                     force, s_out);
+  TK_LAUNCH_CHECK();
+}
+
+void coef_weights_threshold(const double* const* cptr, const double* cscale, const double* sumsq, int nb, double tol,
+                            double* coef, double* w, double* zthr, hipStream_t st) {
+  hipLaunchKernelGGL(coef_weights_threshold_kernel, dim3(1), dim3(256), 0, st, cptr, cscale, sumsq, nb, tol, coef, w,
+                     zthr);
+  TK_LAUNCH_CHECK();
+}
+
 
 hipStream_t side_stream() {
   static std::mutex mu;
@@ -439,6 +500,8 @@ template void zero_sum_fixup<float>(const double*, const double*, int, const int
 template void zero_cols_from<double>(double*, int, int, int, const int*, hipStream_t);
 template void zero_beyond_width<double>(const WidthZero<double>&, int, int, const int*, hipStream_t);
 template void zero_beyond_width<float>(const WidthZero<float>&, int, int, const int*, hipStream_t);
+template void width_and_zero<double>(const WidthZero<double>&, int, int, const int*, int, int, int, int*, hipStream_t);
+template void width_and_zero<float>(const WidthZero<float>&, int, int, const int*, int, int, int, int*, hipStream_t);
 template void zero_cols_from<float>(float*, int, int, int, const int*, hipStream_t);
 template void mat_axpy<double>(const double*, int, double*, int, int, int, hipStream_t);
 template void mat_axpy<float>(const float*, int, float*, int, int, int, hipStream_t);

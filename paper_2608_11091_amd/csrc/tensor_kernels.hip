@@ -235,6 +235,37 @@ __global__ void core_recap_kernel(const T* __restrict__ src, Dims4 sd, Dims4 sv,
   }
 }
 
+// core_recap_kernel without a view limit, and the zero-sum fix-up of the
+// same step: when *tot <= *zthr (or NaN) the core is zero, every factor is
+// e_1 in its first column and every rank is 1.
+template <typename T>
+__global__ void core_recap_fixup_kernel(const T* __restrict__ src, Dims4 sd, T* __restrict__ dst, Dims4 dd, int d,
+                                        size_t total, const double* tot, const double* zthr, Dims4 nn, int rc,
+                                        T* U0, T* U1, T* U2, T* U3, int* rank) {
+  const bool zs = !(*tot > *zthr);
+  const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t nth = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = tid; e < total; e += nth) {
+    size_t rem = e, so = 0, sstr = 1;
+    bool inside = true;
+    for (int k = d - 1; k >= 0; --k) {
+      const int ik = int(rem % dd.v[k]);
+      rem /= dd.v[k];
+      if (ik >= sd.v[k]) inside = false;
+      so += size_t(ik) * sstr;
+      sstr *= sd.v[k];
+    }
+    dst[e] = (inside && !zs) ? src[so] : T(0);
+  }
+  if (!zs) return;
+  T* Us[4] = {U0, U1, U2, U3};
+  for (int k = 0; k < d; ++k) {
+    const size_t len = size_t(nn.v[k]) * rc;
+    for (size_t e = tid; e < len; e += nth) Us[k][e] = (e == 0) ? T(1) : T(0);
+  }
+  if (tid < size_t(d)) rank[tid] = 1;
+}
+
 template <typename T>
 __global__ void mat_recap_kernel(const T* __restrict__ src, int lds, int rs, int cs, T* __restrict__ dst, int ldd,
                                  int rd, int cd) {
@@ -389,6 +420,25 @@ void core_recap(const T* src, const int* sd, const int* sv, T* dst, const int* d
 }
 
 template <typename T>
+void core_recap_fixup(const T* src, const int* sd, T* dst, const int* dd, int d, const double* total,
+                      const double* zthr, const int* n, int rc, T* const* U, int* rank, hipStream_t st) {
+  Dims4 a{}, b{}, nn{};
+  T* uu[4] = {nullptr, nullptr, nullptr, nullptr};
+  size_t len = 1, mx = 1;
+  for (int k = 0; k < d; ++k) {
+    a.v[k] = sd[k];
+    b.v[k] = dd[k];
+    nn.v[k] = n[k];
+    uu[k] = U[k];
+    len *= size_t(dd[k]);
+    mx = std::max(mx, size_t(n[k]) * rc);
+  }
+  hipLaunchKernelGGL((core_recap_fixup_kernel<T>), dim3(grid_for(std::max(len, mx))), dim3(256), 0, st, src, a, dst,
+                     b, d, len, total, zthr, nn, rc, uu[0], uu[1], uu[2], uu[3], rank);
+  TK_LAUNCH_CHECK();
+}
+
+template <typename T>
 void mat_recap(const T* src, int ld_src, int rows_src, int cols_src, T* dst, int ld_dst, int rows_dst, int cols_dst,
                hipStream_t st) {
   const size_t total = size_t(rows_dst) * cols_dst;
@@ -426,6 +476,8 @@ void sketch_width(const int* rt, int d, int p, int cap, int force, int* s_out, h
   template void fill<T>(T*, size_t, T, hipStream_t);                                                       \
   template void core_recap<T>(const T*, const int*, const int*, T*, const int*, int, hipStream_t);         \
   template void mat_recap<T>(const T*, int, int, int, T*, int, int, int, hipStream_t);                     \
+  template void core_recap_fixup<T>(const T*, const int*, T*, const int*, int, const double*, const double*,    \
+                                    const int*, int, T* const*, int*, hipStream_t);                     \
   template void gram_compact<T>(const T*, int, const int* const*, int, int, int, const int*, T*, int, size_t, \
                                 size_t, hipStream_t);
 TK_INST(double)
