@@ -1010,18 +1010,19 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
       q.steps.push_back([=](hipStream_t st) { jacobi_eig<T>(bl->at<EigTask<T>>(off), 1, sc, true, st, in_splits); });
     }
     emit_ttm<T>(q, pl, d, dims, k, sc, {Bt}, {V2[k]}, sc, true, {Cb[1 - cb]});
-    {
-      GemmDesc<T> g;
-      g.M = sc;
-      g.N = sc;
-      g.K = sc;
-      g.lda = sc;
-      g.ldb = sc;
-      g.ldc = sc;
-      g.group1(U12[k], V1[k], V2[k]);
-      emit_gemm(q, pl, std::move(g));
-    }
     cb = 1 - cb;
+  }
+  {
+    // U12_k = V1_k V2_k for every mode, one grouped launch off the chain
+    GemmDesc<T> g;
+    g.M = sc;
+    g.N = sc;
+    g.K = sc;
+    g.lda = sc;
+    g.ldb = sc;
+    g.ldc = sc;
+    for (int k = 0; k < d; ++k) g.group1(U12[k], V1[k], V2[k]);
+    emit_gemm(q, pl, std::move(g));
   }
   // factors U_k = U^_k U12_k[:, :min(rc, sc)]
   for (auto& modes : modes_by_n<T>(sh)) {
