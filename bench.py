@@ -65,7 +65,7 @@ NOTE = {
 TRAFFIC = {
     "jacobi": dict(bytes_per_launch=549478.0,
                    sources={"paper_2608_11091_amd/csrc/eig.hip":
-                            "321ddb892cfa9f186fdf2408f937df2b27c5f22e96ea7ce8af2808593891950f",
+                            "4600f36df1cc73005ab3c5b3b61530ecb54311ca164772f84ab158eabceaf0fd",
                             "paper_2608_11091_amd/csrc/common.hpp":
                             "a72a951f0c6374c30ec565058a937f7bb8014779678f6d341fc5b73470946bd8"},
                    profile="profiles/jacobi_blk_traffic_deblur3d_n512.md"),

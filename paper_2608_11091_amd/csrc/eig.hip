@@ -344,7 +344,10 @@ __global__ __launch_bounds__(TRG_NT) void tridiag_reg_kernel(const EigTask<T>* _
     for (int i = 0; i < TRG_RR; ++i)
 #pragma unroll
       for (int k = 0; k < TRG_RC; ++k) a[i][k] -= vr[i] * wc[k] + wr[i] * vc[k];
-    __syncthreads();
+    // no barrier here: the next step's Householder vector comes from its
+    // wave's own registers and goes to the other buffer, and every shared
+    // array this step reads is written again only after the next step's
+    // first barrier (pp, qs) or two steps on (vb, wb, tau_s by parity)
   }
   // last 2 x 2 block: diagonal entries and the coupling, from their holders
 #pragma unroll
