@@ -148,6 +148,30 @@ __device__ void tridiag_spectrum(const EigTask<T>& tk_, T* dd, T* ee, T* lam, T*
   const T bnorm = fmax(fabs(gl), fabs(gu));
   const T pivmin = fmax(Lim<T>::tiny(), emax2 * Lim<T>::tiny() * T(1e10));
   const T tolx = T(2) * Lim<T>::eps() * bnorm;
+  // Rank rule with a cap (kind 1, cap1 > 0): only min(r~, cap1) is needed,
+  // and one Sturm count settles the common case.  If at least cap1
+  // eigenvalues lie at or above x = max(tau^2 tot, delta (gu + tolx)) + 2 tolx,
+  // with tot = trace + N (max(0, -gl) + tolx) bounding the rule's total (the
+  // positive eigenvalues, as the multisection would compute them), then the
+  // cap1-th largest counts as nonzero and alone exceeds tau^2 total, so the
+  // tail from it on does too and r~ >= cap1.
+  if (tk_.rule.kind == 1 && tk_.rule.cap1 > 0 && tk_.rule.cap1 <= N) {
+    if (tid == 0) {
+      double tr = 0.0;
+      for (int k = 0; k < N; ++k) tr += double(dd[k]);
+      const double tau = *tk_.rule.tau;
+      const double tx = double(tolx);
+      const double tot = tr + double(N) * (fmax(0.0, -double(gl)) + tx);
+      const double x = fmax(tau * tau * tot, tk_.rule.delta * (double(gu) + tx)) + 2.0 * tx;
+      const int below = sturm_count<T>(dd, ee, N, T(x), pivmin);
+      sc[0] = (N - below >= tk_.rule.cap1) ? T(1) : T(0);
+    }
+    __syncthreads();
+    if (sc[0] != T(0)) {
+      if (tid == 0) *tk_.rule.rank_out = tk_.rule.cap1;
+      return;  // uniform: every thread read the same flag after the barrier
+    }
+  }
   // G = lanes per eigenvalue: the largest power of two <= min(16, nthreads / N)
   int G = 1;
   while (G < 16 && 2 * G * N <= nthreads) G *= 2;

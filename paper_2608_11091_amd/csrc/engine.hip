@@ -624,6 +624,7 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
         e.rule.tau = epsd + 1;
         e.rule.delta = cfg.delta;
         e.rule.rank_out = rt + k;
+        e.rule.cap1 = sh.cap;  // the width only takes min(r~ + p, cap + p); lam is scratch
         return e;
       };
       if (n <= kEigRegMax) {

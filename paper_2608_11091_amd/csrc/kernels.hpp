@@ -172,6 +172,8 @@ struct EigRule {
   const double* zthr;  // kind 2: total <= *zthr means a numerically zero sum (rank 1)
   const int* force;    // kind 2: forced rank (nullptr / negative = none)
   int* rank_out;       // resulting rank
+  int cap1 = 0;        // kind 1: > 0 when only min(rank, cap1) is needed (and not the
+                       // eigenvalues): rank_out may then be cap1 for any rank >= cap1
 };
 template <typename T>
 struct EigTask {
