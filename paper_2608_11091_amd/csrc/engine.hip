@@ -268,14 +268,16 @@ struct ForkJoin {
   ForkJoin& operator=(const ForkJoin&) = delete;
 };
 
-// Moves steps [from, end) of q onto the side stream between a fork and the
+}  // namespace
+
+// Moves steps [from, end) of q onto side stream `which` between a fork and the
 // join record; the returned step makes the caller's stream wait for them.
-std::function<void(hipStream_t)> fork_steps(Seq& q, size_t from) {
+std::function<void(hipStream_t)> fork_steps(Seq& q, size_t from, int which) {
   auto fj = std::make_shared<ForkJoin>();
   std::vector<std::function<void(hipStream_t)>> sec(q.steps.begin() + from, q.steps.end());
   q.steps.resize(from);
-  q.steps.push_back([fj, sec](hipStream_t st) {
-    hipStream_t side = side_stream();
+  q.steps.push_back([fj, sec, which](hipStream_t st) {
+    hipStream_t side = side_stream(which);
     TK_HIP(hipEventRecord(fj->fork, st));
     TK_HIP(hipStreamWaitEvent(side, fj->fork, 0));
     for (auto& f : sec) f(side);
@@ -283,8 +285,6 @@ std::function<void(hipStream_t)> fork_steps(Seq& q, size_t from) {
   });
   return [fj](hipStream_t st) { TK_HIP(hipStreamWaitEvent(st, fj->join, 0)); };
 }
-
-}  // namespace
 
 // Khatri-Rao range sketch of a block sum (Sec. 3.1; also the factor sketches
 // of the multilinear Nystrom method): for every mode k,
@@ -722,7 +722,7 @@ RoundSumOut<T> plan_roundsum(Seq& q, Planner& pl, const Shape& sh, const Blocks<
     q.steps.push_back([=](hipStream_t st) { sketch_width(rt, d, p_, cap_, fs_, s_dev, st); });
   };
   if (overlap)
-    join = fork_steps(q, rule_from);
+    join = fork_steps(q, rule_from, 0);
   else
     emit_width();
 

@@ -41,6 +41,10 @@ struct Seq {
     for (auto& f : steps) f(st);
   }
 };
+// Moves steps [from, end) of q onto side stream `which` (after everything
+// issued before them on the caller's stream); the returned step, pushed
+// later, makes the caller's stream wait for them.
+std::function<void(hipStream_t)> fork_steps(Seq& q, size_t from, int which);
 
 struct Shape {
   int d = 3;

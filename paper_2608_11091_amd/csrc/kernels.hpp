@@ -94,9 +94,10 @@ void zero_beyond_width(const WidthZero<T>& a, int d, int sc, const int* s_dev, h
 template <typename T>
 void width_and_zero(const WidthZero<T>& a, int d, int sc, const int* rt, int p, int cap, int force, int* s_out,
                     hipStream_t st);
-// Side stream of the current device (created on first use: non-blocking,
-// default priority) for work that a plan runs beside the caller's stream.
-hipStream_t side_stream();
+// Side streams of the current device (created on first use: non-blocking,
+// default priority) for work that a plan runs beside the caller's stream;
+// `which` selects one of several independent ones.
+hipStream_t side_stream(int which = 0);
 // Copy the leading rows x cols of a column-major matrix (zero-filling dst beyond src).
 template <typename T>
 void mat_recap(const T* src, int ld_src, int rows_src, int cols_src, T* dst, int ld_dst, int rows_dst,

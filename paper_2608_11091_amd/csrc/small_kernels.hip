@@ -331,17 +331,18 @@ void coef_weights_threshold(const double* const* cptr, const double* cscale, con
 }
 
 
-hipStream_t side_stream() {
+hipStream_t side_stream(int which) {
   static std::mutex mu;
-  static std::map<int, hipStream_t> streams;
+  static std::map<std::pair<int, int>, hipStream_t> streams;
   int dev = 0;
   TK_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(mu);
-  auto it = streams.find(dev);
+  const auto key = std::make_pair(dev, which);
+  auto it = streams.find(key);
   if (it != streams.end()) return it->second;
   hipStream_t s = nullptr;
   TK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-  streams[dev] = s;
+  streams[key] = s;
   return s;
 }
 

@@ -190,7 +190,26 @@ struct Cycle {
       plan_roundsum<T>(q, pl, sh, LV, rcfg, omega_, W, nullptr);
       Blocks<T> wb;
       wb.add(W, nullptr, 1.0);
-      if (!full) plan_sketch<T>(q, pl, sh, wb, S, s, Mcols + size_t(k) * s);
+      const int ss = lr, mx = maxiter;
+      LsState lsv = ls;
+      const double* ctol = &conv_tol;
+      const double bdt = bd_tol;
+      const bool tik = tikhonov, fa = full;
+      // The sketch of W and the least-squares column (a3, a7) need only W:
+      // they run on a second side stream beside the inner products and the
+      // orthogonalisation RoundSum, and join before the status record.
+      std::function<void(hipStream_t)> ls_join;
+      if (!full) {
+        const size_t from = q.steps.size();
+        plan_sketch<T>(q, pl, sh, wb, S, s, Mcols + size_t(k) * s);
+        q.steps.push_back([=](hipStream_t st) {
+          ls_add_column(lsv, ss, mx, k, *ctol, bdt, st);
+          // regularised y_k and residual (Sec. 4.3); the breakdown test keeps
+          // the unregularised R factor
+          if (tik) ls_tikhonov(lsv, ss, mx, k, *ctol, -1.0, st);
+        });
+        ls_join = fork_steps(q, from, 1);
+      }
       const int j0 = std::max(0, k - kt + 1);
       std::vector<TT<T>> win(V.begin() + j0, V.begin() + k + 1);
       double* hk = h + size_t(k) * kt;
@@ -199,6 +218,7 @@ struct Cycle {
       ob.add(W, nullptr, 1.0);
       for (size_t j = 0; j < win.size(); ++j) ob.add(win[j], hk + j, -1.0);
       plan_roundsum<T>(q, pl, sh, ob, rcfg, omega_, V[k + 1], nullptr);
+      if (ls_join) q.steps.push_back(ls_join);
       std::vector<const T*> pc = {W.core, V[k + 1].core};
       const size_t off = pl.blob.add(pc);
       const size_t cl = sh.core_len();
@@ -207,22 +227,17 @@ struct Cycle {
       const double* resk = res + k;
       const int* rk = V[k + 1].rank;
       T* vc = V[k + 1].core;
-      const int ss = lr, mx = maxiter;
-      LsState lsv = ls;
-      const double* ctol = &conv_tol;
-      const double bdt = bd_tol;
       IterStatus* sd = st_dev;
       int* fl = flags;
-      const bool tik = tikhonov, fa = full;
       double* hcol = Mcols + size_t(k) * lr;
       q.steps.push_back([=](hipStream_t st) {
         dot_batched<T>(bl->at<const T*>(off), bl->at<const T*>(off), cl, 2, 1.0, s2, st);
-        // Alg. 1: Hessenberg column (h_{1..k}, ||W||) in place of the sketch
-        if (fa) hess_column(hk, k + 1, s2 + 1, hcol, ss, st);
-        ls_add_column(lsv, ss, mx, k, *ctol, bdt, st);
-        // regularised y_k and residual (Sec. 4.3); the breakdown test keeps
-        // the unregularised R factor
-        if (tik) ls_tikhonov(lsv, ss, mx, k, *ctol, -1.0, st);
+        if (fa) {
+          // Alg. 1: Hessenberg column (h_{1..k}, ||W||) in place of the sketch
+          hess_column(hk, k + 1, s2 + 1, hcol, ss, st);
+          ls_add_column(lsv, ss, mx, k, *ctol, bdt, st);
+          if (tik) ls_tikhonov(lsv, ss, mx, k, *ctol, -1.0, st);
+        }
         iter_status(s2, fl, resk, rk, d, bdt, om, sd, st);
         scale_copy<T>(vc, vc, cl, 1.0, nullptr, om, st);
       });
